@@ -1,0 +1,75 @@
+"""The seeded input generator: determinism, prefix stability and the stated
+distributions of the synthetic workloads."""
+import math
+
+import numpy as np
+
+from paper_2309_03717_amd import workloads as W
+
+
+def test_deterministic_and_prefix_stable():
+    a = W.draw_tracks(W.SEED_BASE, 70_000, W.RECIPE_SMALL)
+    b = W.draw_tracks(W.SEED_BASE, 70_000, W.RECIPE_SMALL)
+    for f in W.TRACK_FIELDS:
+        np.testing.assert_array_equal(getattr(a, f), getattr(b, f))
+    head = W.draw_tracks(W.SEED_BASE, 1000, W.RECIPE_SMALL)
+    mid = W.draw_tracks(W.SEED_BASE, 5000, W.RECIPE_SMALL, start=65_000)
+    for f in W.TRACK_FIELDS:
+        np.testing.assert_array_equal(getattr(head, f), getattr(a, f)[:1000])
+        np.testing.assert_array_equal(getattr(mid, f), getattr(a, f)[65_000:70_000])
+
+
+def test_track_distribution():
+    r = W.RECIPE_SMALL
+    t = W.draw_tracks(W.SEED_BASE, 200_000, r)
+    assert set(np.unique(t.qw)) == {-1.0, 1.0}
+    assert abs(np.mean(t.qw > 0) - 0.5) < 0.01
+    assert t.z0.min() >= r.z_lo and t.z0.max() <= r.z_hi
+    assert abs(np.std(t.x0) - r.sigma) < 0.01 * r.sigma
+    length = np.sqrt((t.x1 - t.x0) ** 2 + (t.y1 - t.y0) ** 2 + (t.z1 - t.z0) ** 2)
+    assert length.min() >= r.len_lo - 1e-9 and length.max() <= r.len_hi + 1e-9
+    beta = np.sqrt(t.bx ** 2 + t.by ** 2 + t.bz ** 2)
+    assert beta.min() >= r.beta_lo - 1e-12 and beta.max() <= r.beta_hi + 1e-12
+    cos_down = -t.bz / beta
+    assert cos_down.min() >= math.cos(math.radians(r.cap_deg)) - 1e-12
+    # times: start on the axis front, end after length / (beta c)
+    np.testing.assert_allclose(t.t0, (W.Z_AXIS - t.z0) / W.C_LIGHT, rtol=1e-15)
+    np.testing.assert_allclose(t.t1 - t.t0, length / (beta * W.C_LIGHT), rtol=1e-9)
+
+
+def test_configs_shapes():
+    c0, c1, c2, c3 = (W.config(k) for k in range(4))
+    assert (c0.n_tracks, c0.array.m, c0.array.n_bins, c0.array.dt) == (10_000, 16, 4096, 0.2e-9)
+    assert (c1.n_tracks, c1.array.m, c1.array.dt) == (10_000_000, 160, 0.1e-9)
+    assert (c2.n_tracks, c2.array.m, c2.chunk) == (100_000_000, 4096, 1 << 22)
+    assert (c3.n_tracks, c3.array.m) == (1_000_000, 64)
+    r = np.hypot(c1.array.x, c1.array.y)
+    assert r.min() == 25.0 and abs(r.max() - 500.0) < 1e-9
+    assert abs(np.ptp(c2.array.x) - 63 * 50.0) < 1e-9
+    assert c0.medium.kind == "uniform" and c1.medium.kind == "exponential"
+
+
+def test_mixed_inputs_are_float32_roundings():
+    t = W.config(2).tracks(1000)
+    m = t.to_mixed()
+    assert m.bx.dtype == np.float32 and m.qw.dtype == np.float32 and m.x0.dtype == np.float64
+    np.testing.assert_array_equal(m.widened().bx, t.bx.astype(np.float32).astype(np.float64))
+
+
+def test_window_start_precedes_reference_arrival():
+    c0 = W.config(0)
+    # uniform medium: plane front from 10 km at c / n, window opens 200 ns earlier
+    expect = (1.0 + W.N0_AIR) * W.Z_AXIS / W.C_LIGHT - 200e-9
+    np.testing.assert_allclose(c0.array.t_start, expect, rtol=1e-12)
+
+
+def test_batched_showers_recipe():
+    sh = W.batched_showers(64)
+    assert len(sh) == 64
+    for s in sh:
+        assert 10_000 <= s.n_tracks <= 1_000_000
+        assert 16 <= s.array.m <= 512
+        assert s.array.n_bins % 256 == 0 and 2048 <= s.array.n_bins <= 8192
+        assert 0.1e-9 <= s.array.dt <= 0.5e-9
+    assert {s.formalism for s in sh} == {"endpoint", "zhs"}
+    assert {s.medium.kind for s in sh} == {"uniform", "exponential"}
