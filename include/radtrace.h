@@ -1,0 +1,180 @@
+/*
+ * radtrace.h -- C ABI of the MI355X (gfx950) track x antenna radio-emission
+ * library.
+ *
+ * The computation (paper §2, "Overview of the radio module", Fig. 1): every
+ * particle track is looped over every antenna of the array; for each pair a
+ * straight-line propagator gives the distance R, the effective refractive
+ * index n_eff of the path and the arrival time, and the formalism's field is
+ * stored in the antenna's time trace. The two formalisms are the Endpoint and
+ * the ZHS formalism (§1); Listing 2 (§4) builds a propagator from an
+ * environment and a radio process from a detector and a propagator, which
+ * is what rt_plan_create does here.
+ *
+ * Conventions for every entry point:
+ *  - Units are SI: metres, seconds; velocities in units of c.
+ *  - Array arguments documented as "device" are device pointers of the
+ *    current HIP device (for example torch CUDA tensors' data_ptr()); they are
+ *    owned by the caller and must stay valid until the work enqueued on
+ *    `stream` has completed. "host" pointers are read before the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the null stream). All
+ *    device work of a call is enqueued on it; no call synchronizes the stream
+ *    or allocates device memory, so calls may be captured into a HIP graph.
+ *  - Every function returns an rt_status. On failure nothing is enqueued and
+ *    rt_last_error() holds a description (per host thread).
+ *    Invalid arguments give RT_E_INVALID; shapes the kernels do not support
+ *    give RT_E_UNSUPPORTED; a HIP error at launch gives RT_E_HIP; a too-small
+ *    workspace gives RT_E_WORKSPACE; no usable device gives RT_E_NO_DEVICE.
+ *    Asynchronous faults surface at the caller's next synchronization.
+ *  - A plan is used by one host thread at a time; different plans are
+ *    independent.
+ *
+ * Trace layout: traces[a][k][c] for antenna a, bin k, component c (x, y, z),
+ * row-major, element type double (RT_FP64) or float (RT_MIXED). Bin k of
+ * antenna a covers arrival times [t_start[a] + k dt, t_start[a] + (k+1) dt);
+ * a time exactly on an edge belongs to the bin above it, and times outside
+ * [0, n_bins) bins are dropped (ZHS boxes are clipped to the window).
+ */
+#ifndef RADTRACE_H
+#define RADTRACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RT_ABI_VERSION 1
+
+typedef enum {
+  RT_OK = 0,
+  RT_E_INVALID = 1,
+  RT_E_UNSUPPORTED = 2,
+  RT_E_NO_DEVICE = 3,
+  RT_E_HIP = 4,
+  RT_E_WORKSPACE = 5
+} rt_status;
+
+/* The two formalisms named in §1. */
+typedef enum { RT_ENDPOINT = 0, RT_ZHS = 1 } rt_formalism;
+
+/* RT_FP64: all arithmetic and the traces in double precision.
+ * RT_MIXED: arrival time, distance and bin decision in double precision
+ * (the same bins as RT_FP64); amplitudes, accumulation and traces in float;
+ * tracks carry beta and qw as float. */
+typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
+
+/* Refractive-index model of the environment the propagator is built from
+ * (§2, Listing 2; "media with varying properties", §1):
+ *   RT_UNIFORM:     n(z) = 1 + n0_minus_1
+ *   RT_EXPONENTIAL: n(z) = 1 + n0_minus_1 * exp(-z / scale_height)
+ * The straight path from height zp to an antenna at height za sees the path
+ * mean n_eff = 1 + n0_minus_1 * scale_height * (exp(-za/h) - exp(-zp/h)) /
+ * (zp - za) (the local index at the midpoint height when |zp - za| < 1 mm). */
+typedef enum { RT_UNIFORM = 0, RT_EXPONENTIAL = 1 } rt_medium_kind;
+
+typedef struct {
+  int32_t kind;          /* rt_medium_kind */
+  double n0_minus_1;     /* refractivity at z = 0, >= 0 */
+  double scale_height;   /* metres, > 0 (exponential only) */
+} rt_medium;
+
+/* The antenna collection (§2, "detector" in Listing 2). Device arrays of
+ * n_antennas doubles. The plan keeps these pointers: they must outlive it. */
+typedef struct {
+  int64_t n_antennas;
+  const double *x, *y, *z;   /* device: antenna positions (m) */
+  const double *t_start;     /* device: time of the left edge of bin 0 (s) */
+  double dt;                 /* bin width (s), > 0 */
+  int32_t n_bins;            /* bins per trace, >= 1 */
+} rt_detector;
+
+/* Straight particle tracks, structure of arrays, n of each (device).
+ * Track i starts at (x0,y0,z0) at time t0 and ends at (x1,y1,z1) at t1 with
+ * constant velocity (bx,by,bz) (units of c); qw is its charge (units of e)
+ * times its statistical weight. bx..qw are double for RT_FP64 plans and float
+ * for RT_MIXED plans. Non-finite inputs produce no contribution. */
+typedef struct {
+  int64_t n;
+  const double *x0, *y0, *z0, *t0;
+  const double *x1, *y1, *z1, *t1;
+  const void *bx, *by, *bz, *qw;
+} rt_tracks;
+
+typedef struct rt_plan rt_plan;   /* opaque; host-side metadata only */
+
+/* Version of this ABI (RT_ABI_VERSION). */
+int rt_abi_version(void);
+
+/* Static description of a status code. */
+const char *rt_status_string(int status);
+
+/* Description of the last failure on this host thread ("" if none). */
+const char *rt_last_error(void);
+
+/* A radio process for one detector, medium, formalism and precision (the
+ * analogue of make_radio_process_CoREAS / _ZHS of Listing 2, with a HIP
+ * stream in place of a thread count). k is the field prefactor:
+ * e / (4 pi eps0 c) = 4.80320471518522e-18 V s for SI fields (1 for unit
+ * tests). The plan reads no device memory; it chooses a tiling from the
+ * device's compute-unit count and LDS size, which rt_plan_set_tiling can
+ * override.
+ * Output: *plan (host object, free with rt_plan_destroy). */
+int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
+                   int formalism, int precision, double k);
+
+/* Frees a plan (NULL is accepted). Does not touch device memory. */
+int rt_plan_destroy(rt_plan *plan);
+
+/* Overrides the launch shape; 0 keeps the automatic choice for a field.
+ *  antennas_per_block: antennas whose traces one workgroup keeps in LDS (1-4)
+ *  track_splits: track ranges merged in fixed order afterwards (>= 1)
+ *  block_threads: workgroup size, a multiple of 64 in [64, 1024]
+ *  bins_per_segment: bins per LDS trace segment, a multiple of 64 (or
+ *                    n_bins); segments split long traces across workgroups
+ * Results do not depend on the tiling beyond floating-point summation
+ * order; bins never change. */
+int rt_plan_set_tiling(rt_plan *plan, int antennas_per_block, int track_splits,
+                       int block_threads, int bins_per_segment);
+
+/* The launch shape the plan would use for n_tracks tracks (host outputs,
+ * any may be NULL). */
+int rt_plan_get_tiling(const rt_plan *plan, int64_t n_tracks, int *antennas_per_block,
+                       int *track_splits, int *block_threads, int *bins_per_segment);
+
+/* Device workspace (bytes) rt_accumulate needs for a call with n_tracks
+ * tracks. */
+int rt_plan_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes);
+
+/* The hot loop (§2): for every track and every antenna, propagate both ends,
+ * then add the formalism's contribution into traces (device, [M][n_bins][3],
+ * += so that track chunks can be streamed in consecutive calls):
+ *   Endpoint: at each end an impulse  s k qw [r x (r x beta)] /
+ *             ((1 - n_src beta.r) R dt)  in the bin of that end's arrival,
+ *             s = +1 at the start and -1 at the end, n_src the local index.
+ *   ZHS:      the segment's vector potential, a box between the two arrival
+ *             times whose time integral is k qw beta_perp (t1 - t0) / R_mid
+ *             (beta_perp and R_mid at the segment midpoint), averaged over
+ *             every bin it overlaps.
+ * workspace: device, >= rt_plan_workspace_bytes(plan, tracks->n) bytes, used
+ * as scratch by this call only. tracks->n == 0 is a no-op. Partial traces of
+ * track splits are merged in a fixed order (no float atomics in global
+ * memory), so a call is repeatable for a fixed tiling up to the order of LDS
+ * additions within a workgroup. */
+int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *workspace,
+                  size_t workspace_bytes, void *stream);
+
+/* The propagator alone (§2; the "simple" radio propagator of Listing 2) for
+ * every (end e, track i, antenna a), stored at index (e * n + i) * M + a:
+ *   t_arrival (device double, may be NULL): arrival time (s)
+ *   bin (device int32, may be NULL): bin index, -1 outside the window.
+ * These are the exact times and bins rt_accumulate uses. */
+int rt_propagate(const rt_plan *plan, const rt_tracks *tracks, double *t_arrival, int32_t *bin,
+                 void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADTRACE_H */

@@ -135,9 +135,19 @@ static int64_t bin_of(double u, int32_t n_bins) {
 
 /* ------------------------------------------------------------- formalisms */
 
+/* A track with any non-finite field (position, time, velocity or weight)
+ * contributes nothing. */
+static int track_is_finite(const orc_tracks *tr, int64_t i) {
+  return isfinite(tr->x0[i]) && isfinite(tr->y0[i]) && isfinite(tr->z0[i]) &&
+         isfinite(tr->t0[i]) && isfinite(tr->x1[i]) && isfinite(tr->y1[i]) &&
+         isfinite(tr->z1[i]) && isfinite(tr->t1[i]) && isfinite(tr->bx[i]) &&
+         isfinite(tr->by[i]) && isfinite(tr->bz[i]) && isfinite(tr->qw[i]);
+}
+
 /* Endpoint formalism, one (track, antenna) pair: an impulse at each end. */
 static void endpoint_pair(const orc_tracks *tr, int64_t i, const orc_antennas *ar,
                           const orc_medium *md, int64_t a, double k, double *trace) {
+  if (!track_is_finite(tr, i)) return;
   for (int end = 0; end < 2; ++end) {
     double px = end ? tr->x1[i] : tr->x0[i];
     double py = end ? tr->y1[i] : tr->y0[i];
@@ -187,6 +197,7 @@ static int zhs_integral(const orc_tracks *tr, int64_t i, const orc_antennas *ar,
  * over each bin it overlaps (bin value = integral * overlap / width / dt). */
 static void zhs_pair(const orc_tracks *tr, int64_t i, const orc_antennas *ar,
                      const orc_medium *md, int64_t a, double k, double *trace) {
+  if (!track_is_finite(tr, i)) return;
   path ps = propagate(ar, md, a, tr->x0[i], tr->y0[i], tr->z0[i], tr->t0[i]);
   path pe = propagate(ar, md, a, tr->x1[i], tr->y1[i], tr->z1[i], tr->t1[i]);
   double ulo = ps.u < pe.u ? ps.u : pe.u;
@@ -380,7 +391,7 @@ static void *vjp_worker(void *arg) {
   for (int64_t i = job->i_begin; i < job->i_end; ++i) {
     double gq = 0.0, gp0[3] = {0, 0, 0}, gp1[3] = {0, 0, 0}, gn = 0.0;
     double bx = tr->bx[i], by = tr->by[i], bz = tr->bz[i];
-    for (int64_t a = 0; a < ar->m; ++a) {
+    for (int64_t a = 0; a < ar->m && track_is_finite(tr, i); ++a) {
       path ps = propagate(ar, md, a, tr->x0[i], tr->y0[i], tr->z0[i], tr->t0[i]);
       path pe = propagate(ar, md, a, tr->x1[i], tr->y1[i], tr->z1[i], tr->t1[i]);
       int start_is_lo = ps.u < pe.u;

@@ -9,11 +9,12 @@ per-antenna 3-component time traces (the loop of §2 of the paper).
 lives in ``radtrace`` and is imported on first use: it raises if the compiled
 library is missing rather than falling back to anything else.
 """
+import importlib
+
 __all__ = ["workloads", "radtrace"]
 
 
 def __getattr__(name):
-    if name == "radtrace":
-        from . import radtrace
-        return radtrace
+    if name in ("radtrace", "workloads"):
+        return importlib.import_module(f"{__name__}.{name}")
     raise AttributeError(name)

@@ -1,0 +1,202 @@
+// api.hip -- the extern "C" entry points of include/radtrace.h: argument
+// validation, plan set-up and launches on the caller's stream.
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "rt_internal.h"
+
+static thread_local std::string g_last_error;
+
+void rt_set_error(const std::string &msg) { g_last_error = msg; }
+
+static int fail(int status, const std::string &msg) {
+  rt_set_error(msg);
+  return status;
+}
+
+static bool is_finite(double x) { return std::isfinite(x); }
+
+static int hip_fail(hipError_t e, const char *what) {
+  return fail(RT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static int check_tracks(const rt_plan *p, const rt_tracks *t) {
+  if (!t) return fail(RT_E_INVALID, "tracks is NULL");
+  if (t->n < 0) return fail(RT_E_INVALID, "tracks->n < 0");
+  if (t->n == 0) return RT_OK;
+  if (!t->x0 || !t->y0 || !t->z0 || !t->t0 || !t->x1 || !t->y1 || !t->z1 || !t->t1 || !t->bx ||
+      !t->by || !t->bz || !t->qw)
+    return fail(RT_E_INVALID, "a track array pointer is NULL");
+  if ((int64_t)p->det.n_antennas > 0 && t->n > INT64_MAX / p->det.n_antennas)
+    return fail(RT_E_INVALID, "n_tracks * n_antennas overflows");
+  return RT_OK;
+}
+
+extern "C" {
+
+int rt_abi_version(void) { return RT_ABI_VERSION; }
+
+const char *rt_status_string(int status) {
+  switch (status) {
+    case RT_OK: return "ok";
+    case RT_E_INVALID: return "invalid argument";
+    case RT_E_UNSUPPORTED: return "unsupported configuration";
+    case RT_E_NO_DEVICE: return "no usable HIP device";
+    case RT_E_HIP: return "HIP runtime error";
+    case RT_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char *rt_last_error(void) { return g_last_error.c_str(); }
+
+int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med, int formalism,
+                   int precision, double k) {
+  if (!plan) return fail(RT_E_INVALID, "plan output pointer is NULL");
+  *plan = nullptr;
+  if (!det || !med) return fail(RT_E_INVALID, "detector or medium is NULL");
+  if (det->n_antennas < 1) return fail(RT_E_INVALID, "detector needs at least one antenna");
+  if (!det->x || !det->y || !det->z || !det->t_start)
+    return fail(RT_E_INVALID, "an antenna array pointer is NULL");
+  if (!(det->dt > 0.0) || !is_finite(det->dt)) return fail(RT_E_INVALID, "dt must be finite and > 0");
+  if (det->n_bins < 1) return fail(RT_E_INVALID, "n_bins must be >= 1");
+  if ((int64_t)det->n_bins * 3 > INT32_MAX / 2) return fail(RT_E_UNSUPPORTED, "n_bins too large");
+  if (formalism != RT_ENDPOINT && formalism != RT_ZHS)
+    return fail(RT_E_INVALID, "formalism must be RT_ENDPOINT or RT_ZHS");
+  if (precision != RT_FP64 && precision != RT_MIXED)
+    return fail(RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
+  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL)
+    return fail(RT_E_INVALID, "medium kind must be RT_UNIFORM or RT_EXPONENTIAL");
+  if (!(med->n0_minus_1 >= 0.0) || !is_finite(med->n0_minus_1))
+    return fail(RT_E_INVALID, "n0_minus_1 must be finite and >= 0");
+  if (med->kind == RT_EXPONENTIAL && (!(med->scale_height > 0.0) || !is_finite(med->scale_height)))
+    return fail(RT_E_INVALID, "scale_height must be finite and > 0");
+  if (!is_finite(k)) return fail(RT_E_INVALID, "k must be finite");
+
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return fail(RT_E_NO_DEVICE, "no HIP device is available");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_NO_DEVICE, "hipGetDevice failed");
+  int cus = 0, lds_block = 0, lds_cu = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+  if (e != hipSuccess) return hip_fail(e, "querying device attributes");
+
+  rt_plan *p = new (std::nothrow) rt_plan();
+  if (!p) return fail(RT_E_INVALID, "out of host memory");
+  p->det = *det;
+  p->med = *med;
+  p->formalism = formalism;
+  p->precision = precision;
+  p->k = k;
+  p->device = dev;
+  p->num_cus = cus > 0 ? cus : 1;
+  p->lds_per_block = (size_t)(lds_block > 0 ? lds_block : 65536);
+  p->lds_per_cu = (size_t)(lds_cu > 0 ? lds_cu : (int)p->lds_per_block);
+  p->at_user = p->splits_user = p->block_user = p->seg_user = 0;
+  rt::Consts &c = p->c;
+  c.inv_c = 1.0 / 299792458.0;
+  c.inv_dt = 1.0 / det->dt;
+  c.k = k;
+  c.n_uniform = 1.0 + med->n0_minus_1;
+  c.n0m1 = med->n0_minus_1;
+  c.h = med->kind == RT_EXPONENTIAL ? med->scale_height : 1.0;
+  c.n0h = c.n0m1 * c.h;
+  c.nbins_d = (double)det->n_bins;
+  c.n_bins = det->n_bins;
+  c.medium = med->kind;
+  *plan = p;
+  return RT_OK;
+}
+
+int rt_plan_destroy(rt_plan *plan) {
+  delete plan;
+  return RT_OK;
+}
+
+int rt_plan_set_tiling(rt_plan *plan, int antennas_per_block, int track_splits, int block_threads,
+                       int bins_per_segment) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  if (antennas_per_block < 0 || antennas_per_block > rt::kMaxTile)
+    return fail(RT_E_INVALID, "antennas_per_block must be in [0, 4]");
+  if (track_splits < 0) return fail(RT_E_INVALID, "track_splits must be >= 0");
+  if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64))
+    return fail(RT_E_INVALID, "block_threads must be a multiple of 64 in [64, 1024]");
+  if (bins_per_segment < 0 ||
+      (bins_per_segment > 0 && bins_per_segment % 64 && bins_per_segment != plan->det.n_bins))
+    return fail(RT_E_INVALID, "bins_per_segment must be a multiple of 64 or n_bins");
+  const size_t acc = rt::acc_bytes(plan->precision);
+  int seg = bins_per_segment > 0 ? std::min(bins_per_segment, plan->det.n_bins) : 0;
+  if (seg > 0 && (size_t)seg * 3 * acc * (antennas_per_block > 0 ? antennas_per_block : 1) >
+                     plan->lds_per_block)
+    return fail(RT_E_UNSUPPORTED, "tile does not fit in LDS");
+  if (antennas_per_block > 0 && seg == 0) {
+    size_t need = (size_t)antennas_per_block * plan->det.n_bins * 3 * acc;
+    if (need > plan->lds_per_block)
+      return fail(RT_E_UNSUPPORTED, "antennas_per_block x n_bins does not fit in LDS; "
+                                    "also set bins_per_segment");
+  }
+  plan->at_user = antennas_per_block;
+  plan->splits_user = track_splits;
+  plan->block_user = block_threads;
+  plan->seg_user = bins_per_segment;
+  return RT_OK;
+}
+
+int rt_plan_get_tiling(const rt_plan *plan, int64_t n_tracks, int *antennas_per_block,
+                       int *track_splits, int *block_threads, int *bins_per_segment) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  if (n_tracks < 0) return fail(RT_E_INVALID, "n_tracks < 0");
+  rt::Tiling t = rt::choose_tiling(*plan, n_tracks);
+  if (antennas_per_block) *antennas_per_block = t.at;
+  if (track_splits) *track_splits = t.splits;
+  if (block_threads) *block_threads = t.block;
+  if (bins_per_segment) *bins_per_segment = t.seg_len;
+  return RT_OK;
+}
+
+int rt_plan_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes) {
+  if (!plan || !bytes) return fail(RT_E_INVALID, "plan or bytes is NULL");
+  if (n_tracks < 0) return fail(RT_E_INVALID, "n_tracks < 0");
+  *bytes = n_tracks == 0 ? 0 : rt::workspace_bytes(*plan, n_tracks);
+  return RT_OK;
+}
+
+int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *workspace,
+                  size_t workspace_bytes, void *stream) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  int s = check_tracks(plan, tracks);
+  if (s != RT_OK) return s;
+  if (tracks->n == 0) return RT_OK;
+  if (!traces) return fail(RT_E_INVALID, "traces is NULL");
+  size_t need = rt::workspace_bytes(*plan, tracks->n);
+  if (!workspace || workspace_bytes < need)
+    return fail(RT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
+                                    std::to_string(workspace ? workspace_bytes : 0));
+  (void)hipGetLastError();
+  hipError_t e = rt::launch_forward(*plan, *tracks, traces, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "launching the deposit kernels");
+  return RT_OK;
+}
+
+int rt_propagate(const rt_plan *plan, const rt_tracks *tracks, double *t_arrival, int32_t *bin,
+                 void *stream) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  int s = check_tracks(plan, tracks);
+  if (s != RT_OK) return s;
+  if (tracks->n == 0 || (!t_arrival && !bin)) return RT_OK;
+  (void)hipGetLastError();
+  hipError_t e = rt::launch_propagate(*plan, *tracks, t_arrival, bin, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "launching the propagator kernel");
+  return RT_OK;
+}
+
+}  // extern "C"

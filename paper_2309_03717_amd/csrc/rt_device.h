@@ -1,0 +1,101 @@
+// rt_device.h -- device-side building blocks shared by the radtrace kernels:
+// launch arguments, the straight-line propagator and the media.
+//
+// The propagator's timing chain is evaluated in double precision in one fixed
+// operation order (the whole library is compiled with -ffp-contract=off), so
+// that the arrival bin of every (end, track, antenna) is reproducible
+// bit-for-bit by any implementation of the same definition:
+//     d = X - P;  R = sqrt((dx*dx + dy*dy) + dz*dz)
+//     n_eff = 1 + n0m1                                   (uniform medium)
+//     n_eff = 1 + (n0m1*h) * ((eX - eP) / (zP - zX))     (exponential,
+//             e = exp(-(z / h)), |zP - zX| >= 1e-3 m)
+//     n_eff = 1 + n0m1 * exp(-(((zP + zX) * 0.5) / h))   (|zP - zX| < 1e-3 m)
+//     t = T + (n_eff * R) * (1 / c);   u = (t - t_start) * (1 / dt)
+//     in the window iff 0 <= u < n_bins; bin = floor(u)
+// The exponential form is the mean of n(z) = 1 + n0m1 exp(-z/h) along the
+// straight path (§2: the propagator gives the emission path of each pair).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rt {
+
+constexpr int kMaxTile = 4;     // antennas per workgroup tile (template bound)
+constexpr int kXcds = 8;        // MI355X: 8 XCDs, workgroups dealt round-robin
+
+struct Consts {
+  double inv_c;       // 1 / c
+  double inv_dt;      // 1 / dt
+  double k;           // field prefactor
+  double n_uniform;   // 1 + n0m1
+  double n0m1, h, n0h;  // n0h = n0m1 * h
+  double nbins_d;     // (double) n_bins
+  int32_t n_bins;
+  int32_t medium;     // 0 uniform, 1 exponential
+};
+
+struct TrackPtrs {
+  const double *x0, *y0, *z0, *t0, *x1, *y1, *z1, *t1;
+  const void *bx, *by, *bz, *qw;
+  int64_t n;
+};
+
+struct AntPtrs {
+  const double *x, *y, *z, *t_start;
+  int64_t m;
+};
+
+// exp(-(z / h)): the height factor of the exponential profile.
+__device__ __forceinline__ double height_factor(double z, const Consts &c) {
+  return exp(-(z / c.h));
+}
+
+// Path-mean refractive index from emission height zp (height factor ep) to an
+// antenna at height za (height factor ea).
+__device__ __forceinline__ double path_index(double zp, double za, double ep, double ea,
+                                             const Consts &c) {
+  double dz = zp - za;
+  if (fabs(dz) >= 1e-3) return 1.0 + c.n0h * ((ea - ep) / dz);
+  return 1.0 + c.n0m1 * exp(-(((zp + za) * 0.5) / c.h));
+}
+
+// Straight-line propagation of an emission at (px,py,pz), time tp, to an
+// antenna at (ax,ay,az) whose bin 0 starts at tau. Returns u, the arrival in
+// bins; d = X - P and R are returned for the amplitude.
+__device__ __forceinline__ double arrival_bins(double px, double py, double pz, double tp,
+                                               double ax, double ay, double az, double tau,
+                                               double neff, const Consts &c, double &dx,
+                                               double &dy, double &dz, double &r) {
+  dx = ax - px;
+  dy = ay - py;
+  dz = az - pz;
+  r = sqrt((dx * dx + dy * dy) + dz * dz);
+  double t = tp + (neff * r) * c.inv_c;
+  return (t - tau) * c.inv_dt;
+}
+
+// Arrival time (seconds) for the same path; used by the propagate entry point.
+__device__ __forceinline__ double arrival_time(double px, double py, double pz, double tp,
+                                               double ax, double ay, double az, double neff,
+                                               const Consts &c) {
+  double dx = ax - px, dy = ay - py, dz = az - pz;
+  double r = sqrt((dx * dx + dy * dy) + dz * dz);
+  return tp + (neff * r) * c.inv_c;
+}
+
+// Bijection of [0, grid) that gives each XCD a contiguous range of virtual
+// block ids (hardware deals workgroup b to XCD b % 8), so workgroups that
+// share a track range run on the same XCD and share its L2.
+__device__ __forceinline__ int xcd_major(int b, int grid) {
+  int per = grid / kXcds, rem = grid % kXcds;
+  int x = b % kXcds, j = b / kXcds;
+  return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T *p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+}  // namespace rt

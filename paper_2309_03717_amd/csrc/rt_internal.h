@@ -1,0 +1,60 @@
+// rt_internal.h -- host-side plan object and kernel launchers shared by the
+// translation units of libradtrace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/radtrace.h"
+#include "rt_device.h"
+
+struct rt_plan {
+  rt_detector det;        // device pointers owned by the caller
+  rt_medium med;
+  int formalism;          // rt_formalism
+  int precision;          // rt_precision
+  double k;
+  rt::Consts c;
+  int device;
+  int num_cus;
+  size_t lds_per_block;   // bytes of LDS one workgroup may use
+  size_t lds_per_cu;      // bytes of LDS per compute unit
+  // tiling (0 = automatic)
+  int at_user, splits_user, block_user, seg_user;
+};
+
+namespace rt {
+
+struct Tiling {
+  int at;          // antennas per tile
+  int seg_len;     // bins per segment
+  int n_segs;
+  int n_atiles;
+  int splits;
+  int block;
+  int64_t per_split;
+  size_t lds_bytes;
+};
+
+// Effective launch shape of a plan for n tracks.
+Tiling choose_tiling(const rt_plan &p, int64_t n);
+size_t acc_bytes(int precision);
+// Bytes of the per-track prepared media values for n tracks (0 if none).
+size_t prep_bytes(const rt_plan &p, int64_t n);
+size_t workspace_bytes(const rt_plan &p, int64_t n);
+
+TrackPtrs track_ptrs(const rt_tracks &t);
+AntPtrs ant_ptrs(const rt_detector &d);
+
+// Launchers: enqueue on `stream`, return the hipGetLastError() status.
+hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, void *workspace,
+                          hipStream_t stream);
+hipError_t launch_propagate(const rt_plan &p, const rt_tracks &t, double *t_arrival,
+                            int32_t *bin, hipStream_t stream);
+
+}  // namespace rt
+
+// Thread-local error text (api.hip).
+void rt_set_error(const std::string &msg);

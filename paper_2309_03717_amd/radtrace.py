@@ -1,0 +1,276 @@
+"""Python binding of libradtrace (include/radtrace.h): argument marshalling
+only. Every step of the computation runs in the library's HIP kernels; torch
+provides device memory and streams.
+
+The low-level functions carry the C names (``rt_plan_create``,
+``rt_accumulate``, ...). ``Plan`` bundles a detector, a plan handle and a
+workspace for convenience. Importing this module loads the compiled library
+and raises ImportError if it is missing: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch  # loads the HIP runtime the library must share
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libradtrace.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(or python paper_2309_03717_amd/build_lib.py)")
+
+_lib = C.CDLL(LIB_PATH)
+
+RT_OK, RT_E_INVALID, RT_E_UNSUPPORTED, RT_E_NO_DEVICE, RT_E_HIP, RT_E_WORKSPACE = range(6)
+RT_ENDPOINT, RT_ZHS = 0, 1
+RT_FP64, RT_MIXED = 0, 1
+RT_UNIFORM, RT_EXPONENTIAL = 0, 1
+FORMALISM = {"endpoint": RT_ENDPOINT, "zhs": RT_ZHS}
+PRECISION = {"fp64": RT_FP64, "mixed": RT_MIXED}
+K_SI = 4.80320471518522e-18
+
+
+class rt_medium(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n0_minus_1", C.c_double), ("scale_height", C.c_double)]
+
+
+class rt_detector(C.Structure):
+    _fields_ = [("n_antennas", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p),
+                ("z", C.c_void_p), ("t_start", C.c_void_p), ("dt", C.c_double),
+                ("n_bins", C.c_int32)]
+
+
+_TRACK_FIELDS = ("x0", "y0", "z0", "t0", "x1", "y1", "z1", "t1", "bx", "by", "bz", "qw")
+
+
+class rt_tracks(C.Structure):
+    _fields_ = [("n", C.c_int64)] + [(f, C.c_void_p) for f in _TRACK_FIELDS]
+
+
+_P = C.c_void_p
+_lib.rt_abi_version.restype = C.c_int
+_lib.rt_status_string.restype = C.c_char_p
+_lib.rt_status_string.argtypes = [C.c_int]
+_lib.rt_last_error.restype = C.c_char_p
+_lib.rt_plan_create.argtypes = [C.POINTER(_P), C.POINTER(rt_detector), C.POINTER(rt_medium),
+                                C.c_int, C.c_int, C.c_double]
+_lib.rt_plan_destroy.argtypes = [_P]
+_lib.rt_plan_set_tiling.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.c_int]
+_lib.rt_plan_get_tiling.argtypes = [_P, C.c_int64] + [C.POINTER(C.c_int)] * 4
+_lib.rt_plan_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
+_lib.rt_accumulate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
+_lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
+
+
+class RadtraceError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.rt_last_error().decode()
+        super().__init__(f"{where}: {_lib.rt_status_string(status).decode()} ({status}): {msg}")
+
+
+def _check(status: int, where: str):
+    if status != RT_OK:
+        raise RadtraceError(status, where)
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+# ------------------------------------------------------------------ device data
+@dataclass
+class DeviceDetector:
+    """Antenna arrays on the device (float64 tensors) plus the time binning."""
+    x: torch.Tensor
+    y: torch.Tensor
+    z: torch.Tensor
+    t_start: torch.Tensor
+    dt: float
+    n_bins: int
+
+    @property
+    def m(self) -> int:
+        return int(self.x.numel())
+
+    @staticmethod
+    def from_array(array, device="cuda") -> "DeviceDetector":
+        f = lambda a: torch.as_tensor(a, dtype=torch.float64).contiguous().to(device)
+        return DeviceDetector(f(array.x), f(array.y), f(array.z), f(array.t_start),
+                              float(array.dt), int(array.n_bins))
+
+    def struct(self) -> rt_detector:
+        for t in (self.x, self.y, self.z, self.t_start):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != self.m:
+                raise ValueError("antenna arrays must be contiguous float64 of equal length")
+        return rt_detector(self.m, _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.t_start),
+                           self.dt, self.n_bins)
+
+
+@dataclass
+class DeviceTracks:
+    """Structure-of-arrays tracks on the device: geometry float64; beta and
+    qw float64 (FP64 plans) or float32 (mixed plans)."""
+    x0: torch.Tensor
+    y0: torch.Tensor
+    z0: torch.Tensor
+    t0: torch.Tensor
+    x1: torch.Tensor
+    y1: torch.Tensor
+    z1: torch.Tensor
+    t1: torch.Tensor
+    bx: torch.Tensor
+    by: torch.Tensor
+    bz: torch.Tensor
+    qw: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.x0.numel())
+
+    @staticmethod
+    def from_tracks(tracks, device="cuda") -> "DeviceTracks":
+        return DeviceTracks(**{f: torch.from_numpy(getattr(tracks, f).copy()).to(device)
+                               for f in _TRACK_FIELDS})
+
+    def struct(self, precision: int) -> rt_tracks:
+        want = torch.float64 if precision == RT_FP64 else torch.float32
+        n = self.n
+        for f in _TRACK_FIELDS:
+            t = getattr(self, f)
+            dt = torch.float64 if f in _TRACK_FIELDS[:8] else want
+            if t.dtype != dt or not t.is_contiguous() or t.numel() != n:
+                raise ValueError(f"track field {f} must be contiguous {dt} of length {n}")
+        return rt_tracks(n, *[_ptr(getattr(self, f)) for f in _TRACK_FIELDS])
+
+    def slice(self, lo: int, hi: int) -> "DeviceTracks":
+        return DeviceTracks(**{f: getattr(self, f)[lo:hi] for f in _TRACK_FIELDS})
+
+
+# ------------------------------------------------------------------ C names
+def rt_abi_version() -> int:
+    return _lib.rt_abi_version()
+
+
+def rt_status_string(status: int) -> str:
+    return _lib.rt_status_string(status).decode()
+
+
+def rt_last_error() -> str:
+    return _lib.rt_last_error().decode()
+
+
+def rt_plan_create(det: DeviceDetector, medium_kind: int, n0_minus_1: float, scale_height: float,
+                   formalism: int, precision: int, k: float) -> int:
+    handle = _P()
+    d = det.struct()
+    m = rt_medium(medium_kind, n0_minus_1, scale_height)
+    _check(_lib.rt_plan_create(C.byref(handle), C.byref(d), C.byref(m), formalism, precision,
+                               float(k)), "rt_plan_create")
+    return handle.value
+
+
+def rt_plan_destroy(plan: int) -> None:
+    _check(_lib.rt_plan_destroy(plan), "rt_plan_destroy")
+
+
+def rt_plan_set_tiling(plan: int, antennas_per_block=0, track_splits=0, block_threads=0,
+                       bins_per_segment=0) -> None:
+    _check(_lib.rt_plan_set_tiling(plan, antennas_per_block, track_splits, block_threads,
+                                   bins_per_segment), "rt_plan_set_tiling")
+
+
+def rt_plan_get_tiling(plan: int, n_tracks: int):
+    v = [C.c_int() for _ in range(4)]
+    _check(_lib.rt_plan_get_tiling(plan, n_tracks, *[C.byref(x) for x in v]),
+           "rt_plan_get_tiling")
+    return tuple(x.value for x in v)
+
+
+def rt_plan_workspace_bytes(plan: int, n_tracks: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.rt_plan_workspace_bytes(plan, n_tracks, C.byref(b)), "rt_plan_workspace_bytes")
+    return b.value
+
+
+def rt_accumulate(plan: int, tracks: rt_tracks, traces: torch.Tensor, workspace: torch.Tensor,
+                  stream=None) -> None:
+    _check(_lib.rt_accumulate(plan, C.byref(tracks), _ptr(traces), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream)),
+           "rt_accumulate")
+
+
+def rt_propagate(plan: int, tracks: rt_tracks, t_arrival: Optional[torch.Tensor],
+                 bins: Optional[torch.Tensor], stream=None) -> None:
+    _check(_lib.rt_propagate(plan, C.byref(tracks), _ptr(t_arrival), _ptr(bins), _stream(stream)),
+           "rt_propagate")
+
+
+# ------------------------------------------------------------------ convenience
+class Plan:
+    """A radio process for one detector, medium, formalism and precision
+    (§4, Listing 2), with its own workspace."""
+
+    def __init__(self, det: DeviceDetector, medium, formalism: str = "endpoint",
+                 precision: str = "fp64", k: float = 1.0):
+        self.det = det
+        self.medium = medium
+        self.formalism = FORMALISM[formalism]
+        self.precision = PRECISION[precision]
+        kind = RT_UNIFORM if medium.kind == "uniform" else RT_EXPONENTIAL
+        self.handle = rt_plan_create(det, kind, float(medium.n0m1), float(medium.h),
+                                     self.formalism, self.precision, k)
+        self._ws = None
+        self.dtype = torch.float64 if self.precision == RT_FP64 else torch.float32
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.rt_plan_destroy(h)
+            self.handle = None
+
+    def set_tiling(self, antennas_per_block=0, track_splits=0, block_threads=0,
+                   bins_per_segment=0):
+        rt_plan_set_tiling(self.handle, antennas_per_block, track_splits, block_threads,
+                           bins_per_segment)
+
+    def tiling(self, n_tracks: int):
+        return rt_plan_get_tiling(self.handle, n_tracks)
+
+    def workspace(self, n_tracks: int) -> torch.Tensor:
+        need = rt_plan_workspace_bytes(self.handle, n_tracks)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.det.x.device)
+        return self._ws
+
+    def new_traces(self) -> torch.Tensor:
+        return torch.zeros((self.det.m, self.det.n_bins, 3), dtype=self.dtype,
+                           device=self.det.x.device)
+
+    def accumulate(self, tracks: DeviceTracks, traces: torch.Tensor, stream=None) -> torch.Tensor:
+        if traces.dtype != self.dtype or not traces.is_contiguous() or \
+                tuple(traces.shape) != (self.det.m, self.det.n_bins, 3):
+            raise ValueError("traces must be a contiguous [M, n_bins, 3] tensor of the plan dtype")
+        rt_accumulate(self.handle, tracks.struct(self.precision), traces, self.workspace(tracks.n),
+                      stream)
+        return traces
+
+    def traces(self, tracks: DeviceTracks, stream=None) -> torch.Tensor:
+        return self.accumulate(tracks, self.new_traces(), stream)
+
+    def propagate(self, tracks: DeviceTracks, stream=None):
+        shape = (2, tracks.n, self.det.m)
+        t = torch.empty(shape, dtype=torch.float64, device=self.det.x.device)
+        b = torch.empty(shape, dtype=torch.int32, device=self.det.x.device)
+        rt_propagate(self.handle, tracks.struct(self.precision), t, b, stream)
+        return t, b
