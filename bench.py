@@ -1,0 +1,238 @@
+"""Benchmark of the track x antenna radio-emission loop on one MI355X.
+
+Workload: 1e8 straight tracks (streamed in chunks of 2^22, all resident in
+HBM before timing) x 4096 antennas on a 64 x 64 grid of 50 m spacing,
+exponential refractivity, 4096 bins of 0.2 ns x 3 components, mixed
+precision (FP64 arrival time and bins, FP32 amplitudes and traces); one step
+is the Endpoint pass plus the ZHS pass over all tracks. The metric is
+antenna-track pairs per second over both formalisms.
+
+Prints one JSON line on stdout (progress goes to stderr). The roofline entry
+is for the dominant deposit kernel, timed with HIP events recorded on its own
+stream around every launch; the CPU baseline is the FP64 oracle on a bounded
+sample of the same workload on this host's cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "antenna-track pairs/sec (Endpoint, ZHS), % FP32 VALU peak; mixed vs FP64"
+
+# Algorithmic floating-point operations of the definition (add, sub, mul, div,
+# sqrt each count 1; comparisons and index arithmetic are not counted), mixed
+# mode, split into the part every pair needs (the arrival-time chain, which
+# decides whether the pair lands in the window) and the part only pairs that
+# land need (amplitude and deposit). Per-track and per-antenna work is
+# excluded.
+OPS = {
+    # per track end: timing 14 (FP64); amplitude and deposit 21 (10 FP64: beta.d,
+    # n beta.d, R - n beta.d, three accumulating adds; 11 FP32: (beta.d)/R^2,
+    # d q - beta, s k qw / (num dt), a V)
+    "endpoint": {"timing_per_end": 14, "amp_per_end_fp64": 10, "amp_per_end_fp32": 11},
+    # per pair: timing of both ends 28 (FP64); box 61 (16 FP64: width, the two
+    # edge shares, twelve accumulating adds; 45 FP32: midpoint geometry 27, box
+    # height 4, deposit values 14)
+    "zhs": {"timing": 28, "box_fp64": 16, "box_fp32": 45},
+}
+# MI355X VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12
+# lane-operations/s for FP64 and for unpacked FP32 (packed FP32 is disabled in
+# this build); the published 78.6 TFLOP/s counts an FMA as two operations.
+VALU_OPS_PEAK = 256 * 64 * 2.4e9
+FP32_PEAK_PUBLISHED = 157.3e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def in_window_fractions(rt, plan, dtr, n_sample):
+    """Fraction of track ends (Endpoint) and of boxes (ZHS) that land in the
+    window, from the library's own propagator on a sample of tracks."""
+    import torch
+    t, b = plan.propagate(dtr.slice(0, n_sample))
+    torch.cuda.synchronize()
+    ends_in = float((b >= 0).double().mean().item())
+    # a box overlaps iff u_hi >= 0 and u_lo < B; with both ends outside on
+    # opposite sides it still overlaps (rare); count via the arrival times
+    tau = plan.det.t_start.view(1, -1)
+    dt = plan.det.dt
+    u = (t - tau) / dt
+    lo = torch.minimum(u[0], u[1])
+    hi = torch.maximum(u[0], u[1])
+    box_in = float(((hi >= 0) & (lo < plan.det.n_bins)).double().mean().item())
+    del t, b, u, lo, hi
+    return ends_in, box_in
+
+
+def ops_per_pair(formalism, ends_in, box_in):
+    o = OPS[formalism]
+    if formalism == "endpoint":
+        f64 = 2 * (o["timing_per_end"] + ends_in * o["amp_per_end_fp64"])
+        f32 = 2 * ends_in * o["amp_per_end_fp32"]
+    else:
+        f64 = o["timing"] + box_in * o["box_fp64"]
+        f32 = box_in * o["box_fp32"]
+    return f64, f32
+
+
+def cpu_baseline(workload, n_sample):
+    import oracle
+    oracle._load()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    tr = workload.tracks(n_sample).to_mixed().widened()
+    secs = {}
+    for f in ("endpoint", "zhs"):
+        t0 = time.perf_counter()
+        oracle.traces(f, tr, workload.array, workload.medium, k=1.0, n_threads=cores)
+        secs[f] = time.perf_counter() - t0
+        log(f"cpu baseline {f}: {secs[f]:.2f} s on {cores} threads")
+    pairs = tr.n * workload.array.m
+    return {"value": 2 * pairs / (secs["endpoint"] + secs["zhs"]), "unit": "pairs/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"first {tr.n} tracks of the {workload.n_tracks}-track workload x all "
+                      f"{workload.array.m} antennas, Endpoint and ZHS each, FP64 oracle on the "
+                      f"same float32-rounded beta/qw",
+            "seconds": {k: round(v, 3) for k, v in secs.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tracks", type=int, default=None,
+                    help="override the track count (smaller runs for profiling)")
+    ap.add_argument("--formalisms", default="endpoint,zhs")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiling", default=None, help="at,splits,block,seg override")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(antenna sharding across GPUs is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2309_03717_amd import radtrace as rt
+    from paper_2309_03717_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.config(2)
+    n_total = args.tracks or w.n_tracks
+    chunk = w.chunk
+    formalisms = args.formalisms.split(",")
+
+    # ---- inputs resident in HBM before timing
+    t0 = time.perf_counter()
+    fields = {f: [] for f in W.TRACK_FIELDS}
+    for lo in range(0, n_total, chunk):
+        part = w.tracks(min(chunk, n_total - lo), start=lo, mixed=True)
+        for f in W.TRACK_FIELDS:
+            fields[f].append(torch.from_numpy(getattr(part, f)).to("cuda", non_blocking=False))
+        if (lo // chunk) % 6 == 0:
+            log(f"generated {lo + part.n}/{n_total} tracks ({time.perf_counter() - t0:.1f} s)")
+    chunks = [rt.DeviceTracks(**{f: fields[f][c] for f in W.TRACK_FIELDS})
+              for c in range(len(fields["x0"]))]
+    det = rt.DeviceDetector.from_array(w.array)
+    plans = {f: rt.Plan(det, w.medium, f, "mixed", k=rt.K_SI) for f in formalisms}
+    if args.tiling:
+        for p in plans.values():
+            p.set_tiling(*[int(x) for x in args.tiling.split(",")])
+    traces = {f: plans[f].new_traces() for f in formalisms}
+    for f in formalisms:
+        plans[f].workspace(chunk)
+    torch.cuda.synchronize()
+    log(f"inputs resident: {n_total} tracks in {len(chunks)} chunks, "
+        f"{sum(c.n for c in chunks) * 80 / 1e9:.2f} GB ({time.perf_counter() - t0:.1f} s)")
+
+    kernel_events = {f: [] for f in formalisms}
+
+    def step(record):
+        for f in formalisms:
+            traces[f].zero_()
+            for c in chunks:
+                if record:
+                    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    rt.rt_plan_set_timing_events(plans[f].handle, s, e)
+                    kernel_events[f].append((s, e))
+                plans[f].accumulate(c, traces[f])
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for i in range(args.steps):
+        step(True)
+        if i == 0:
+            pass
+    stop.record()
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(stop)
+    ms_step = ms_total / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.1f} ms/step")
+
+    pairs_per_formalism = n_total * w.array.m
+    value = len(formalisms) * pairs_per_formalism / (ms_step / 1e3)
+
+    # ---- per-kernel durations and the roofline of the dominant kernel
+    ends_in, box_in = in_window_fractions(rt, plans[formalisms[0]], chunks[0],
+                                          min(chunks[0].n, 1 << 13))
+    per = {}
+    for f in formalisms:
+        durs = [s.elapsed_time(e) for s, e in kernel_events[f]]
+        n_launch = len(durs)
+        avg_ms = sum(durs) / n_launch
+        f64, f32 = ops_per_pair(f, ends_in, box_in)
+        pairs_per_launch = pairs_per_formalism * args.steps / n_launch
+        achieved = (f64 + f32) * pairs_per_launch / (avg_ms / 1e3)
+        per[f] = {"kernel_ms_avg": avg_ms, "launches": n_launch,
+                  "kernel_ms_total_per_step": sum(durs) / args.steps,
+                  "pairs_per_s_kernel": pairs_per_launch / (avg_ms / 1e3),
+                  "ops_per_pair": {"fp64": round(f64, 3), "fp32": round(f32, 3)},
+                  "achieved_tops": achieved / 1e12,
+                  "fp32_peak_frac_literal": f32 * pairs_per_launch / (avg_ms / 1e3) / FP32_PEAK_PUBLISHED}
+    dom = max(formalisms, key=lambda f: per[f]["kernel_ms_total_per_step"])
+    achieved = per[dom]["achieved_tops"]
+    peak = VALU_OPS_PEAK / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": f"deposit_kernel<{dom},mixed,exponential>",
+                "kernel_ms_avg": round(per[dom]["kernel_ms_avg"], 3),
+                "ops_per_pair": per[dom]["ops_per_pair"],
+                "in_window": {"endpoint_ends": round(ends_in, 4), "zhs_boxes": round(box_in, 4)}}
+
+    out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": w.name if n_total == w.n_tracks else f"{w.name}[{n_total}]",
+                      "n_tracks": n_total, "n_antennas": w.array.m, "n_bins": w.array.n_bins,
+                      "dt_ns": w.array.dt * 1e9, "medium": w.medium.kind,
+                      "precision": "mixed", "formalisms": formalisms, "chunk": chunk,
+                      "tiling": {f: plans[f].tiling(chunk) for f in formalisms}},
+           "per_formalism": {f: {"pairs_per_s": pairs_per_formalism / (per[f]["kernel_ms_total_per_step"] / 1e3),
+                                 **{k: (round(v, 4) if isinstance(v, float) else v)
+                                    for k, v in per[f].items()}} for f in formalisms},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n_total))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -61,8 +61,8 @@ typedef enum { RT_ENDPOINT = 0, RT_ZHS = 1 } rt_formalism;
 
 /* RT_FP64: all arithmetic and the traces in double precision.
  * RT_MIXED: arrival time, distance and bin decision in double precision
- * (the same bins as RT_FP64); amplitudes, accumulation and traces in float;
- * tracks carry beta and qw as float. */
+ * (the same bins as RT_FP64); amplitudes in float, accumulated in double,
+ * traces in float; tracks carry beta and qw as float. */
 typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
 
 /* Refractive-index model of the environment the propagator is built from
@@ -164,6 +164,13 @@ int rt_plan_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes
  * additions within a workgroup. */
 int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *workspace,
                   size_t workspace_bytes, void *stream);
+
+/* Profiling aid: the next rt_accumulate call on this plan records
+ * start_event on its stream immediately before its deposit kernel and
+ * stop_event immediately after it, then forgets both. The events are
+ * hipEvent_t handles passed as void*, created and owned by the caller (with
+ * timing enabled); NULL for both clears a pending request. */
+int rt_plan_set_timing_events(rt_plan *plan, void *start_event, void *stop_event);
 
 /* The propagator alone (§2; the "simple" radio propagator of Listing 2) for
  * every (end e, track i, antenna a), stored at index (e * n + i) * M + a:

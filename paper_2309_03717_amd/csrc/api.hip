@@ -102,6 +102,7 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
   p->lds_per_block = (size_t)(lds_block > 0 ? lds_block : 65536);
   p->lds_per_cu = (size_t)(lds_cu > 0 ? lds_cu : (int)p->lds_per_block);
   p->at_user = p->splits_user = p->block_user = p->seg_user = 0;
+  p->ev_start = p->ev_stop = nullptr;
   rt::Consts &c = p->c;
   c.inv_c = 1.0 / 299792458.0;
   c.inv_dt = 1.0 / det->dt;
@@ -183,7 +184,17 @@ int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *wo
                                     std::to_string(workspace ? workspace_bytes : 0));
   (void)hipGetLastError();
   hipError_t e = rt::launch_forward(*plan, *tracks, traces, workspace, (hipStream_t)stream);
+  plan->ev_start = plan->ev_stop = nullptr;
   if (e != hipSuccess) return hip_fail(e, "launching the deposit kernels");
+  return RT_OK;
+}
+
+int rt_plan_set_timing_events(rt_plan *plan, void *start_event, void *stop_event) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return fail(RT_E_INVALID, "give both events or neither");
+  plan->ev_start = (hipEvent_t)start_event;
+  plan->ev_stop = (hipEvent_t)stop_event;
   return RT_OK;
 }
 

@@ -16,17 +16,23 @@
 
 namespace rt {
 
+// Accumulation in LDS and in the split partials is double precision in both
+// modes: gfx950 executes LDS double-precision atomic adds (ds_add_f64) at
+// close to the rate of plain LDS stores, while single-precision ones
+// (ds_add_f32) are several times slower on this workload.
+using acc_t = double;
+
 template <int P>
 struct Prec;
 template <>
 struct Prec<0> {  // RT_FP64
-  using acc = double;
-  using in = double;
+  using in = double;   // beta, qw
+  using out = double;  // traces
 };
 template <>
 struct Prec<1> {  // RT_MIXED
-  using acc = float;
   using in = float;
+  using out = float;
 };
 
 struct DepositArgs {
@@ -75,12 +81,12 @@ __device__ __forceinline__ void put3_clamped(T *row, int j, int lo, int hi, T vx
 // ((1 - n_src beta.r) R dt), written as sc * (d (beta.d) / R^2 - beta) / num
 // with num = R - n_src (beta.d) = (1 - n_src beta.r) R and sc = s k qw / dt.
 template <int P>
-__device__ __forceinline__ void endpoint_end(typename Prec<P>::acc *row, int lo, int hi, double sc,
+__device__ __forceinline__ void endpoint_end(acc_t *row, int lo, int hi, double sc,
                                              double px, double py, double pz, double tp,
                                              double ax, double ay, double az, double tau,
                                              double neff, double nsrc, double bx, double by,
                                              double bz, const Consts &c) {
-  using T = typename Prec<P>::acc;
+  using T = acc_t;
   double dx, dy, dz, r;
   double u = arrival_bins(px, py, pz, tp, ax, ay, az, tau, neff, c, dx, dy, dz, r);
   if (!(u >= 0.0 && u < c.nbins_d)) return;
@@ -110,11 +116,11 @@ __device__ __forceinline__ void endpoint_end(typename Prec<P>::acc *row, int lo,
 // deposited as at most four differences whose prefix sum is that average,
 // each bounded by |Ibar|.
 template <int P>
-__device__ __forceinline__ void zhs_box(typename Prec<P>::acc *row, int lo, int hi, double us,
-                                        double ue, double mx, double my, double mz, double ax,
-                                        double ay, double az, double cz, double bx, double by,
-                                        double bz) {
-  using T = typename Prec<P>::acc;
+__device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double us, double ue,
+                                        double mx, double my, double mz, double ax, double ay,
+                                        double az, double cz, double bx, double by, double bz) {
+  // T: arithmetic type of the amplitudes (deposits are widened to acc_t)
+  using T = typename Prec<P>::out;
   double ulo = us < ue ? us : ue;
   double uhi = us < ue ? ue : us;
   if (!(uhi >= (double)lo && ulo < (double)hi)) return;   // outside this segment (or NaN)
@@ -145,8 +151,8 @@ __device__ __forceinline__ void zhs_box(typename Prec<P>::acc *row, int lo, int 
   double kl = floor(ulo), kh = floor(uhi);
   if (kl == kh) {   // whole box inside one bin of this segment
     int j = (int)kl;
-    put3<T>(row, j - lo, ix, iy, iz);
-    if (j + 1 < hi) put3<T>(row, j + 1 - lo, -ix, -iy, -iz);
+    put3<acc_t>(row, j - lo, ix, iy, iz);
+    if (j + 1 < hi) put3<acc_t>(row, j + 1 - lo, -ix, -iy, -iz);
     return;
   }
   double w = uhi - ulo;
@@ -167,9 +173,9 @@ __device__ __forceinline__ void zhs_box(typename Prec<P>::acc *row, int lo, int 
     }
     T axv = ix * fa, ayv = iy * fa, azv = iz * fa;
     T bxv = ix * fb, byv = iy * fb, bzv = iz * fb;
-    put3_clamped<T>(row, jl, lo, hi, axv, ayv, azv);
-    put3_clamped<T>(row, jl + 1, lo, hi, bxv - axv, byv - ayv, bzv - azv);
-    put3_clamped<T>(row, jl + 2, lo, hi, -bxv, -byv, -bzv);
+    put3_clamped<acc_t>(row, jl, lo, hi, axv, ayv, azv);
+    put3_clamped<acc_t>(row, jl + 1, lo, hi, bxv - axv, byv - ayv, bzv - azv);
+    put3_clamped<acc_t>(row, jl + 2, lo, hi, -bxv, -byv, -bzv);
   } else {
     T wi;
     if (P == 0) wi = (T)(1.0 / w);
@@ -177,10 +183,10 @@ __device__ __forceinline__ void zhs_box(typename Prec<P>::acc *row, int lo, int 
     T hx = ix * wi, hy = iy * wi, hz = iz * wi;
     T fl = (T)flo, fh = (T)fhi;
     T gl = (T)1 - fl, gh = (T)1 - fh;
-    put3_clamped<T>(row, jl, lo, hi, hx * fl, hy * fl, hz * fl);
-    put3_clamped<T>(row, jl + 1, lo, hi, hx * gl, hy * gl, hz * gl);
-    put3_clamped<T>(row, jh, lo, hi, -hx * gh, -hy * gh, -hz * gh);
-    put3_clamped<T>(row, jh + 1, lo, hi, -hx * fh, -hy * fh, -hz * fh);
+    put3_clamped<acc_t>(row, jl, lo, hi, hx * fl, hy * fl, hz * fl);
+    put3_clamped<acc_t>(row, jl + 1, lo, hi, hx * gl, hy * gl, hz * gl);
+    put3_clamped<acc_t>(row, jh, lo, hi, -hx * gh, -hy * gh, -hz * gh);
+    put3_clamped<acc_t>(row, jh + 1, lo, hi, -hx * fh, -hy * fh, -hz * fh);
   }
 }
 
@@ -188,7 +194,7 @@ __device__ __forceinline__ void zhs_box(typename Prec<P>::acc *row, int lo, int 
 // AT: antennas per tile.
 template <int F, int P, int MED, int AT>
 __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
-  using T = typename Prec<P>::acc;
+  using T = acc_t;
   using In = typename Prec<P>::in;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   T *tile = reinterpret_cast<T *>(smem);
@@ -310,8 +316,8 @@ template <int F, int P>
 __global__ void __launch_bounds__(256) merge_kernel(const void *partial, void *traces, int64_t m,
                                                     int n_bins, int splits, int seg_len,
                                                     int n_segs) {
-  using T = typename Prec<P>::acc;
-  const T *part = reinterpret_cast<const T *>(partial);
+  using T = typename Prec<P>::out;
+  const acc_t *part = reinterpret_cast<const acc_t *>(partial);
   T *out = reinterpret_cast<T *>(traces);
   const int64_t a = blockIdx.x / n_segs;
   const int seg = blockIdx.x % n_segs;
@@ -383,7 +389,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(TrackPtrs tr, AntPtrs an
 
 // ------------------------------------------------------------------ host side
 
-size_t acc_bytes(int precision) { return precision == RT_FP64 ? 8 : 4; }
+size_t acc_bytes(int) { return sizeof(acc_t); }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -496,7 +502,9 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
     (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)tl.lds_bytes);
   const int64_t grid = (int64_t)tl.n_atiles * tl.n_segs * tl.splits;
+  if (p.ev_start) (void)hipEventRecord(p.ev_start, stream);
   fn<<<dim3((unsigned)grid), dim3(tl.block), tl.lds_bytes, stream>>>(g);
+  if (p.ev_stop) (void)hipEventRecord(p.ev_stop, stream);
   MergeFn mf = pick_merge(p.formalism, p.precision);
   mf<<<dim3((unsigned)(p.det.n_antennas * tl.n_segs)), dim3(256), 0, stream>>>(
       g.partial, traces, p.det.n_antennas, p.det.n_bins, tl.splits, tl.seg_len, tl.n_segs);

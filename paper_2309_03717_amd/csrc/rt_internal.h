@@ -23,6 +23,8 @@ struct rt_plan {
   size_t lds_per_cu;      // bytes of LDS per compute unit
   // tiling (0 = automatic)
   int at_user, splits_user, block_user, seg_user;
+  // one-shot profiling events around the next deposit kernel
+  hipEvent_t ev_start, ev_stop;
 };
 
 namespace rt {

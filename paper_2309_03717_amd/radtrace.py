@@ -64,6 +64,7 @@ _lib.rt_plan_get_tiling.argtypes = [_P, C.c_int64] + [C.POINTER(C.c_int)] * 4
 _lib.rt_plan_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_accumulate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
 _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
+_lib.rt_plan_set_timing_events.argtypes = [_P, _P, _P]
 
 
 class RadtraceError(RuntimeError):
@@ -208,6 +209,19 @@ def rt_accumulate(plan: int, tracks: rt_tracks, traces: torch.Tensor, workspace:
     _check(_lib.rt_accumulate(plan, C.byref(tracks), _ptr(traces), _ptr(workspace),
                               workspace.numel() * workspace.element_size(), _stream(stream)),
            "rt_accumulate")
+
+
+def rt_plan_set_timing_events(plan: int, start_event, stop_event) -> None:
+    """start_event / stop_event: torch.cuda.Event (timing enabled) or raw
+    hipEvent_t handles; None clears."""
+    def handle(ev):
+        if ev is None or isinstance(ev, int):
+            return ev
+        if not ev.cuda_event:   # torch creates events lazily: force creation
+            ev.record()
+        return ev.cuda_event
+    _check(_lib.rt_plan_set_timing_events(plan, handle(start_event), handle(stop_event)),
+           "rt_plan_set_timing_events")
 
 
 def rt_propagate(plan: int, tracks: rt_tracks, t_arrival: Optional[torch.Tensor],
