@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--formalisms", default="endpoint,zhs")
     ap.add_argument("--cpu-sample", type=int, default=1 << 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tiling", default=None, help="at,splits,block,seg override")
+    ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -194,14 +194,16 @@ def main():
                                           min(chunks[0].n, 1 << 13))
     per = {}
     for f in formalisms:
-        durs = [s.elapsed_time(e) for s, e in kernel_events[f]]
+        # one event pair spans the deposit launches of all passes of a call
+        passes = -(-chunk // plans[f].tiling(chunk)[4])
+        durs = [s.elapsed_time(e) / passes for s, e in kernel_events[f]]
         n_launch = len(durs)
         avg_ms = sum(durs) / n_launch
         f64, f32 = ops_per_pair(f, ends_in, box_in)
-        pairs_per_launch = pairs_per_formalism * args.steps / n_launch
+        pairs_per_launch = pairs_per_formalism * args.steps / (n_launch * passes)
         achieved = (f64 + f32) * pairs_per_launch / (avg_ms / 1e3)
-        per[f] = {"kernel_ms_avg": avg_ms, "launches": n_launch,
-                  "kernel_ms_total_per_step": sum(durs) / args.steps,
+        per[f] = {"kernel_ms_avg": avg_ms, "launches": n_launch * passes,
+                  "kernel_ms_total_per_step": sum(durs) * passes / args.steps,
                   "pairs_per_s_kernel": pairs_per_launch / (avg_ms / 1e3),
                   "ops_per_pair": {"fp64": round(f64, 3), "fp32": round(f32, 3)},
                   "achieved_tops": achieved / 1e12,

@@ -127,21 +127,33 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
 /* Frees a plan (NULL is accepted). Does not touch device memory. */
 int rt_plan_destroy(rt_plan *plan);
 
-/* Overrides the launch shape; 0 keeps the automatic choice for a field.
- *  antennas_per_block: antennas whose traces one workgroup keeps in LDS (1-4)
- *  track_splits: track ranges merged in fixed order afterwards (>= 1)
+/* Launch shape of the deposit kernels. In rt_plan_set_tiling a zero field
+ * keeps the automatic choice.
+ *  antennas_per_block: antennas whose traces one workgroup keeps in LDS (1-8)
+ *  track_splits: track ranges per pass, merged in fixed order afterwards
  *  block_threads: workgroup size, a multiple of 64 in [64, 1024]
  *  bins_per_segment: bins per LDS trace segment, a multiple of 64 (or
  *                    n_bins); segments split long traces across workgroups
+ *  tracks_per_pass: a call deposits its tracks in consecutive passes of at
+ *                   most this many tracks (a multiple of 64), so that the
+ *                   per-track records of a pass stay resident in the
+ *                   last-level cache while every antenna tile streams them
  * Results do not depend on the tiling beyond floating-point summation
  * order; bins never change. */
-int rt_plan_set_tiling(rt_plan *plan, int antennas_per_block, int track_splits,
-                       int block_threads, int bins_per_segment);
+typedef struct {
+  int32_t antennas_per_block;
+  int32_t track_splits;
+  int32_t block_threads;
+  int32_t bins_per_segment;
+  int64_t tracks_per_pass;
+} rt_tiling;
 
-/* The launch shape the plan would use for n_tracks tracks (host outputs,
- * any may be NULL). */
-int rt_plan_get_tiling(const rt_plan *plan, int64_t n_tracks, int *antennas_per_block,
-                       int *track_splits, int *block_threads, int *bins_per_segment);
+/* Overrides the launch shape (tiling: host, read during the call). */
+int rt_plan_set_tiling(rt_plan *plan, const rt_tiling *tiling);
+
+/* The launch shape the plan uses for a call with n_tracks tracks (out:
+ * host). */
+int rt_plan_get_tiling(const rt_plan *plan, int64_t n_tracks, rt_tiling *out);
 
 /* Device workspace (bytes) rt_accumulate needs for a call with n_tracks
  * tracks. */
@@ -158,7 +170,8 @@ int rt_plan_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes
  *             (beta_perp and R_mid at the segment midpoint), averaged over
  *             every bin it overlaps.
  * workspace: device, >= rt_plan_workspace_bytes(plan, tracks->n) bytes, used
- * as scratch by this call only. tracks->n == 0 is a no-op. Partial traces of
+ * as scratch by this call only. tracks->n == 0 is a no-op; at most 2^31 - 1
+ * tracks per call (RT_E_UNSUPPORTED beyond: stream larger inputs in chunks). Partial traces of
  * track splits are merged in a fixed order (no float atomics in global
  * memory), so a call is repeatable for a fixed tiling up to the order of LDS
  * additions within a workgroup. */

@@ -102,6 +102,7 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
   p->lds_per_block = (size_t)(lds_block > 0 ? lds_block : 65536);
   p->lds_per_cu = (size_t)(lds_cu > 0 ? lds_cu : (int)p->lds_per_block);
   p->at_user = p->splits_user = p->block_user = p->seg_user = 0;
+  p->pass_user = 0;
   p->ev_start = p->ev_stop = nullptr;
   rt::Consts &c = p->c;
   c.inv_c = 1.0 / 299792458.0;
@@ -123,44 +124,42 @@ int rt_plan_destroy(rt_plan *plan) {
   return RT_OK;
 }
 
-int rt_plan_set_tiling(rt_plan *plan, int antennas_per_block, int track_splits, int block_threads,
-                       int bins_per_segment) {
-  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
-  if (antennas_per_block < 0 || antennas_per_block > rt::kMaxTile)
-    return fail(RT_E_INVALID, "antennas_per_block must be in [0, 4]");
-  if (track_splits < 0) return fail(RT_E_INVALID, "track_splits must be >= 0");
-  if (block_threads != 0 && (block_threads < 64 || block_threads > 1024 || block_threads % 64))
+int rt_plan_set_tiling(rt_plan *plan, const rt_tiling *tl) {
+  if (!plan || !tl) return fail(RT_E_INVALID, "plan or tiling is NULL");
+  const int at = tl->antennas_per_block, splits = tl->track_splits;
+  const int block = tl->block_threads, seg_in = tl->bins_per_segment;
+  if (at < 0 || at > rt::kMaxTile) return fail(RT_E_INVALID, "antennas_per_block must be in [0, 8]");
+  if (splits < 0) return fail(RT_E_INVALID, "track_splits must be >= 0");
+  if (block != 0 && (block < 64 || block > 1024 || block % 64))
     return fail(RT_E_INVALID, "block_threads must be a multiple of 64 in [64, 1024]");
-  if (bins_per_segment < 0 ||
-      (bins_per_segment > 0 && bins_per_segment % 64 && bins_per_segment != plan->det.n_bins))
+  if (seg_in < 0 || (seg_in > 0 && seg_in % 64 && seg_in != plan->det.n_bins))
     return fail(RT_E_INVALID, "bins_per_segment must be a multiple of 64 or n_bins");
+  if (tl->tracks_per_pass < 0 || tl->tracks_per_pass % 64)
+    return fail(RT_E_INVALID, "tracks_per_pass must be a non-negative multiple of 64");
   const size_t acc = rt::acc_bytes(plan->precision);
-  int seg = bins_per_segment > 0 ? std::min(bins_per_segment, plan->det.n_bins) : 0;
-  if (seg > 0 && (size_t)seg * 3 * acc * (antennas_per_block > 0 ? antennas_per_block : 1) >
-                     plan->lds_per_block)
+  const int seg = seg_in > 0 ? std::min(seg_in, plan->det.n_bins) : 0;
+  if (seg > 0 && (size_t)seg * 3 * acc * (at > 0 ? at : 1) > plan->lds_per_block)
     return fail(RT_E_UNSUPPORTED, "tile does not fit in LDS");
-  if (antennas_per_block > 0 && seg == 0) {
-    size_t need = (size_t)antennas_per_block * plan->det.n_bins * 3 * acc;
-    if (need > plan->lds_per_block)
-      return fail(RT_E_UNSUPPORTED, "antennas_per_block x n_bins does not fit in LDS; "
-                                    "also set bins_per_segment");
-  }
-  plan->at_user = antennas_per_block;
-  plan->splits_user = track_splits;
-  plan->block_user = block_threads;
-  plan->seg_user = bins_per_segment;
+  if (at > 0 && seg == 0 && (size_t)at * plan->det.n_bins * 3 * acc > plan->lds_per_block)
+    return fail(RT_E_UNSUPPORTED,
+                "antennas_per_block x n_bins does not fit in LDS; also set bins_per_segment");
+  plan->at_user = at;
+  plan->splits_user = splits;
+  plan->block_user = block;
+  plan->seg_user = seg_in;
+  plan->pass_user = tl->tracks_per_pass;
   return RT_OK;
 }
 
-int rt_plan_get_tiling(const rt_plan *plan, int64_t n_tracks, int *antennas_per_block,
-                       int *track_splits, int *block_threads, int *bins_per_segment) {
-  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+int rt_plan_get_tiling(const rt_plan *plan, int64_t n_tracks, rt_tiling *out) {
+  if (!plan || !out) return fail(RT_E_INVALID, "plan or out is NULL");
   if (n_tracks < 0) return fail(RT_E_INVALID, "n_tracks < 0");
   rt::Tiling t = rt::choose_tiling(*plan, n_tracks);
-  if (antennas_per_block) *antennas_per_block = t.at;
-  if (track_splits) *track_splits = t.splits;
-  if (block_threads) *block_threads = t.block;
-  if (bins_per_segment) *bins_per_segment = t.seg_len;
+  out->antennas_per_block = t.at;
+  out->track_splits = t.splits;
+  out->block_threads = t.block;
+  out->bins_per_segment = t.seg_len;
+  out->tracks_per_pass = t.pass_tracks;
   return RT_OK;
 }
 
@@ -178,6 +177,8 @@ int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *wo
   if (s != RT_OK) return s;
   if (tracks->n == 0) return RT_OK;
   if (!traces) return fail(RT_E_INVALID, "traces is NULL");
+  if (tracks->n >= ((int64_t)1 << 31))
+    return fail(RT_E_UNSUPPORTED, "at most 2^31 - 1 tracks per call; stream larger inputs in chunks");
   size_t need = rt::workspace_bytes(*plan, tracks->n);
   if (!workspace || workspace_bytes < need)
     return fail(RT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +

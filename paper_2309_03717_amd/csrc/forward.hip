@@ -1,25 +1,36 @@
-// forward.hip -- the track x antenna loop on gfx950: per-track media values,
-// LDS-resident antenna trace tiles fed by streamed tracks, fixed-order merge
-// of track-split partials (with the ZHS prefix scan), and the propagator
-// alone.
+// forward.hip -- the track x antenna loop on gfx950: a per-track record
+// written once per call, LDS-resident antenna trace tiles fed by streamed
+// track records, a fixed-order merge of track-split partials (with the ZHS
+// prefix scan), and the propagator alone.
 //
 // Work decomposition (the analogue of §4's "bunch of antennas" per task): a
 // workgroup owns a tile of up to kMaxTile antennas x one segment of bins in
 // LDS and streams one range ("split") of the tracks past it; each lane takes
-// one track and loops over the tile's antennas, so the track loads are
-// coalesced structure-of-arrays reads and each deposit is an LDS atomic add.
-// The tile is then written once to a partial buffer [split][M][B][3] and a
-// second kernel sums the splits in index order into the caller's traces, so
-// no float atomic ever touches global memory and a fixed tiling gives the
-// same merge order on every call.
+// one track and loops over the tile's antennas, so track loads are coalesced
+// and each deposit is an LDS atomic add. The tile is then written once to a
+// partial buffer [split][M][B][3] and a second kernel sums the splits in index
+// order into the caller's traces, so no float atomic ever touches global
+// memory and a fixed tiling gives the same merge order on every call.
+//
+// Track records are loaded one wave block ahead (register double-buffering)
+// so that the L2 latency of the next record overlaps the arithmetic of the
+// current one; with one 4096-bin FP64 trace per workgroup every record is read
+// once per antenna, which makes this loop sensitive to load latency.
+//
+// Precision. Accumulation in LDS and in the split partials is double in both
+// modes: gfx950 executes LDS double-precision atomic adds (ds_add_f64) at close
+// to the rate of plain LDS stores, while single-precision ones (ds_add_f32)
+// are several times slower on this workload. In RT_MIXED the arrival time and
+// bin are computed exactly as in RT_FP64; the amplitude uses the hardware
+// reciprocal / reciprocal square root refined by one Newton step (about 28
+// correct bits) instead of correctly rounded division, in double precision,
+// because unpacked single-precision arithmetic runs at the double-precision
+// rate on this chip and would only add conversions. Tracks carry beta and qw
+// as float and the traces are float in RT_MIXED.
 #include "rt_internal.h"
 
 namespace rt {
 
-// Accumulation in LDS and in the split partials is double precision in both
-// modes: gfx950 executes LDS double-precision atomic adds (ds_add_f64) at
-// close to the rate of plain LDS stores, while single-precision ones
-// (ds_add_f32) are several times slower on this workload.
 using acc_t = double;
 
 template <int P>
@@ -35,34 +46,93 @@ struct Prec<1> {  // RT_MIXED
   using out = float;
 };
 
-struct DepositArgs {
+// ------------------------------------------------------------------ track record
+
+// Per-track record, kRec doubles per track, blocked by waves of 64 tracks:
+// field f of track 64 b + l is rec[(b * kRec + f) * 64 + l], so a wave reads
+// each field as one contiguous 512-byte run from a single base address.
+constexpr int kRec = 16;
+enum : int {
+  R_X0, R_Y0, R_Z0, R_T0,  // start point and time
+  R_X1, R_Y1, R_Z1, R_T1,  // end point and time
+  R_NE0, R_NE1,            // path index of each end to the height of antenna 0
+  R_E0, R_E1,              // height factors exp(-(z / h)) of the two ends
+  R_AMP,                   // Endpoint: k qw / dt;  ZHS: k qw (t1 - t0) / dt
+  R_BX, R_BY, R_BZ         // velocity (units of c)
+};
+
+struct PrepArgs {
   TrackPtrs tr;
   AntPtrs an;
   Consts c;
-  const double *e0, *e1;   // per-track height factors (exponential medium)
-  void *partial;           // [splits][M][n_bins][3]
-  int64_t per_split;       // tracks per split
-  int n_atiles, n_segs, seg_len;
+  double *rec;
+  int64_t n_blocks;   // wave blocks (tracks rounded up to 64)
 };
 
-// ------------------------------------------------------------------ prepare
-
-// Height factors exp(-(z / h)) of both track ends, once per call instead of
-// once per workgroup.
-__global__ void __launch_bounds__(256) prepare_kernel(TrackPtrs tr, Consts c, double *e0,
-                                                      double *e1) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tr.n;
+// One thread per (padded) track. A track with any non-finite field, and the
+// padding past the last track, get NaN times so that no antenna window
+// accepts them.
+template <int F, int P>
+__global__ void __launch_bounds__(256) prepare_kernel(PrepArgs g) {
+  using In = typename Prec<P>::in;
+  const Consts &c = g.c;
+  const double z_ref = g.an.z[0];
+  const double e_ref = c.medium == 1 ? height_factor(z_ref, c) : 0.0;
+  const int64_t n_pad = g.n_blocks * 64;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
        i += (int64_t)gridDim.x * blockDim.x) {
-    e0[i] = height_factor(tr.z0[i], c);
-    e1[i] = height_factor(tr.z1[i], c);
+    double v[kRec];
+    bool ok = i < g.tr.n;
+    if (ok) {
+      v[R_X0] = g.tr.x0[i];
+      v[R_Y0] = g.tr.y0[i];
+      v[R_Z0] = g.tr.z0[i];
+      v[R_T0] = g.tr.t0[i];
+      v[R_X1] = g.tr.x1[i];
+      v[R_Y1] = g.tr.y1[i];
+      v[R_Z1] = g.tr.z1[i];
+      v[R_T1] = g.tr.t1[i];
+      v[R_BX] = (double)((const In *)g.tr.bx)[i];
+      v[R_BY] = (double)((const In *)g.tr.by)[i];
+      v[R_BZ] = (double)((const In *)g.tr.bz)[i];
+      double qw = (double)((const In *)g.tr.qw)[i];
+      v[R_AMP] = F == 0 ? c.k * qw * c.inv_dt : c.k * qw * (v[R_T1] - v[R_T0]) * c.inv_dt;
+      ok = isfinite(qw);
+      for (int f = R_X0; f <= R_T1; ++f) ok = ok && isfinite(v[f]);
+      for (int f = R_BX; f <= R_BZ; ++f) ok = ok && isfinite(v[f]);
+    }
+    if (!ok) {
+      for (int f = 0; f < kRec; ++f) v[f] = 0.0;
+      v[R_T0] = v[R_T1] = __builtin_nan("");
+    }
+    v[R_E0] = v[R_E1] = 0.0;
+    v[R_NE0] = v[R_NE1] = c.n_uniform;
+    if (c.medium == 1) {
+      v[R_E0] = height_factor(v[R_Z0], c);
+      v[R_E1] = height_factor(v[R_Z1], c);
+      v[R_NE0] = path_index(v[R_Z0], z_ref, v[R_E0], e_ref, c);
+      v[R_NE1] = path_index(v[R_Z1], z_ref, v[R_E1], e_ref, c);
+    }
+    double *out = g.rec + ((i >> 6) * kRec) * 64 + (i & 63);
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) out[f * 64] = v[f];
   }
 }
 
 // ------------------------------------------------------------------ deposits
 
-template <typename T>
-__device__ __forceinline__ void put3(T *row, int j, T vx, T vy, T vz) {
-  T *p = row + 3 * j;
+struct DepositArgs {
+  AntPtrs an;
+  Consts c;
+  const double *rec;       // per-track records of this pass (first wave block)
+  void *partial;           // [splits][M][n_bins][3] doubles
+  int64_t n_blocks;        // wave blocks of tracks in this pass
+  int64_t blocks_per_split;
+  int n_atiles, n_segs, seg_len;
+};
+
+__device__ __forceinline__ void put3(acc_t *row, int j, double vx, double vy, double vz) {
+  acc_t *p = row + 3 * j;
   lds_add(p, vx);
   lds_add(p + 1, vy);
   lds_add(p + 2, vz);
@@ -71,43 +141,49 @@ __device__ __forceinline__ void put3(T *row, int j, T vx, T vy, T vz) {
 // ZHS difference deposit at absolute bin j of a segment [lo, hi): bins before
 // the segment fold into its first bin (the segment's prefix scan starts
 // there), bins at or after its end are dropped.
-template <typename T>
-__device__ __forceinline__ void put3_clamped(T *row, int j, int lo, int hi, T vx, T vy, T vz) {
+__device__ __forceinline__ void put3_clamped(acc_t *row, int j, int lo, int hi, double vx,
+                                             double vy, double vz) {
   if (j < lo) j = lo;
   if (j < hi) put3(row, j - lo, vx, vy, vz);
 }
 
+// 1/x and 1/sqrt(x) from the hardware estimate plus one Newton step.
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double fast_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = fma(-0.5 * x * y, y, 1.5);
+  return y * h;
+}
+
 // Endpoint impulse of one track end at one antenna: s k qw [r x (r x beta)] /
-// ((1 - n_src beta.r) R dt), written as sc * (d (beta.d) / R^2 - beta) / num
+// ((1 - n_src beta.r) R dt), evaluated as sc (d (beta.d) / R^2 - beta) / num
 // with num = R - n_src (beta.d) = (1 - n_src beta.r) R and sc = s k qw / dt.
 template <int P>
-__device__ __forceinline__ void endpoint_end(acc_t *row, int lo, int hi, double sc,
-                                             double px, double py, double pz, double tp,
-                                             double ax, double ay, double az, double tau,
-                                             double neff, double nsrc, double bx, double by,
-                                             double bz, const Consts &c) {
-  using T = acc_t;
-  double dx, dy, dz, r;
-  double u = arrival_bins(px, py, pz, tp, ax, ay, az, tau, neff, c, dx, dy, dz, r);
-  if (!(u >= 0.0 && u < c.nbins_d)) return;
-  int kb = (int)u;
-  if (kb < lo || kb >= hi) return;
-  double bd = (bx * dx + by * dy) + bz * dz;
-  double num = r - nsrc * bd;
+__device__ __forceinline__ void endpoint_end(acc_t *row, int lo, double lo_d, double hi_d,
+                                             double sc, double px, double py, double pz,
+                                             double tp, double ax, double ay, double az,
+                                             double tau, double neff, double nsrc, double bx,
+                                             double by, double bz, const Consts &c) {
+  double dx, dy, dz, r, r2;
+  double u = arrival_bins(px, py, pz, tp, ax, ay, az, tau, neff, c, dx, dy, dz, r, r2);
+  if (!(u >= lo_d && u < hi_d)) return;   // outside this segment of the window (or NaN)
+  const int j = (int)u - lo;
+  double bd = fma(bx, dx, fma(by, dy, bz * dz));
+  double num = fma(-nsrc, bd, r);
   if (num == 0.0) return;   // on the Cherenkov cone, or R = 0
+  double q, a;
   if (P == 0) {
-    double q = bd / (r * r);
-    double a = sc / num;
-    put3<T>(row, kb - lo, (T)((dx * q - bx) * a), (T)((dy * q - by) * a), (T)((dz * q - bz) * a));
+    q = bd / r2;
+    a = sc / num;
   } else {
-    float fr = (float)r;
-    float q = (float)bd * __builtin_amdgcn_rcpf(fr * fr);
-    float a = (float)sc * __builtin_amdgcn_rcpf((float)num);
-    float vx = fmaf((float)dx, q, -(float)bx);
-    float vy = fmaf((float)dy, q, -(float)by);
-    float vz = fmaf((float)dz, q, -(float)bz);
-    put3<T>(row, kb - lo, (T)(vx * a), (T)(vy * a), (T)(vz * a));
+    q = bd * fast_rcp(r2);
+    a = sc * fast_rcp(num);
   }
+  put3(row, j, fma(dx, q, -bx) * a, fma(dy, q, -by) * a, fma(dz, q, -bz) * a);
 }
 
 // ZHS box of one segment at one antenna. us, ue: arrival of start and end in
@@ -116,77 +192,106 @@ __device__ __forceinline__ void endpoint_end(acc_t *row, int lo, int hi, double 
 // deposited as at most four differences whose prefix sum is that average,
 // each bounded by |Ibar|.
 template <int P>
-__device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double us, double ue,
-                                        double mx, double my, double mz, double ax, double ay,
-                                        double az, double cz, double bx, double by, double bz) {
-  // T: arithmetic type of the amplitudes (deposits are widened to acc_t)
-  using T = typename Prec<P>::out;
+__device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double lo_d, double hi_d,
+                                        double us, double ue, double mx, double my, double mz,
+                                        double ax, double ay, double az, double cz, double bx,
+                                        double by, double bz) {
   double ulo = us < ue ? us : ue;
   double uhi = us < ue ? ue : us;
-  if (!(uhi >= (double)lo && ulo < (double)hi)) return;   // outside this segment (or NaN)
+  if (!(uhi >= lo_d && ulo < hi_d)) return;   // outside this segment (or NaN)
   // midpoint geometry: Ibar = cz * beta_perp / R_m, cz = k qw (t1 - t0) / dt
-  T ix, iy, iz;
-  if (P == 0) {
-    double dx = ax - mx, dy = ay - my, dz = az - mz;
-    double r2 = (dx * dx + dy * dy) + dz * dz;
-    if (r2 == 0.0) return;
-    double rm = sqrt(r2);
-    double q = ((bx * dx + by * dy) + bz * dz) / r2;
-    double s = cz / rm;
-    ix = (bx - dx * q) * s;
-    iy = (by - dy * q) * s;
-    iz = (bz - dz * q) * s;
-  } else {
-    float dx = (float)(ax - mx), dy = (float)(ay - my), dz = (float)(az - mz);
-    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    if (r2 == 0.0f) return;
-    float rinv = __builtin_amdgcn_rsqf(r2);
-    float fbx = (float)bx, fby = (float)by, fbz = (float)bz;
-    float q = fmaf(fbx, dx, fmaf(fby, dy, fbz * dz)) * (rinv * rinv);
-    float s = (float)cz * rinv;
-    ix = fmaf(-dx, q, fbx) * s;
-    iy = fmaf(-dy, q, fby) * s;
-    iz = fmaf(-dz, q, fbz) * s;
-  }
+  double dx = ax - mx, dy = ay - my, dz = az - mz;
+  double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+  if (r2 == 0.0) return;
+  double rinv = P == 0 ? 1.0 / sqrt(r2) : fast_rsq(r2);
+  double q = fma(bx, dx, fma(by, dy, bz * dz)) * (rinv * rinv);
+  double s = cz * rinv;
+  double ix = fma(-dx, q, bx) * s, iy = fma(-dy, q, by) * s, iz = fma(-dz, q, bz) * s;
   double kl = floor(ulo), kh = floor(uhi);
   if (kl == kh) {   // whole box inside one bin of this segment
     int j = (int)kl;
-    put3<acc_t>(row, j - lo, ix, iy, iz);
-    if (j + 1 < hi) put3<acc_t>(row, j + 1 - lo, -ix, -iy, -iz);
+    put3(row, j - lo, ix, iy, iz);
+    if (j + 1 < hi) put3(row, j + 1 - lo, -ix, -iy, -iz);
     return;
   }
   double w = uhi - ulo;
+  double wi = P == 0 ? 1.0 / w : fast_rcp(w);
   double flo = (kl + 1.0) - ulo;   // share of bin kl, in (0, 1]
   double fhi = uhi - kh;           // share of bin kh, in [0, 1)
   // clamp far-out indices before the int conversion (all fold or drop alike)
-  int jl = (int)fmax(kl, (double)lo - 2.0);
-  int jh = (int)fmin(kh, (double)hi);
+  int jl = (int)fmax(kl, lo_d - 2.0);
+  int jh = (int)fmin(kh, hi_d);
   if (kh == kl + 1.0) {
-    T fa, fb;
-    if (P == 0) {
-      fa = (T)(flo / w);
-      fb = (T)(fhi / w);
-    } else {
-      float wi = __builtin_amdgcn_rcpf((float)w);
-      fa = (T)((float)flo * wi);
-      fb = (T)((float)fhi * wi);
-    }
-    T axv = ix * fa, ayv = iy * fa, azv = iz * fa;
-    T bxv = ix * fb, byv = iy * fb, bzv = iz * fb;
-    put3_clamped<acc_t>(row, jl, lo, hi, axv, ayv, azv);
-    put3_clamped<acc_t>(row, jl + 1, lo, hi, bxv - axv, byv - ayv, bzv - azv);
-    put3_clamped<acc_t>(row, jl + 2, lo, hi, -bxv, -byv, -bzv);
+    double fa = flo * wi, fb = fhi * wi;
+    double ax_ = ix * fa, ay_ = iy * fa, az_ = iz * fa;
+    double bx_ = ix * fb, by_ = iy * fb, bz_ = iz * fb;
+    put3_clamped(row, jl, lo, hi, ax_, ay_, az_);
+    put3_clamped(row, jl + 1, lo, hi, bx_ - ax_, by_ - ay_, bz_ - az_);
+    put3_clamped(row, jl + 2, lo, hi, -bx_, -by_, -bz_);
   } else {
-    T wi;
-    if (P == 0) wi = (T)(1.0 / w);
-    else wi = (T)__builtin_amdgcn_rcpf((float)w);
-    T hx = ix * wi, hy = iy * wi, hz = iz * wi;
-    T fl = (T)flo, fh = (T)fhi;
-    T gl = (T)1 - fl, gh = (T)1 - fh;
-    put3_clamped<acc_t>(row, jl, lo, hi, hx * fl, hy * fl, hz * fl);
-    put3_clamped<acc_t>(row, jl + 1, lo, hi, hx * gl, hy * gl, hz * gl);
-    put3_clamped<acc_t>(row, jh, lo, hi, -hx * gh, -hy * gh, -hz * gh);
-    put3_clamped<acc_t>(row, jh + 1, lo, hi, -hx * fh, -hy * fh, -hz * fh);
+    double hx = ix * wi, hy = iy * wi, hz = iz * wi;
+    double gl = 1.0 - flo, gh = 1.0 - fhi;
+    put3_clamped(row, jl, lo, hi, hx * flo, hy * flo, hz * flo);
+    put3_clamped(row, jl + 1, lo, hi, hx * gl, hy * gl, hz * gl);
+    put3_clamped(row, jh, lo, hi, -hx * gh, -hy * gh, -hz * gh);
+    put3_clamped(row, jh + 1, lo, hi, -hx * fhi, -hy * fhi, -hz * fhi);
+  }
+}
+
+// The tile antennas of one workgroup (uniform values).
+template <int AT>
+struct Tile {
+  double ax[AT], ay[AT], az[AT], tau[AT], ea[AT];
+  bool at_ref[AT];   // at the height of antenna 0: the record's path index applies
+};
+
+// All deposits of one track record (this lane's track) into the tile
+// antennas selected by mask.
+template <int F, int P, int MED, int AT>
+__device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, const Tile<AT> &t,
+                                               acc_t *tile, int row_len, int lo, int hi,
+                                               double lo_d, double hi_d, const Consts &c) {
+  const double x0 = v[R_X0], y0 = v[R_Y0], z0 = v[R_Z0], t0 = v[R_T0];
+  const double x1 = v[R_X1], y1 = v[R_Y1], z1 = v[R_Z1], t1 = v[R_T1];
+  const double amp = v[R_AMP], bx = v[R_BX], by = v[R_BY], bz = v[R_BZ];
+  const double e0 = MED == 1 ? v[R_E0] : 0.0, e1 = MED == 1 ? v[R_E1] : 0.0;
+  if (F == 0) {
+    const double ns0 = MED == 1 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
+    const double ns1 = MED == 1 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
+#pragma unroll
+    for (int a = 0; a < AT; ++a) {
+      if ((mask >> a) & 1) {
+        double ne0 = v[R_NE0], ne1 = v[R_NE1];
+        if (MED == 1 && !t.at_ref[a]) {
+          ne0 = path_index(z0, t.az[a], e0, t.ea[a], c);
+          ne1 = path_index(z1, t.az[a], e1, t.ea[a], c);
+        }
+        acc_t *row = tile + a * row_len;
+        endpoint_end<P>(row, lo, lo_d, hi_d, amp, x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a],
+                        t.tau[a], ne0, ns0, bx, by, bz, c);
+        endpoint_end<P>(row, lo, lo_d, hi_d, -amp, x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a],
+                        t.tau[a], ne1, ns1, bx, by, bz, c);
+      }
+    }
+  } else {
+    const double mx = (x0 + x1) * 0.5, my = (y0 + y1) * 0.5, mz = (z0 + z1) * 0.5;
+#pragma unroll
+    for (int a = 0; a < AT; ++a) {
+      if ((mask >> a) & 1) {
+        double ne0 = v[R_NE0], ne1 = v[R_NE1];
+        if (MED == 1 && !t.at_ref[a]) {
+          ne0 = path_index(z0, t.az[a], e0, t.ea[a], c);
+          ne1 = path_index(z1, t.az[a], e1, t.ea[a], c);
+        }
+        double dx, dy, dz, rr, r2;
+        double us = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c, dx,
+                                 dy, dz, rr, r2);
+        double ue = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c, dx,
+                                 dy, dz, rr, r2);
+        zhs_box<P>(tile + a * row_len, lo, hi, lo_d, hi_d, us, ue, mx, my, mz, t.ax[a], t.ay[a],
+                   t.az[a], amp, bx, by, bz);
+      }
+    }
   }
 }
 
@@ -194,10 +299,8 @@ __device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double us, d
 // AT: antennas per tile.
 template <int F, int P, int MED, int AT>
 __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
-  using T = acc_t;
-  using In = typename Prec<P>::in;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  T *tile = reinterpret_cast<T *>(smem);
+  acc_t *tile = reinterpret_cast<acc_t *>(smem);
 
   const int v = xcd_major(blockIdx.x, gridDim.x);
   const int n_tiles = g.n_atiles * g.n_segs;
@@ -209,100 +312,55 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int n_ant = (int)min((int64_t)AT, g.an.m - a_begin);
   const int lo = seg * g.seg_len;
   const int hi = min(lo + g.seg_len, g.c.n_bins);
+  const double lo_d = (double)lo, hi_d = (double)hi;
   const int row_len = (hi - lo) * 3;
 
-  for (int i = threadIdx.x; i < AT * row_len; i += blockDim.x) tile[i] = T(0);
+  for (int i = threadIdx.x; i < AT * row_len; i += blockDim.x) tile[i] = 0.0;
 
-  double ax[AT], ay[AT], az[AT], tau[AT], ea[AT];
+  const double z_ref = g.an.z[0];
+  Tile<AT> t;
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
     int64_t ai = a_begin + (a < n_ant ? a : 0);
-    ax[a] = g.an.x[ai];
-    ay[a] = g.an.y[ai];
-    az[a] = g.an.z[ai];
-    tau[a] = g.an.t_start[ai];
-    ea[a] = MED == 1 ? height_factor(az[a], g.c) : 0.0;
-  }
-  // all tile antennas at one height: one path index per track end
-  bool flat = true;
-#pragma unroll
-  for (int a = 1; a < AT; ++a) flat = flat && (a >= n_ant || az[a] == az[0]);
-  __syncthreads();
-
-  const int64_t i0 = (int64_t)split * g.per_split;
-  const int64_t i1 = min(g.tr.n, i0 + g.per_split);
-  const In *pbx = (const In *)g.tr.bx, *pby = (const In *)g.tr.by, *pbz = (const In *)g.tr.bz,
-           *pqw = (const In *)g.tr.qw;
-
-  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const double x0 = g.tr.x0[i], y0 = g.tr.y0[i], z0 = g.tr.z0[i], t0 = g.tr.t0[i];
-    const double x1 = g.tr.x1[i], y1 = g.tr.y1[i], z1 = g.tr.z1[i], t1 = g.tr.t1[i];
-    const double bx = (double)pbx[i], by = (double)pby[i], bz = (double)pbz[i];
-    const double qw = (double)pqw[i];
-    // a track with any non-finite field contributes nothing (the sum is
-    // non-finite iff some field is, barring overflow of finite fields)
-    if (!isfinite(((((x0 + y0) + (z0 + t0)) + ((x1 + y1) + (z1 + t1))) + ((bx + by) + (bz + qw)))))
-      continue;
-    double e0 = 0.0, e1 = 0.0;
-    if (MED == 1) {
-      e0 = g.e0[i];
-      e1 = g.e1[i];
-    }
-    double nf0 = g.c.n_uniform, nf1 = g.c.n_uniform;
-    if (MED == 1 && flat) {
-      nf0 = path_index(z0, az[0], e0, ea[0], g.c);
-      nf1 = path_index(z1, az[0], e1, ea[0], g.c);
-    }
-    if (F == 0) {
-      double ns0 = g.c.n_uniform, ns1 = g.c.n_uniform;
-      if (MED == 1) {
-        ns0 = 1.0 + g.c.n0m1 * e0;
-        ns1 = 1.0 + g.c.n0m1 * e1;
-      }
-      const double sc = g.c.k * qw * g.c.inv_dt;
-#pragma unroll
-      for (int a = 0; a < AT; ++a) {
-        if (a < n_ant) {
-          double ne0 = nf0, ne1 = nf1;
-          if (MED == 1 && !flat) {
-            ne0 = path_index(z0, az[a], e0, ea[a], g.c);
-            ne1 = path_index(z1, az[a], e1, ea[a], g.c);
-          }
-          T *row = tile + a * row_len;
-          endpoint_end<P>(row, lo, hi, sc, x0, y0, z0, t0, ax[a], ay[a], az[a], tau[a], ne0, ns0,
-                          bx, by, bz, g.c);
-          endpoint_end<P>(row, lo, hi, -sc, x1, y1, z1, t1, ax[a], ay[a], az[a], tau[a], ne1, ns1,
-                          bx, by, bz, g.c);
-        }
-      }
-    } else {
-      const double mx = (x0 + x1) * 0.5, my = (y0 + y1) * 0.5, mz = (z0 + z1) * 0.5;
-      const double cz = g.c.k * qw * (t1 - t0) * g.c.inv_dt;
-#pragma unroll
-      for (int a = 0; a < AT; ++a) {
-        if (a < n_ant) {
-          double ne0 = nf0, ne1 = nf1;
-          if (MED == 1 && !flat) {
-            ne0 = path_index(z0, az[a], e0, ea[a], g.c);
-            ne1 = path_index(z1, az[a], e1, ea[a], g.c);
-          }
-          double dx, dy, dz, r;
-          double us = arrival_bins(x0, y0, z0, t0, ax[a], ay[a], az[a], tau[a], ne0, g.c, dx, dy,
-                                   dz, r);
-          double ue = arrival_bins(x1, y1, z1, t1, ax[a], ay[a], az[a], tau[a], ne1, g.c, dx, dy,
-                                   dz, r);
-          zhs_box<P>(tile + a * row_len, lo, hi, us, ue, mx, my, mz, ax[a], ay[a], az[a], cz, bx,
-                     by, bz);
-        }
-      }
-    }
+    t.ax[a] = g.an.x[ai];
+    t.ay[a] = g.an.y[ai];
+    t.az[a] = g.an.z[ai];
+    t.tau[a] = g.an.t_start[ai];
+    t.ea[a] = MED == 1 ? height_factor(t.az[a], g.c) : 0.0;
+    t.at_ref[a] = t.az[a] == z_ref;
   }
   __syncthreads();
 
-  T *dst = reinterpret_cast<T *>(g.partial);
+  const int lane = threadIdx.x & 63;
+  const uint64_t mask = (1ull << n_ant) - 1;
+  const int64_t waves = blockDim.x >> 6;
+  const int64_t b_first = (int64_t)split * g.blocks_per_split + (threadIdx.x >> 6);
+  const int64_t b_end = min(g.n_blocks, (int64_t)(split + 1) * g.blocks_per_split);
+  // each wave walks its wave blocks; the next record is loaded before the
+  // current one is processed
+  double nx[kRec];
+  if (b_first < b_end) {
+    const double *r = g.rec + b_first * (kRec * 64) + lane;
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) nx[f] = r[f * 64];
+  }
+  for (int64_t blk = b_first; blk < b_end; blk += waves) {
+    double rv[kRec];
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
+    if (blk + waves < b_end) {
+      const double *r = g.rec + (blk + waves) * (kRec * 64) + lane;
+#pragma unroll
+      for (int f = 0; f < kRec; ++f) nx[f] = r[f * 64];
+    }
+    deposit_record<F, P, MED, AT>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, g.c);
+  }
+  __syncthreads();
+
+  acc_t *dst = reinterpret_cast<acc_t *>(g.partial);
   for (int a = 0; a < n_ant; ++a) {
-    T *out = dst + (((size_t)split * g.an.m + (size_t)(a_begin + a)) * g.c.n_bins + lo) * 3;
-    const T *src = tile + a * row_len;
+    acc_t *out = dst + (((size_t)split * g.an.m + (size_t)(a_begin + a)) * g.c.n_bins + lo) * 3;
+    const acc_t *src = tile + a * row_len;
     for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = src[i];
   }
 }
@@ -328,7 +386,7 @@ __global__ void __launch_bounds__(256) merge_kernel(const void *partial, void *t
   if (F == 0) {
     for (int i = threadIdx.x; i < nb * 3; i += blockDim.x) {
       double s = 0.0;
-      for (int sp = 0; sp < splits; ++sp) s += (double)part[sp * plane + base + i];
+      for (int sp = 0; sp < splits; ++sp) s += part[sp * plane + base + i];
       out[base + i] = (T)((double)out[base + i] + s);
     }
     return;
@@ -339,7 +397,7 @@ __global__ void __launch_bounds__(256) merge_kernel(const void *partial, void *t
   double run[3] = {0.0, 0.0, 0.0};
   for (int b = b0; b < b1; ++b)
     for (int c = 0; c < 3; ++c)
-      for (int sp = 0; sp < splits; ++sp) run[c] += (double)part[sp * plane + base + 3 * b + c];
+      for (int sp = 0; sp < splits; ++sp) run[c] += part[sp * plane + base + 3 * b + c];
   for (int c = 0; c < 3; ++c) carry[threadIdx.x][c] = run[c];
   __syncthreads();
   if (threadIdx.x < 3) {
@@ -355,7 +413,7 @@ __global__ void __launch_bounds__(256) merge_kernel(const void *partial, void *t
   for (int b = b0; b < b1; ++b)
     for (int c = 0; c < 3; ++c) {
       double d = 0.0;
-      for (int sp = 0; sp < splits; ++sp) d += (double)part[sp * plane + base + 3 * b + c];
+      for (int sp = 0; sp < splits; ++sp) d += part[sp * plane + base + 3 * b + c];
       run[c] += d;
       size_t o = base + 3 * b + c;
       out[o] = (T)((double)out[o] + run[c]);
@@ -393,8 +451,11 @@ size_t acc_bytes(int) { return sizeof(acc_t); }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t prep_bytes(const rt_plan &p, int64_t n) {
-  return p.med.kind == RT_EXPONENTIAL ? align256((size_t)n * 2 * sizeof(double)) : 0;
+static int64_t wave_blocks(int64_t n) { return (n + 63) / 64; }
+
+// Workspace: [records][partials]
+size_t prep_bytes(const rt_plan &, int64_t n) {
+  return align256((size_t)wave_blocks(n) * kRec * 64 * sizeof(double));
 }
 
 Tiling choose_tiling(const rt_plan &p, int64_t n) {
@@ -416,22 +477,26 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
   t.at = at;
   t.n_atiles = (int)((M + at - 1) / at);
   t.lds_bytes = (size_t)at * seg * 3 * acc;
-  t.block = p.block_user > 0 ? p.block_user : 1024;
+  t.block = p.block_user > 0 ? p.block_user : 512;
+  t.pass_tracks = p.pass_user > 0 ? p.pass_user : kDefaultPass;
   const int64_t n_tiles = (int64_t)t.n_atiles * t.n_segs;
+  const int64_t nb = std::max<int64_t>(1, wave_blocks(std::min(n, t.pass_tracks)));
   int64_t splits;
   if (p.splits_user > 0) {
     splits = p.splits_user;
   } else {
-    // aim for two rounds of workgroups over the chip, each split >= 2 blocks of tracks
+    // aim for two rounds of workgroups over the chip, each split >= 4 passes
+    // of the workgroup over its tracks
     int64_t resident = (int64_t)p.num_cus * (int64_t)std::max<size_t>(1, p.lds_per_cu / t.lds_bytes);
     splits = (2 * resident + n_tiles - 1) / n_tiles;
-    int64_t cap = std::max<int64_t>(1, n / (2 * t.block));
+    int64_t cap = std::max<int64_t>(1, nb / (4 * (t.block / 64)));
     if (splits > cap) splits = cap;
     if (splits < 1) splits = 1;
   }
-  if (n > 0 && splits > n) splits = n;
-  t.per_split = n > 0 ? (n + splits - 1) / splits : 1;
-  t.splits = n > 0 ? (int)((n + t.per_split - 1) / t.per_split) : 1;
+  if (splits > nb) splits = nb;
+  t.blocks_per_split = (nb + splits - 1) / splits;
+  t.splits = (int)((nb + t.blocks_per_split - 1) / t.blocks_per_split);
+  t.per_split = t.blocks_per_split * 64;
   return t;
 }
 
@@ -448,6 +513,7 @@ TrackPtrs track_ptrs(const rt_tracks &t) {
 AntPtrs ant_ptrs(const rt_detector &d) { return AntPtrs{d.x, d.y, d.z, d.t_start, d.n_antennas}; }
 
 using DepositFn = void (*)(DepositArgs);
+using PrepFn = void (*)(PrepArgs);
 
 template <int F, int P, int MED>
 static DepositFn pick_at(int at) {
@@ -455,7 +521,11 @@ static DepositFn pick_at(int at) {
     case 1: return deposit_kernel<F, P, MED, 1>;
     case 2: return deposit_kernel<F, P, MED, 2>;
     case 3: return deposit_kernel<F, P, MED, 3>;
-    default: return deposit_kernel<F, P, MED, 4>;
+    case 4: return deposit_kernel<F, P, MED, 4>;
+    case 5: return deposit_kernel<F, P, MED, 5>;
+    case 6: return deposit_kernel<F, P, MED, 6>;
+    case 7: return deposit_kernel<F, P, MED, 7>;
+    default: return deposit_kernel<F, P, MED, 8>;
   }
 }
 
@@ -466,6 +536,11 @@ static DepositFn pick_deposit(int f, int prec, int med, int at) {
   }
   if (prec == RT_FP64) return med ? pick_at<1, 0, 1>(at) : pick_at<1, 0, 0>(at);
   return med ? pick_at<1, 1, 1>(at) : pick_at<1, 1, 0>(at);
+}
+
+static PrepFn pick_prep(int f, int prec) {
+  if (f == RT_ENDPOINT) return prec == RT_FP64 ? prepare_kernel<0, 0> : prepare_kernel<0, 1>;
+  return prec == RT_FP64 ? prepare_kernel<1, 0> : prepare_kernel<1, 1>;
 }
 
 using MergeFn = void (*)(const void *, void *, int64_t, int, int, int, int);
@@ -479,35 +554,42 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
                           hipStream_t stream) {
   const Tiling tl = choose_tiling(p, t.n);
   char *ws = reinterpret_cast<char *>(workspace);
-  DepositArgs g;
-  g.tr = track_ptrs(t);
-  g.an = ant_ptrs(p.det);
-  g.c = p.c;
-  g.e0 = g.e1 = nullptr;
-  const int med = p.med.kind == RT_EXPONENTIAL ? 1 : 0;
-  if (med) {
-    double *e = reinterpret_cast<double *>(ws);
-    g.e0 = e;
-    g.e1 = e + t.n;
-    int blocks = (int)std::min<int64_t>((t.n + 255) / 256, 65536);
-    prepare_kernel<<<blocks, 256, 0, stream>>>(g.tr, p.c, e, e + t.n);
+  PrepArgs pa;
+  pa.tr = track_ptrs(t);
+  pa.an = ant_ptrs(p.det);
+  pa.c = p.c;
+  pa.rec = reinterpret_cast<double *>(ws);
+  pa.n_blocks = wave_blocks(t.n);
+  {
+    int blocks = (int)std::min<int64_t>((pa.n_blocks * 64 + 255) / 256, 65536);
+    pick_prep(p.formalism, p.precision)<<<blocks, 256, 0, stream>>>(pa);
   }
+  DepositArgs g;
+  g.an = pa.an;
+  g.c = p.c;
   g.partial = ws + prep_bytes(p, t.n);
-  g.per_split = tl.per_split;
+  g.blocks_per_split = tl.blocks_per_split;
   g.n_atiles = tl.n_atiles;
   g.n_segs = tl.n_segs;
   g.seg_len = tl.seg_len;
+  const int med = p.med.kind == RT_EXPONENTIAL ? 1 : 0;
   DepositFn fn = pick_deposit(p.formalism, p.precision, med, tl.at);
+  MergeFn mf = pick_merge(p.formalism, p.precision);
   if (tl.lds_bytes > 65536)
     (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)tl.lds_bytes);
-  const int64_t grid = (int64_t)tl.n_atiles * tl.n_segs * tl.splits;
+  const int64_t pass_blocks = tl.pass_tracks / 64;
   if (p.ev_start) (void)hipEventRecord(p.ev_start, stream);
-  fn<<<dim3((unsigned)grid), dim3(tl.block), tl.lds_bytes, stream>>>(g);
-  if (p.ev_stop) (void)hipEventRecord(p.ev_stop, stream);
-  MergeFn mf = pick_merge(p.formalism, p.precision);
-  mf<<<dim3((unsigned)(p.det.n_antennas * tl.n_segs)), dim3(256), 0, stream>>>(
-      g.partial, traces, p.det.n_antennas, p.det.n_bins, tl.splits, tl.seg_len, tl.n_segs);
+  for (int64_t b0 = 0; b0 < pa.n_blocks; b0 += pass_blocks) {
+    g.rec = pa.rec + b0 * (kRec * 64);
+    g.n_blocks = std::min(pass_blocks, pa.n_blocks - b0);
+    const int64_t splits = (g.n_blocks + tl.blocks_per_split - 1) / tl.blocks_per_split;
+    const int64_t grid = (int64_t)tl.n_atiles * tl.n_segs * splits;
+    fn<<<dim3((unsigned)grid), dim3(tl.block), tl.lds_bytes, stream>>>(g);
+    if (b0 + pass_blocks >= pa.n_blocks && p.ev_stop) (void)hipEventRecord(p.ev_stop, stream);
+    mf<<<dim3((unsigned)(p.det.n_antennas * tl.n_segs)), dim3(256), 0, stream>>>(
+        g.partial, traces, p.det.n_antennas, p.det.n_bins, (int)splits, tl.seg_len, tl.n_segs);
+  }
   return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@
 
 namespace rt {
 
-constexpr int kMaxTile = 4;     // antennas per workgroup tile (template bound)
+constexpr int kMaxTile = 8;     // antennas per workgroup tile (template bound)
+constexpr int64_t kDefaultPass = 1 << 20;   // tracks per deposit pass by default
 constexpr int kXcds = 8;        // MI355X: 8 XCDs, workgroups dealt round-robin
 
 struct Consts {
@@ -62,15 +63,16 @@ __device__ __forceinline__ double path_index(double zp, double za, double ep, do
 
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an
 // antenna at (ax,ay,az) whose bin 0 starts at tau. Returns u, the arrival in
-// bins; d = X - P and R are returned for the amplitude.
+// bins; d = X - P, R and R^2 are returned for the amplitude.
 __device__ __forceinline__ double arrival_bins(double px, double py, double pz, double tp,
                                                double ax, double ay, double az, double tau,
                                                double neff, const Consts &c, double &dx,
-                                               double &dy, double &dz, double &r) {
+                                               double &dy, double &dz, double &r, double &r2) {
   dx = ax - px;
   dy = ay - py;
   dz = az - pz;
-  r = sqrt((dx * dx + dy * dy) + dz * dz);
+  r2 = (dx * dx + dy * dy) + dz * dz;
+  r = sqrt(r2);
   double t = tp + (neff * r) * c.inv_c;
   return (t - tau) * c.inv_dt;
 }

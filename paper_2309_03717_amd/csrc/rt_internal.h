@@ -23,6 +23,7 @@ struct rt_plan {
   size_t lds_per_cu;      // bytes of LDS per compute unit
   // tiling (0 = automatic)
   int at_user, splits_user, block_user, seg_user;
+  int64_t pass_user;
   // one-shot profiling events around the next deposit kernel
   hipEvent_t ev_start, ev_stop;
 };
@@ -36,7 +37,9 @@ struct Tiling {
   int n_atiles;
   int splits;
   int block;
-  int64_t per_split;
+  int64_t pass_tracks;        // tracks per pass (a multiple of 64)
+  int64_t per_split;          // tracks per split of a pass (a multiple of 64)
+  int64_t blocks_per_split;   // the same in wave blocks of 64 tracks
   size_t lds_bytes;
 };
 

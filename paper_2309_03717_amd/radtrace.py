@@ -51,6 +51,16 @@ class rt_tracks(C.Structure):
     _fields_ = [("n", C.c_int64)] + [(f, C.c_void_p) for f in _TRACK_FIELDS]
 
 
+class rt_tiling(C.Structure):
+    _fields_ = [("antennas_per_block", C.c_int32), ("track_splits", C.c_int32),
+                ("block_threads", C.c_int32), ("bins_per_segment", C.c_int32),
+                ("tracks_per_pass", C.c_int64)]
+
+    def as_tuple(self):
+        return (self.antennas_per_block, self.track_splits, self.block_threads,
+                self.bins_per_segment, self.tracks_per_pass)
+
+
 _P = C.c_void_p
 _lib.rt_abi_version.restype = C.c_int
 _lib.rt_status_string.restype = C.c_char_p
@@ -59,8 +69,8 @@ _lib.rt_last_error.restype = C.c_char_p
 _lib.rt_plan_create.argtypes = [C.POINTER(_P), C.POINTER(rt_detector), C.POINTER(rt_medium),
                                 C.c_int, C.c_int, C.c_double]
 _lib.rt_plan_destroy.argtypes = [_P]
-_lib.rt_plan_set_tiling.argtypes = [_P, C.c_int, C.c_int, C.c_int, C.c_int]
-_lib.rt_plan_get_tiling.argtypes = [_P, C.c_int64] + [C.POINTER(C.c_int)] * 4
+_lib.rt_plan_set_tiling.argtypes = [_P, C.POINTER(rt_tiling)]
+_lib.rt_plan_get_tiling.argtypes = [_P, C.c_int64, C.POINTER(rt_tiling)]
 _lib.rt_plan_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_accumulate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
 _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
@@ -186,16 +196,18 @@ def rt_plan_destroy(plan: int) -> None:
 
 
 def rt_plan_set_tiling(plan: int, antennas_per_block=0, track_splits=0, block_threads=0,
-                       bins_per_segment=0) -> None:
-    _check(_lib.rt_plan_set_tiling(plan, antennas_per_block, track_splits, block_threads,
-                                   bins_per_segment), "rt_plan_set_tiling")
+                       bins_per_segment=0, tracks_per_pass=0) -> None:
+    tl = rt_tiling(antennas_per_block, track_splits, block_threads, bins_per_segment,
+                   tracks_per_pass)
+    _check(_lib.rt_plan_set_tiling(plan, C.byref(tl)), "rt_plan_set_tiling")
 
 
 def rt_plan_get_tiling(plan: int, n_tracks: int):
-    v = [C.c_int() for _ in range(4)]
-    _check(_lib.rt_plan_get_tiling(plan, n_tracks, *[C.byref(x) for x in v]),
-           "rt_plan_get_tiling")
-    return tuple(x.value for x in v)
+    """(antennas_per_block, track_splits, block_threads, bins_per_segment,
+    tracks_per_pass) the plan uses for n_tracks tracks."""
+    tl = rt_tiling()
+    _check(_lib.rt_plan_get_tiling(plan, n_tracks, C.byref(tl)), "rt_plan_get_tiling")
+    return tl.as_tuple()
 
 
 def rt_plan_workspace_bytes(plan: int, n_tracks: int) -> int:
@@ -254,9 +266,9 @@ class Plan:
             self.handle = None
 
     def set_tiling(self, antennas_per_block=0, track_splits=0, block_threads=0,
-                   bins_per_segment=0):
+                   bins_per_segment=0, tracks_per_pass=0):
         rt_plan_set_tiling(self.handle, antennas_per_block, track_splits, block_threads,
-                           bins_per_segment)
+                           bins_per_segment, tracks_per_pass)
 
     def tiling(self, n_tracks: int):
         return rt_plan_get_tiling(self.handle, n_tracks)

@@ -102,7 +102,7 @@ def test_plan_create_without_gpu_reports_no_device(rt):
 
 def test_null_plan_arguments(rt):
     assert rt._lib.rt_plan_destroy(None) == rt.RT_OK
-    assert rt._lib.rt_plan_set_tiling(None, 0, 0, 0, 0) == rt.RT_E_INVALID
+    assert rt._lib.rt_plan_set_tiling(None, C.byref(rt.rt_tiling())) == rt.RT_E_INVALID
     tr = rt.rt_tracks()
     assert rt._lib.rt_accumulate(None, C.byref(tr), None, None, 0, None) == rt.RT_E_INVALID
     assert rt._lib.rt_propagate(None, C.byref(tr), None, None, None) == rt.RT_E_INVALID

@@ -128,10 +128,10 @@ def test_mixed_star_array_exponential(rt, orc, formalism):
 
 
 # ------------------------------------------------------------------ tiling invariance
-# (antennas per workgroup, track splits, workgroup size, bins per segment);
-# every explicit tile fits 64 KB of LDS
-TILINGS = [(1, 1, 256, 2048), (2, 3, 512, 1024), (4, 7, 1024, 512), (1, 0, 0, 1024),
-           (3, 2, 128, 640), (0, 5, 64, 0)]
+# (antennas per workgroup, track splits, workgroup size, bins per segment,
+# tracks per pass); every explicit tile fits 64 KB of LDS
+TILINGS = [(1, 1, 256, 2048, 0), (2, 3, 512, 1024, 0), (4, 7, 1024, 512, 0), (1, 0, 0, 1024, 0),
+           (3, 2, 128, 640, 0), (0, 5, 64, 0, 0), (1, 2, 256, 2048, 1024), (0, 0, 0, 0, 64)]
 
 
 @pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
