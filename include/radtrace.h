@@ -193,6 +193,29 @@ int rt_plan_set_timing_events(rt_plan *plan, void *start_event, void *stop_event
 int rt_propagate(const rt_plan *plan, const rt_tracks *tracks, double *t_arrival, int32_t *bin,
                  void *stream);
 
+/* Device workspace (bytes) rt_zhs_vjp needs for n_tracks tracks. */
+int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes);
+
+/* Vector-Jacobian product of the ZHS traces (the differentiable form of the
+ * ZHS deposit of rt_accumulate; plan must be RT_ZHS). Given the upstream
+ * gradient grad_traces = dL/dA of a scalar loss L with respect to the traces
+ * (device, [M][n_bins][3], the plan's trace type), writes the exact
+ * derivatives of L with respect to each track's weight qw, its start point P0
+ * and end point P1, and the refractivity n0_minus_1, with the velocity and
+ * the emission times t0, t1 held fixed (piecewise: the derivative of a box
+ * edge that sits exactly on a bin edge is the right derivative):
+ *   grad_qw   device double [n]
+ *   grad_p0   device double [3][n]  (x, y, z rows)
+ *   grad_p1   device double [3][n]
+ *   grad_n0m1 device double [1]     (sum over this call's tracks)
+ * All outputs are overwritten; for streamed chunks the caller sums grad_n0m1.
+ * Tracks with a non-finite field get zero gradients. The per-track gradients
+ * do not depend on any launch shape; grad_n0m1 is summed in a fixed order.
+ * workspace: device, >= rt_plan_vjp_workspace_bytes(plan, tracks->n). */
+int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, double *grad_qw,
+               double *grad_p0, double *grad_p1, double *grad_n0m1, void *workspace,
+               size_t workspace_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

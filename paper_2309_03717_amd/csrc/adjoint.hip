@@ -1,0 +1,270 @@
+// adjoint.hip -- vector-Jacobian product of the ZHS traces.
+//
+// For a scalar loss with upstream gradient G = dL/dA over the traces
+// [M][B][3], the share of one (track, antenna) pair is
+//     L_p = sum_c I_c / dt * gbar_c,
+//     gbar_c = (Phi_c(u_hi) - Phi_c(u_lo)) / (u_hi - u_lo)   (or G_c at the bin
+//                                                         when both ends share it)
+// where I = k qw beta_perp (t1 - t0) / R_mid is the box's time integral, u_lo
+// and u_hi its edges in bins, and Phi_c the integral of the piecewise-constant
+// G_c from bin 0 (zero outside the window). Its exact derivatives with respect
+// to the track weight, the two end points (through R_mid and beta_perp at the
+// midpoint, and through the arrival times of the box edges) and the
+// refractivity n0 - 1 (through the path indices of the edges) are accumulated
+// per track over all antennas; beta and the emission times are held fixed.
+//
+// Kernels: phi_kernel (one workgroup per antenna: prefix sums of G in double),
+// vjp_kernel (one thread per track, loop over antennas, per-track gradients
+// in registers, per-workgroup partial of the n0 - 1 gradient in fixed order)
+// and n0_sum_kernel (fixed-order sum of the partials).
+#include <type_traits>
+
+#include "rt_internal.h"
+
+namespace rt {
+
+constexpr int kVjpBlock = 256;
+
+// Phi[a][c][j] = sum_{i < j} G[a][i][c], j = 0..B (double).
+template <typename TG>
+__global__ void __launch_bounds__(256) phi_kernel(const TG *grad, double *phi, int n_bins) {
+  const int64_t a = blockIdx.x;
+  const TG *g = grad + (size_t)a * n_bins * 3;
+  double *out = phi + (size_t)a * 3 * (n_bins + 1);
+  __shared__ double carry[256][3];
+  const int per = (n_bins + blockDim.x - 1) / blockDim.x;
+  const int b0 = min((int)threadIdx.x * per, n_bins), b1 = min(b0 + per, n_bins);
+  double run[3] = {0.0, 0.0, 0.0};
+  for (int b = b0; b < b1; ++b)
+    for (int c = 0; c < 3; ++c) run[c] += (double)g[3 * b + c];
+  for (int c = 0; c < 3; ++c) carry[threadIdx.x][c] = run[c];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double acc = 0.0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      double x = carry[t][threadIdx.x];
+      carry[t][threadIdx.x] = acc;
+      acc += x;
+    }
+    out[threadIdx.x * (n_bins + 1) + n_bins] = acc;   // Phi[B]: the total
+  }
+  __syncthreads();
+  for (int c = 0; c < 3; ++c) run[c] = carry[threadIdx.x][c];
+  for (int b = b0; b < b1; ++b)
+    for (int c = 0; c < 3; ++c) {
+      out[c * (n_bins + 1) + b] = run[c];
+      run[c] += (double)g[3 * b + c];
+    }
+}
+
+template <typename TG>
+struct GradView {
+  const TG *g;       // [B][3] of one antenna
+  const double *phi; // [3][B + 1] of one antenna
+  int n_bins;
+  double nb;
+
+  // G_c at u (zero outside [0, B))
+  __device__ __forceinline__ double value(int c, double u) const {
+    if (!(u >= 0.0 && u < nb)) return 0.0;
+    return (double)g[3 * (int)u + c];
+  }
+  // Phi_c(u) = integral of G_c from 0 to u
+  __device__ __forceinline__ double cumulative(int c, double u) const {
+    if (!(u > 0.0)) return 0.0;
+    if (u >= nb) return phi[c * (n_bins + 1) + n_bins];
+    int j = (int)u;
+    return phi[c * (n_bins + 1) + j] + (u - (double)j) * (double)g[3 * j + c];
+  }
+};
+
+struct VjpArgs {
+  TrackPtrs tr;
+  AntPtrs an;
+  Consts c;
+  const void *grad;     // [M][B][3], float (mixed) or double
+  const double *phi;    // [M][3][B+1]
+  double *g_qw, *g_p0, *g_p1;   // [n], [3][n], [3][n]
+  double *n0_part;      // [gridDim.x]
+};
+
+// d t / d z_P of the path index for an end at height zp with height factor
+// ep (and of n_eff itself), and d n_eff / d (n0 - 1); antenna at height za
+// with height factor ea.
+__device__ __forceinline__ void index_derivatives(double zp, double za, double ep, double ea,
+                                                  const Consts &c, double &neff, double &dn_dz,
+                                                  double &dn_dn0) {
+  if (c.medium == 0) {
+    neff = c.n_uniform;
+    dn_dz = 0.0;
+    dn_dn0 = 1.0;
+    return;
+  }
+  neff = path_index(zp, za, ep, ea, c);
+  double dz = zp - za;
+  if (fabs(dz) >= 1e-3) {
+    double f = (ea - ep) / dz;
+    dn_dn0 = c.h * f;
+    // d f / d zp = (ep / h) / dz - f / dz
+    dn_dz = c.n0h * ((ep / c.h) / dz - f / dz);
+  } else {
+    double e = exp(-(((zp + za) * 0.5) / c.h));
+    dn_dn0 = e;
+    dn_dz = -c.n0m1 * e / (2.0 * c.h);
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
+  using In = typename std::conditional<P == 0, double, float>::type;
+  const Consts &c = v.c;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double gn_local = 0.0;
+  if (i < v.tr.n) {
+    const double x0 = v.tr.x0[i], y0 = v.tr.y0[i], z0 = v.tr.z0[i], t0 = v.tr.t0[i];
+    const double x1 = v.tr.x1[i], y1 = v.tr.y1[i], z1 = v.tr.z1[i], t1 = v.tr.t1[i];
+    const double b[3] = {(double)((const In *)v.tr.bx)[i], (double)((const In *)v.tr.by)[i],
+                         (double)((const In *)v.tr.bz)[i]};
+    const double qw = (double)((const In *)v.tr.qw)[i];
+    bool ok = isfinite(qw) && isfinite(x0) && isfinite(y0) && isfinite(z0) && isfinite(t0) &&
+              isfinite(x1) && isfinite(y1) && isfinite(z1) && isfinite(t1) && isfinite(b[0]) &&
+              isfinite(b[1]) && isfinite(b[2]);
+    double gq = 0.0, gp0[3] = {0.0, 0.0, 0.0}, gp1[3] = {0.0, 0.0, 0.0};
+    const double e0 = c.medium == 1 ? height_factor(z0, c) : 0.0;
+    const double e1 = c.medium == 1 ? height_factor(z1, c) : 0.0;
+    const double mx = (x0 + x1) * 0.5, my = (y0 + y1) * 0.5, mz = (z0 + z1) * 0.5;
+    const double kdt = c.k * (t1 - t0);   // I = kdt * qw * beta_perp / R_m
+    for (int64_t a = 0; ok && a < v.an.m; ++a) {
+      const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
+      const double ea = c.medium == 1 ? height_factor(az, c) : 0.0;
+      double ne0, dnz0, dnn0, ne1, dnz1, dnn1;
+      index_derivatives(z0, az, e0, ea, c, ne0, dnz0, dnn0);
+      index_derivatives(z1, az, e1, ea, c, ne1, dnz1, dnn1);
+      double d0x, d0y, d0z, r0, r02, d1x, d1y, d1z, r1, r12;
+      const double us = arrival_bins(x0, y0, z0, t0, ax, ay, az, tau, ne0, c, d0x, d0y, d0z, r0, r02);
+      const double ue = arrival_bins(x1, y1, z1, t1, ax, ay, az, tau, ne1, c, d1x, d1y, d1z, r1, r12);
+      const bool start_lo = us < ue;
+      const double ulo = start_lo ? us : ue, uhi = start_lo ? ue : us;
+      if (!(uhi >= 0.0 && ulo < c.nbins_d)) continue;
+      // midpoint geometry
+      const double d[3] = {ax - mx, ay - my, az - mz};
+      const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+      if (r2 == 0.0) continue;
+      const double r = sqrt(r2);
+      const double bd = (b[0] * d[0] + b[1] * d[1]) + b[2] * d[2];
+      double iu[3];   // integral per unit weight
+      for (int k = 0; k < 3; ++k) iu[k] = kdt * (b[k] - bd / r2 * d[k]) / r;
+      GradView<In> gv{(const In *)v.grad + (size_t)a * c.n_bins * 3,
+                      v.phi + (size_t)a * 3 * (c.n_bins + 1), c.n_bins, c.nbins_d};
+      const bool same_bin = floor(ulo) == floor(uhi);
+      const double w = uhi - ulo;
+      double gbar[3], dl_dlo = 0.0, dl_dhi = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        if (same_bin) {
+          gbar[k] = gv.value(k, ulo);
+        } else {
+          gbar[k] = (gv.cumulative(k, uhi) - gv.cumulative(k, ulo)) / w;
+          const double ik = qw * iu[k] * c.inv_dt;
+          dl_dhi += ik * (gv.value(k, uhi) - gbar[k]) / w;
+          dl_dlo += ik * (gbar[k] - gv.value(k, ulo)) / w;
+        }
+      }
+      // weight: the pair's loss share is linear in qw
+      double gam[3];
+      for (int k = 0; k < 3; ++k) {
+        gam[k] = gbar[k] * c.inv_dt;
+        gq += iu[k] * gam[k];
+      }
+      // midpoint: I = K (beta / R - (beta.d) d / R^3), K = kdt qw, d = X - M
+      const double kk = kdt * qw;
+      const double gb = (gam[0] * b[0] + gam[1] * b[1]) + gam[2] * b[2];
+      const double gd = (gam[0] * d[0] + gam[1] * d[1]) + gam[2] * d[2];
+      const double r3 = r2 * r, r5 = r3 * r2;
+      for (int k = 0; k < 3; ++k) {
+        const double dl_dd = kk * (-(gb * d[k] + gd * b[k] + bd * gam[k]) / r3 +
+                                   3.0 * bd * gd * d[k] / r5);
+        gp0[k] -= 0.5 * dl_dd;   // d = X - (P0 + P1) / 2
+        gp1[k] -= 0.5 * dl_dd;
+      }
+      // box edges: u = (T + n_eff R / c - tau) / dt
+      const double dl_ds = (start_lo ? dl_dlo : dl_dhi) * c.inv_dt * c.inv_c;
+      const double dl_de = (start_lo ? dl_dhi : dl_dlo) * c.inv_dt * c.inv_c;
+      // d (n_eff R) / d P = -n_eff d / R + R dn_eff/dz e_z
+      gp0[0] += dl_ds * (-ne0 * d0x / r0);
+      gp0[1] += dl_ds * (-ne0 * d0y / r0);
+      gp0[2] += dl_ds * (-ne0 * d0z / r0 + r0 * dnz0);
+      gp1[0] += dl_de * (-ne1 * d1x / r1);
+      gp1[1] += dl_de * (-ne1 * d1y / r1);
+      gp1[2] += dl_de * (-ne1 * d1z / r1 + r1 * dnz1);
+      gn_local += dl_ds * r0 * dnn0 + dl_de * r1 * dnn1;
+    }
+    v.g_qw[i] = gq;
+    for (int k = 0; k < 3; ++k) {
+      v.g_p0[(size_t)k * v.tr.n + i] = gp0[k];
+      v.g_p1[(size_t)k * v.tr.n + i] = gp1[k];
+    }
+  }
+  // fixed-order workgroup reduction of the n0 - 1 gradient
+  __shared__ double red[kVjpBlock];
+  red[threadIdx.x] = gn_local;
+  __syncthreads();
+  for (int s = kVjpBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) v.n0_part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) n0_sum_kernel(const double *part, int64_t n, double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += blockDim.x) s += part[j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t vjp_workspace_bytes(const rt_plan &p, int64_t n) {
+  const int64_t blocks = (n + kVjpBlock - 1) / kVjpBlock;
+  return align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double)) +
+         align256((size_t)std::max<int64_t>(blocks, 1) * sizeof(double));
+}
+
+hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, double *g_qw,
+                      double *g_p0, double *g_p1, double *g_n0, void *workspace,
+                      hipStream_t stream) {
+  char *ws = reinterpret_cast<char *>(workspace);
+  double *phi = reinterpret_cast<double *>(ws);
+  ws += align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double));
+  double *part = reinterpret_cast<double *>(ws);
+  const unsigned m = (unsigned)p.det.n_antennas;
+  if (p.precision == RT_FP64)
+    phi_kernel<double><<<m, 256, 0, stream>>>((const double *)grad, phi, p.det.n_bins);
+  else
+    phi_kernel<float><<<m, 256, 0, stream>>>((const float *)grad, phi, p.det.n_bins);
+  VjpArgs v;
+  v.tr = track_ptrs(t);
+  v.an = ant_ptrs(p.det);
+  v.c = p.c;
+  v.grad = grad;
+  v.phi = phi;
+  v.g_qw = g_qw;
+  v.g_p0 = g_p0;
+  v.g_p1 = g_p1;
+  v.n0_part = part;
+  const int64_t blocks = (t.n + kVjpBlock - 1) / kVjpBlock;
+  if (p.precision == RT_FP64)
+    vjp_kernel<0><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+  else
+    vjp_kernel<1><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+  n0_sum_kernel<<<1, 256, 0, stream>>>(part, blocks, g_n0);
+  return hipGetLastError();
+}
+
+}  // namespace rt

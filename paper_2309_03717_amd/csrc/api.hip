@@ -190,6 +190,35 @@ int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *wo
   return RT_OK;
 }
 
+int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes) {
+  if (!plan || !bytes) return fail(RT_E_INVALID, "plan or bytes is NULL");
+  if (n_tracks < 0) return fail(RT_E_INVALID, "n_tracks < 0");
+  *bytes = rt::vjp_workspace_bytes(*plan, n_tracks);
+  return RT_OK;
+}
+
+int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, double *grad_qw,
+               double *grad_p0, double *grad_p1, double *grad_n0m1, void *workspace,
+               size_t workspace_bytes, void *stream) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  if (plan->formalism != RT_ZHS) return fail(RT_E_INVALID, "rt_zhs_vjp needs an RT_ZHS plan");
+  int s = check_tracks(plan, tracks);
+  if (s != RT_OK) return s;
+  if (!grad_traces || !grad_n0m1) return fail(RT_E_INVALID, "grad_traces or grad_n0m1 is NULL");
+  if (tracks->n > 0 && (!grad_qw || !grad_p0 || !grad_p1))
+    return fail(RT_E_INVALID, "a per-track gradient pointer is NULL");
+  if (tracks->n >= ((int64_t)1 << 31) - 1024)
+    return fail(RT_E_UNSUPPORTED, "at most 2^31 - 1025 tracks per call");
+  size_t need = rt::vjp_workspace_bytes(*plan, tracks->n);
+  if (!workspace || workspace_bytes < need)
+    return fail(RT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");
+  (void)hipGetLastError();
+  hipError_t e = rt::launch_vjp(*plan, *tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1,
+                                workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "launching the ZHS adjoint kernels");
+  return RT_OK;
+}
+
 int rt_plan_set_timing_events(rt_plan *plan, void *start_event, void *stop_event) {
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if ((start_event == nullptr) != (stop_event == nullptr))

@@ -56,6 +56,12 @@ AntPtrs ant_ptrs(const rt_detector &d);
 // Launchers: enqueue on `stream`, return the hipGetLastError() status.
 hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, void *workspace,
                           hipStream_t stream);
+// ZHS vector-Jacobian product (adjoint.hip).
+size_t vjp_workspace_bytes(const rt_plan &p, int64_t n);
+hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, double *g_qw,
+                      double *g_p0, double *g_p1, double *g_n0, void *workspace,
+                      hipStream_t stream);
+
 hipError_t launch_propagate(const rt_plan &p, const rt_tracks &t, double *t_arrival,
                             int32_t *bin, hipStream_t stream);
 

@@ -75,6 +75,8 @@ _lib.rt_plan_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_accumulate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
 _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
 _lib.rt_plan_set_timing_events.argtypes = [_P, _P, _P]
+_lib.rt_plan_vjp_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
+_lib.rt_zhs_vjp.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P, _P, _P, _P, C.c_size_t, _P]
 
 
 class RadtraceError(RuntimeError):
@@ -242,6 +244,22 @@ def rt_propagate(plan: int, tracks: rt_tracks, t_arrival: Optional[torch.Tensor]
            "rt_propagate")
 
 
+def rt_plan_vjp_workspace_bytes(plan: int, n_tracks: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.rt_plan_vjp_workspace_bytes(plan, n_tracks, C.byref(b)),
+           "rt_plan_vjp_workspace_bytes")
+    return b.value
+
+
+def rt_zhs_vjp(plan: int, tracks: rt_tracks, grad_traces: torch.Tensor, grad_qw: torch.Tensor,
+               grad_p0: torch.Tensor, grad_p1: torch.Tensor, grad_n0m1: torch.Tensor,
+               workspace: torch.Tensor, stream=None) -> None:
+    _check(_lib.rt_zhs_vjp(plan, C.byref(tracks), _ptr(grad_traces), _ptr(grad_qw), _ptr(grad_p0),
+                           _ptr(grad_p1), _ptr(grad_n0m1), _ptr(workspace),
+                           workspace.numel() * workspace.element_size(), _stream(stream)),
+           "rt_zhs_vjp")
+
+
 # ------------------------------------------------------------------ convenience
 class Plan:
     """A radio process for one detector, medium, formalism and precision
@@ -293,6 +311,23 @@ class Plan:
 
     def traces(self, tracks: DeviceTracks, stream=None) -> torch.Tensor:
         return self.accumulate(tracks, self.new_traces(), stream)
+
+    def zhs_vjp(self, tracks: DeviceTracks, grad_traces: torch.Tensor, stream=None):
+        """Gradients (qw [n], p0 [3, n], p1 [3, n], n0m1 [1]) of sum(grad * A),
+        all float64, for a ZHS plan."""
+        dev = self.det.x.device
+        n = tracks.n
+        g = grad_traces.to(self.dtype).contiguous()
+        if tuple(g.shape) != (self.det.m, self.det.n_bins, 3):
+            raise ValueError("grad_traces must be [M, n_bins, 3]")
+        gq = torch.empty(n, dtype=torch.float64, device=dev)
+        gp0 = torch.empty((3, n), dtype=torch.float64, device=dev)
+        gp1 = torch.empty((3, n), dtype=torch.float64, device=dev)
+        gn = torch.empty(1, dtype=torch.float64, device=dev)
+        ws = torch.empty(max(rt_plan_vjp_workspace_bytes(self.handle, n), 256), dtype=torch.uint8,
+                         device=dev)
+        rt_zhs_vjp(self.handle, tracks.struct(self.precision), g, gq, gp0, gp1, gn, ws, stream)
+        return gq, gp0, gp1, gn
 
     def propagate(self, tracks: DeviceTracks, stream=None):
         shape = (2, tracks.n, self.det.m)

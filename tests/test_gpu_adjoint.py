@@ -1,0 +1,155 @@
+"""GPU parity of the ZHS adjoint (rt_zhs_vjp) and its autograd Function.
+
+Checked against the oracle's FP64 adjoint on the same upstream gradient, the
+exact weight-linearity identity, central finite differences of the GPU
+forward (bar: 1e-4 relative per parameter group), and a differentiable
+trace-loss workflow on the 64-antenna exponential-medium workload.
+"""
+import numpy as np
+import pytest
+
+from paper_2309_03717_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_03717_amd import radtrace
+    return radtrace
+
+
+def rel(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_vjp(rt, tracks, array, medium, grad, precision):
+    import torch
+    det = rt.DeviceDetector.from_array(array)
+    plan = rt.Plan(det, medium, "zhs", precision)
+    tr = tracks.to_mixed() if precision == "mixed" else tracks
+    g = torch.from_numpy(grad).to("cuda")
+    out = plan.zhs_vjp(rt.DeviceTracks.from_tracks(tr), g)
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_vjp_matches_oracle_adjoint(rt, orc, precision):
+    w = W.config(3)
+    tr = w.tracks(20_000)
+    grad = np.random.default_rng(4).normal(size=(w.array.m, w.array.n_bins, 3))
+    if precision == "mixed":
+        grad = grad.astype(np.float32)
+    gq, gp0, gp1, gn = gpu_vjp(rt, tr, w.array, w.medium, grad, precision)
+    tr_ref = tr.to_mixed().widened() if precision == "mixed" else tr
+    ref = orc.zhs_vjp(tr_ref, w.array, w.medium, grad.astype(np.float64), n_threads=8)
+    errs = {"qw": rel(gq, ref["qw"]), "p0": rel(gp0, ref["p0"]), "p1": rel(gp1, ref["p1"]),
+            "n0m1": rel(gn[0], ref["n0m1"])}
+    print(precision, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-9, (k, v)
+
+
+def gpu_loss(rt, tracks, array, medium, grad, precision="fp64"):
+    import torch
+    det = rt.DeviceDetector.from_array(array)
+    plan = rt.Plan(det, medium, "zhs", precision)
+    a = plan.traces(rt.DeviceTracks.from_tracks(tracks)).double().cpu().numpy()
+    return float(np.sum(a * grad))
+
+
+def test_vjp_weight_identity_and_finite_differences(rt, orc):
+    """dL/dqw = L_i / qw_i exactly (A is linear in qw); positions and n0 - 1
+    against Richardson central differences of the GPU forward (FP64),
+    skipping parameters whose shift moves a box edge across a bin edge."""
+    import torch
+    w = W.config(3)
+    md, ar = w.medium, w.array
+    tr = w.tracks(400)
+    _, u, b = orc.propagate(tr, ar, md)
+    reach = np.flatnonzero(((b >= 0).any(axis=0)).any(axis=1))[:6]
+    tr = tr.take(reach)
+    grad = np.random.default_rng(9).normal(size=(ar.m, ar.n_bins, 3))
+    gq, gp0, gp1, gn = gpu_vjp(rt, tr, ar, md, grad, "fp64")
+    for i in range(tr.n):
+        li = gpu_loss(rt, tr.take([i]), ar, md, grad)
+        assert gq[i] == pytest.approx(li / tr.qw[i], rel=1e-9)
+
+    def richardson(f, x, h):
+        c = lambda s: (f(x + s) - f(x - s)) / (2 * s)
+        return (4.0 * c(h) - c(2 * h)) / 3.0
+
+    h = 1e-5
+    checked = 0
+    for i in range(tr.n):
+        one = tr.take([i])
+        _, u0, _ = orc.propagate(one, ar, md)
+        scale = max(np.abs(gp0[:, i]).max(), np.abs(gp1[:, i]).max())
+        for end in (0, 1):
+            for c, comp in enumerate("xyz"):
+                key = f"{comp}{end}"
+                base = float(one.arrays()[key][0])
+                moved = lambda v: W.Tracks(**{**one.arrays(), key: np.array([v])})
+                if any((np.floor(orc.propagate(moved(base + s), ar, md)[1]) != np.floor(u0)).any()
+                       for s in (-2 * h, 2 * h)):
+                    continue
+                fd = richardson(lambda v: gpu_loss(rt, moved(v), ar, md, grad), base, h)
+                an = (gp0 if end == 0 else gp1)[c, i]
+                assert abs(an - fd) <= 1e-4 * abs(fd) + 1e-5 * scale, (i, key, an, fd)
+                checked += 1
+    assert checked >= 12
+    hn = 1e-6 * md.n0m1
+    keep = [i for i in range(tr.n)
+            if all((np.floor(orc.propagate(tr.take([i]), ar, W.Medium(md.kind, md.n0m1 + s, md.h))[1])
+                    == np.floor(orc.propagate(tr.take([i]), ar, md)[1])).all() for s in (-2 * hn, 2 * hn))]
+    sub = tr.take(keep)
+    fd = richardson(lambda v: gpu_loss(rt, sub, ar, W.Medium(md.kind, v, md.h), grad), md.n0m1, hn)
+    an = gpu_vjp(rt, sub, ar, md, grad, "fp64")[3][0]
+    assert an == pytest.approx(fd, rel=1e-4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autograd_trace_loss_workflow(rt, orc, precision):
+    """Differentiable ZHS on the 64-antenna workload: loss = sum (A - A*)^2
+    with the target made by the same generator at perturbed parameters
+    (positions +N(0, 0.5 m), weights x(1+N(0, 0.05)), n0-1 x1.02); autograd
+    gradients equal the oracle adjoint with the same upstream gradient."""
+    import torch
+    from paper_2309_03717_amd.autograd import zhs_traces
+    w = W.config(3)
+    tr = w.tracks(5000)
+    target_tr, target_md = W.perturbed_target(tr, w.medium, w.seed)
+    det = rt.DeviceDetector.from_array(w.array)
+    dev = "cuda"
+
+    def params(t, md):
+        qw = torch.tensor(t.qw, dtype=torch.float64, device=dev, requires_grad=True)
+        p0 = torch.tensor(np.stack([t.x0, t.y0, t.z0]), device=dev, requires_grad=True)
+        p1 = torch.tensor(np.stack([t.x1, t.y1, t.z1]), device=dev, requires_grad=True)
+        n0 = torch.tensor(md.n0m1, dtype=torch.float64, device=dev, requires_grad=True)
+        return qw, p0, p1, n0
+
+    fixed = dict(t0=torch.tensor(tr.t0, device=dev), t1=torch.tensor(tr.t1, device=dev),
+                 beta=torch.tensor(np.stack([tr.bx, tr.by, tr.bz]), device=dev), det=det,
+                 medium_kind=w.medium.kind, scale_height=w.medium.h, precision=precision)
+    with torch.no_grad():
+        tq, t0p, t1p, tn = params(target_tr, target_md)
+        target = zhs_traces(tq, t0p, t1p, tn, **fixed)
+    qw, p0, p1, n0 = params(tr, w.medium)
+    traces = zhs_traces(qw, p0, p1, n0, **fixed)
+    loss = ((traces.double() - target.double()) ** 2).sum()
+    loss.backward()
+    upstream = (2.0 * (traces.double() - target.double())).to(traces.dtype).detach().cpu().numpy()
+    tr_ref = tr.to_mixed().widened() if precision == "mixed" else tr
+    ref = orc.zhs_vjp(tr_ref, w.array, w.medium, upstream.astype(np.float64), n_threads=8)
+    assert loss.item() > 0
+    errs = {"qw": rel(qw.grad.cpu(), ref["qw"]), "p0": rel(p0.grad.cpu(), ref["p0"]),
+            "p1": rel(p1.grad.cpu(), ref["p1"]), "n0m1": rel(n0.grad.cpu(), ref["n0m1"])}
+    print(precision, "loss", loss.item(), {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-9, (k, v)
