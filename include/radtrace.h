@@ -20,6 +20,9 @@
  *  - `stream` is a hipStream_t passed as void* (NULL: the null stream). All
  *    device work of a call is enqueued on it; no call synchronizes the stream
  *    or allocates device memory, so calls may be captured into a HIP graph.
+ *    The exceptions are the batch calls at the end of this header:
+ *    rt_batch_create allocates and fills the batch's small device tables
+ *    (synchronously) and rt_batch_destroy frees them.
  *  - Every function returns an rt_status. On failure nothing is enqueued and
  *    rt_last_error() holds a description (per host thread).
  *    Invalid arguments give RT_E_INVALID; shapes the kernels do not support
@@ -215,6 +218,87 @@ int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *b
 int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, double *grad_qw,
                double *grad_p0, double *grad_p1, double *grad_n0m1, void *workspace,
                size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------ batches
+ *
+ * Many independent showers in one launch. Each shower is one call of §2's
+ * loop (its own detector, medium, formalism and tracks; the tracks of one
+ * shower never reach another shower's antennas); a batch runs all of them
+ * with one persistent deposit kernel whose workgroups take work items
+ * (antenna tile x bin segment x track split of some shower) from a shared
+ * counter, longest first, followed by one merge kernel. Per-shower results
+ * are those of rt_accumulate on that shower alone up to floating-point
+ * summation order; bins never change. */
+typedef struct {
+  rt_detector det;   /* as for rt_plan_create; n_bins * 3 doubles of a tile
+                        segment must fit in LDS after splitting (any n_bins) */
+  rt_medium med;
+  int32_t formalism; /* rt_formalism */
+  rt_tracks tracks;  /* device; n < 2^31; n == 0 allowed */
+  void *traces;      /* device, [M][n_bins][3] of the batch precision; += */
+} rt_shower;
+
+/* Launch shape of a batch (a zeroed struct, or NULL, keeps every automatic
+ * choice):
+ *  block_threads: workgroup size of the persistent kernel, a multiple of 64
+ *                 in [64, 512] (0: 512)
+ *  items_per_cu: work items per compute unit that the track splits aim for
+ *                (0: 4); more items balance better, fewer merge less
+ *  max_antennas_per_tile: cap on the antennas one item keeps in LDS, 1-3
+ *                         (0: 3)
+ *  direct_launch: 0 captures the batch's kernels into a HIP graph on the
+ *                 first rt_batch_launch (and again when the workspace
+ *                 changes) and replays it; 1 enqueues the kernels on every
+ *                 launch. A launch on a stream that the caller is capturing
+ *                 always enqueues directly into the caller's capture.
+ *  per_shower: NULL, or n_showers tilings overriding antennas_per_block
+ *              (1-3), track_splits and bins_per_segment per shower (0 keeps
+ *              the automatic choice; block_threads and tracks_per_pass are
+ *              ignored) */
+typedef struct {
+  int32_t block_threads;
+  int32_t items_per_cu;
+  int32_t max_antennas_per_tile;
+  int32_t direct_launch;
+  const rt_tiling *per_shower;
+} rt_batch_options;
+
+typedef struct rt_batch rt_batch;   /* opaque; host object plus device tables */
+
+/* Plans a batch of n_showers >= 1 showers (showers, options: host, read
+ * during the call) for the current device, in one precision (RT_FP64 or
+ * RT_MIXED, as for rt_plan_create) and with one field prefactor k. The batch
+ * keeps every device pointer of `showers`; to run new inputs, overwrite those
+ * buffers and launch again. Allocates the work-item, merge and shower tables
+ * (a few bytes per item) on the device and copies them there before
+ * returning. Output: *batch (free with rt_batch_destroy). */
+int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_showers, int precision,
+                    double k, const rt_batch_options *options);
+
+/* Frees a batch, its device tables and its graph (NULL is accepted). The
+ * caller makes sure no launch of it is still running. */
+int rt_batch_destroy(rt_batch *batch);
+
+/* Device workspace (bytes) rt_batch_launch needs (per-track records of all
+ * showers and one partial-trace slot per work item). */
+int rt_batch_workspace_bytes(const rt_batch *batch, size_t *bytes);
+
+/* Statistics of the plan (out: host; any pointer may be NULL): work items,
+ * persistent workgroups, LDS bytes per workgroup and track x antenna pairs. */
+int rt_batch_get_info(const rt_batch *batch, int64_t *n_items, int32_t *n_workgroups,
+                      int64_t *lds_bytes, int64_t *pairs);
+
+/* traces += contribution of the shower's tracks, for every shower (on
+ * `stream`, see rt_batch_options.direct_launch for graphs). workspace:
+ * device, >= rt_batch_workspace_bytes bytes, used by this launch only;
+ * launches of one batch that overlap in time race on its device counter. */
+int rt_batch_launch(rt_batch *batch, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Profiling aid: the next rt_batch_launch enqueues its kernels directly (not
+ * through the graph) and records start_event before and stop_event after its
+ * persistent deposit kernel, then forgets both (hipEvent_t as void*, created
+ * and owned by the caller); NULL for both clears a pending request. */
+int rt_batch_set_timing_events(rt_batch *batch, void *start_event, void *stop_event);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,176 @@
+"""Launch-shape autotuner for batches and single plans.
+
+Candidate shapes are timed on the device with HIP events around real
+launches (same inputs, direct launches, warm-up first); the fastest is kept in
+a JSON cache keyed by the device (architecture and compute-unit count) and a
+signature of the workload's shapes, so that later runs of the same shapes
+reuse it without timing anything. The cache file is written atomically
+(temporary file + rename).
+"""
+from __future__ import annotations
+
+import hashlib
+import itertools
+import json
+import os
+import statistics
+import tempfile
+import time
+from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+DEFAULT_CACHE = os.environ.get(
+    "RADTRACE_TUNE_CACHE",
+    os.path.join(os.path.expanduser("~"), ".cache", "paper_2309_03717_amd", "tuning.json"))
+
+
+# ------------------------------------------------------------------ cache
+class TuningCache:
+    """A JSON object {key: {"best": ..., "timings": [...], "when": ...}}."""
+
+    def __init__(self, path: Optional[str] = None):
+        self.path = path or DEFAULT_CACHE
+        self.data: Dict[str, dict] = {}
+        if os.path.exists(self.path):
+            try:
+                with open(self.path) as f:
+                    self.data = json.load(f)
+            except (OSError, ValueError):
+                self.data = {}   # unreadable cache: start afresh
+
+    def get(self, key: str):
+        e = self.data.get(key)
+        return None if e is None else e["best"]
+
+    def put(self, key: str, best, timings) -> None:
+        self.data[key] = {"best": best, "timings": timings, "when": time.time()}
+        d = os.path.dirname(os.path.abspath(self.path))
+        os.makedirs(d, exist_ok=True)
+        fd, tmp = tempfile.mkstemp(dir=d, prefix=".tuning", suffix=".json")
+        with os.fdopen(fd, "w") as f:
+            json.dump(self.data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def device_key() -> str:
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", p.name)
+    return f"{arch}/{p.multi_processor_count}cu"
+
+
+def signature(parts: Iterable) -> str:
+    return hashlib.sha1(json.dumps(list(parts)).encode()).hexdigest()[:16]
+
+
+# ------------------------------------------------------------------ timing
+def time_launches(fn: Callable[[], None], warmup: int = 1, reps: int = 3) -> float:
+    """Median seconds of fn() on the current stream, by HIP events."""
+    for _ in range(warmup):
+        fn()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b) * 1e-3)
+    return statistics.median(times)
+
+
+def tune(key: str, candidates: Sequence, measure: Callable[[object], float],
+         cache: Optional[TuningCache] = None, log: Optional[Callable[[str], None]] = None):
+    """The candidate with the smallest measure(candidate) (seconds), cached
+    under key. A candidate whose measurement raises (for example a shape the
+    library rejects) is skipped. Returns (best, timings, from_cache)."""
+    cache = cache if cache is not None else TuningCache()
+    hit = cache.get(key)
+    if hit is not None:
+        return hit, None, True
+    timings: List[Tuple[object, float]] = []
+    for c in candidates:
+        try:
+            t = measure(c)
+        except (RuntimeError, ValueError) as e:
+            if log:
+                log(f"  {c}: rejected ({e})")
+            continue
+        timings.append((c, t))
+        if log:
+            log(f"  {c}: {t * 1e3:.3f} ms")
+    if not timings:
+        raise RuntimeError("no candidate launch shape could be measured")
+    best = min(timings, key=lambda ct: ct[1])[0]
+    cache.put(key, best, [[c, t] for c, t in timings])
+    return best, timings, False
+
+
+# ------------------------------------------------------------------ batches
+BATCH_BLOCKS = (256, 512)
+BATCH_AT = (1, 2, 3)
+BATCH_ITEMS = (2, 4, 8)
+
+
+def batch_key(showers, precision: str) -> str:
+    shapes = [(f, md.kind, det.m, det.n_bins, tr.n) for det, md, f, tr in showers]
+    return f"batch/{device_key()}/{precision}/{signature(shapes)}"
+
+
+def tune_batch(showers, precision: str = "mixed", k: float = 1.0,
+               cache_path: Optional[str] = None, candidates=None, sample_tracks: Optional[int] = None,
+               warmup: int = 1, reps: int = 2, log=None):
+    """BatchOptions for the showers (list of (DeviceDetector, medium,
+    formalism, DeviceTracks)). Candidates are (block_threads, max antennas
+    per tile, items per CU) triples; sample_tracks times each candidate on
+    the first tracks of every shower only. The result launches through a HIP
+    graph."""
+    from . import radtrace as rt
+    key = batch_key(showers, precision)
+    cands = candidates or [list(c) for c in itertools.product(BATCH_BLOCKS, BATCH_AT, BATCH_ITEMS)]
+    sample = showers
+    if sample_tracks is not None:
+        sample = [(d, m, f, t.slice(0, min(t.n, sample_tracks))) for d, m, f, t in showers]
+
+    def measure(c):
+        opt = rt.BatchOptions(block_threads=c[0], max_antennas_per_tile=c[1], items_per_cu=c[2],
+                              direct_launch=1)
+        b = rt.Batch(sample, precision, k, opt)
+        t = time_launches(b.launch, warmup, reps)
+        del b
+        return t
+
+    best, timings, cached = tune(key, cands, measure, TuningCache(cache_path), log)
+    return rt.BatchOptions(block_threads=best[0], max_antennas_per_tile=best[1],
+                           items_per_cu=best[2]), timings, cached
+
+
+# ------------------------------------------------------------------ single plans
+PLAN_BLOCKS = (256, 512, 1024)
+PLAN_PASSES = (1 << 19, 1 << 20, 1 << 21)
+
+
+def plan_key(plan, n_tracks: int) -> str:
+    shapes = [plan.formalism, plan.precision, plan.medium.kind, plan.det.m, plan.det.n_bins,
+              int(n_tracks).bit_length()]
+    return f"plan/{device_key()}/{signature(shapes)}"
+
+
+def tune_plan(plan, tracks, cache_path: Optional[str] = None, candidates=None, warmup: int = 1,
+              reps: int = 2, log=None):
+    """Sets and returns the fastest (antennas_per_block, track_splits,
+    block_threads, bins_per_segment, tracks_per_pass) tiling of a Plan for
+    calls like plan.accumulate(tracks); candidates default to the automatic
+    tile with every block size and pass length above."""
+    key = plan_key(plan, tracks.n)
+    cands = candidates or [[0, 0, b, 0, p] for b in PLAN_BLOCKS for p in PLAN_PASSES]
+    traces = plan.new_traces()
+
+    def measure(c):
+        plan.set_tiling(*c)
+        return time_launches(lambda: plan.accumulate(tracks, traces), warmup, reps)
+
+    best, timings, cached = tune(key, cands, measure, TuningCache(cache_path), log)
+    plan.set_tiling(*best)
+    return list(best), timings, cached

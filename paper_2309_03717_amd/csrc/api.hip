@@ -22,17 +22,66 @@ static int hip_fail(hipError_t e, const char *what) {
   return fail(RT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static int check_tracks(const rt_plan *p, const rt_tracks *t) {
+int rt_check_tracks(const rt_tracks *t, int64_t n_antennas) {
   if (!t) return fail(RT_E_INVALID, "tracks is NULL");
   if (t->n < 0) return fail(RT_E_INVALID, "tracks->n < 0");
   if (t->n == 0) return RT_OK;
   if (!t->x0 || !t->y0 || !t->z0 || !t->t0 || !t->x1 || !t->y1 || !t->z1 || !t->t1 || !t->bx ||
       !t->by || !t->bz || !t->qw)
     return fail(RT_E_INVALID, "a track array pointer is NULL");
-  if ((int64_t)p->det.n_antennas > 0 && t->n > INT64_MAX / p->det.n_antennas)
+  if (n_antennas > 0 && t->n > INT64_MAX / n_antennas)
     return fail(RT_E_INVALID, "n_tracks * n_antennas overflows");
   return RT_OK;
 }
+
+static int check_tracks(const rt_plan *p, const rt_tracks *t) {
+  return rt_check_tracks(t, p->det.n_antennas);
+}
+
+int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, int precision,
+                   double k) {
+  if (!det || !med) return fail(RT_E_INVALID, "detector or medium is NULL");
+  if (det->n_antennas < 1) return fail(RT_E_INVALID, "detector needs at least one antenna");
+  if (!det->x || !det->y || !det->z || !det->t_start)
+    return fail(RT_E_INVALID, "an antenna array pointer is NULL");
+  if (!(det->dt > 0.0) || !is_finite(det->dt)) return fail(RT_E_INVALID, "dt must be finite and > 0");
+  if (det->n_bins < 1) return fail(RT_E_INVALID, "n_bins must be >= 1");
+  if ((int64_t)det->n_bins * 3 > INT32_MAX / 2) return fail(RT_E_UNSUPPORTED, "n_bins too large");
+  if (formalism != RT_ENDPOINT && formalism != RT_ZHS)
+    return fail(RT_E_INVALID, "formalism must be RT_ENDPOINT or RT_ZHS");
+  if (precision != RT_FP64 && precision != RT_MIXED)
+    return fail(RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
+  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL)
+    return fail(RT_E_INVALID, "medium kind must be RT_UNIFORM or RT_EXPONENTIAL");
+  if (!(med->n0_minus_1 >= 0.0) || !is_finite(med->n0_minus_1))
+    return fail(RT_E_INVALID, "n0_minus_1 must be finite and >= 0");
+  if (med->kind == RT_EXPONENTIAL && (!(med->scale_height > 0.0) || !is_finite(med->scale_height)))
+    return fail(RT_E_INVALID, "scale_height must be finite and > 0");
+  if (!is_finite(k)) return fail(RT_E_INVALID, "k must be finite");
+  return RT_OK;
+}
+
+int rt_device_info(int *dev, int *num_cus, size_t *lds_block, size_t *lds_cu) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return fail(RT_E_NO_DEVICE, "no HIP device is available");
+  }
+  if (hipGetDevice(dev) != hipSuccess) return fail(RT_E_NO_DEVICE, "hipGetDevice failed");
+  int cus = 0, lb = 0, lc = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, *dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&lb, hipDeviceAttributeMaxSharedMemoryPerBlock, *dev);
+  if (e == hipSuccess)
+    e = hipDeviceGetAttribute(&lc, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, *dev);
+  if (e != hipSuccess) return hip_fail(e, "querying device attributes");
+  *num_cus = cus > 0 ? cus : 1;
+  *lds_block = (size_t)(lb > 0 ? lb : 65536);
+  *lds_cu = (size_t)(lc > 0 ? lc : (int)*lds_block);
+  return RT_OK;
+}
+
+int rt_fail(int status, const std::string &msg) { return fail(status, msg); }
+int rt_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
 
 extern "C" {
 
@@ -56,39 +105,12 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
                    int precision, double k) {
   if (!plan) return fail(RT_E_INVALID, "plan output pointer is NULL");
   *plan = nullptr;
-  if (!det || !med) return fail(RT_E_INVALID, "detector or medium is NULL");
-  if (det->n_antennas < 1) return fail(RT_E_INVALID, "detector needs at least one antenna");
-  if (!det->x || !det->y || !det->z || !det->t_start)
-    return fail(RT_E_INVALID, "an antenna array pointer is NULL");
-  if (!(det->dt > 0.0) || !is_finite(det->dt)) return fail(RT_E_INVALID, "dt must be finite and > 0");
-  if (det->n_bins < 1) return fail(RT_E_INVALID, "n_bins must be >= 1");
-  if ((int64_t)det->n_bins * 3 > INT32_MAX / 2) return fail(RT_E_UNSUPPORTED, "n_bins too large");
-  if (formalism != RT_ENDPOINT && formalism != RT_ZHS)
-    return fail(RT_E_INVALID, "formalism must be RT_ENDPOINT or RT_ZHS");
-  if (precision != RT_FP64 && precision != RT_MIXED)
-    return fail(RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
-  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL)
-    return fail(RT_E_INVALID, "medium kind must be RT_UNIFORM or RT_EXPONENTIAL");
-  if (!(med->n0_minus_1 >= 0.0) || !is_finite(med->n0_minus_1))
-    return fail(RT_E_INVALID, "n0_minus_1 must be finite and >= 0");
-  if (med->kind == RT_EXPONENTIAL && (!(med->scale_height > 0.0) || !is_finite(med->scale_height)))
-    return fail(RT_E_INVALID, "scale_height must be finite and > 0");
-  if (!is_finite(k)) return fail(RT_E_INVALID, "k must be finite");
-
-  int count = 0;
-  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
-    (void)hipGetLastError();
-    return fail(RT_E_NO_DEVICE, "no HIP device is available");
-  }
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(RT_E_NO_DEVICE, "hipGetDevice failed");
-  int cus = 0, lds_block = 0, lds_cu = 0;
-  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess)
-    e = hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-  if (e == hipSuccess)
-    e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
-  if (e != hipSuccess) return hip_fail(e, "querying device attributes");
+  int st = rt_check_setup(det, med, formalism, precision, k);
+  if (st != RT_OK) return st;
+  int dev = 0, cus = 0;
+  size_t lds_block = 0, lds_cu = 0;
+  st = rt_device_info(&dev, &cus, &lds_block, &lds_cu);
+  if (st != RT_OK) return st;
 
   rt_plan *p = new (std::nothrow) rt_plan();
   if (!p) return fail(RT_E_INVALID, "out of host memory");
@@ -98,9 +120,9 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
   p->precision = precision;
   p->k = k;
   p->device = dev;
-  p->num_cus = cus > 0 ? cus : 1;
-  p->lds_per_block = (size_t)(lds_block > 0 ? lds_block : 65536);
-  p->lds_per_cu = (size_t)(lds_cu > 0 ? lds_cu : (int)p->lds_per_block);
+  p->num_cus = cus;
+  p->lds_per_block = lds_block;
+  p->lds_per_cu = lds_cu;
   p->at_user = p->splits_user = p->block_user = p->seg_user = 0;
   p->pass_user = 0;
   p->ev_start = p->ev_stop = nullptr;

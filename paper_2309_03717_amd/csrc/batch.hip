@@ -1,0 +1,578 @@
+// batch.hip -- many independent showers (each with its own antenna array,
+// time binning, medium, formalism and tracks) in one persistent launch.
+//
+// The host cuts every shower into work items (antenna tile x bin segment x
+// track split) of similar cost and sorts them longest first. A persistent
+// grid (one or more workgroups per compute unit) takes items in that order
+// from an integer atomic counter; each item deposits into an LDS tile exactly
+// as the single-plan kernel does and writes the tile to its own partial slot,
+// so the result does not depend on which workgroup took which item. A merge
+// kernel then adds, per (shower, antenna, segment), the slots of the splits in
+// index order into the shower's traces (with the ZHS prefix scan). On a
+// non-null stream the whole sequence is captured once into a HIP graph and
+// replayed by later launches.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "rt_deposit.h"
+#include "rt_internal.h"
+
+namespace rt {
+
+struct ShowerDesc {
+  TrackPtrs tr;
+  AntPtrs an;
+  Consts c;
+  void *traces;
+  int32_t formalism, at, seg_len, n_segs, n_atiles, splits;
+  int64_t rec_block0;        // first wave block of this shower in the record array
+  int64_t n_blocks;          // wave blocks of 64 tracks of this shower
+  int64_t blocks_per_split;
+  int64_t part0;             // first double of this shower's partial slots
+  int64_t slot_len;          // doubles per slot: at * seg_len * 3
+};
+
+struct WorkItem {
+  int32_t shower, atile, seg, split;
+};
+
+struct MergeTask {
+  int32_t shower, antenna, seg, pad;
+};
+
+struct BatchArgs {
+  const ShowerDesc *sh;
+  const WorkItem *items;
+  const MergeTask *merges;
+  const int64_t *cum_blocks;   // [n_showers + 1] first wave block of each shower
+  int32_t n_showers, n_items;
+  int *counter;
+  double *rec;
+  double *partial;
+  int64_t total_blocks;
+};
+
+__global__ void batch_reset_kernel(int *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// Records of every shower, one thread per padded track.
+template <int P>
+__global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
+  const int64_t n_pad = b.total_blocks * 64;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_pad;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = g >> 6;
+    int lo = 0, hi = b.n_showers;   // cum[lo] <= blk < cum[hi]
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if (b.cum_blocks[mid] <= blk) lo = mid; else hi = mid;
+    }
+    const ShowerDesc &s = b.sh[lo];
+    const int64_t i = g - s.rec_block0 * 64;
+    const Consts c = s.c;
+    const double z_ref = s.an.z[0];
+    const double e_ref = c.medium == 1 ? height_factor(z_ref, c) : 0.0;
+    double v[kRec];
+    if (s.formalism == RT_ENDPOINT)
+      make_record<0, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
+    else
+      make_record<1, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
+    double *out = b.rec + (blk * kRec) * 64 + (g & 63);
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) out[f * 64] = v[f];
+  }
+}
+
+// The deposits of one work item into the LDS tile.
+template <int F, int P, int MED, int AT>
+__device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int64_t b_end,
+                                         const AntPtrs &an, const Consts &c, acc_t *tile,
+                                         int64_t a_begin, int n_ant, int row_len, int lo,
+                                         int hi) {
+  Tile<AT> t;
+  load_tile<AT, MED>(an, a_begin, n_ant, c, t);
+  const uint64_t mask = (1ull << n_ant) - 1;
+  const int64_t waves = blockDim.x >> 6;
+  deposit_blocks<F, P, MED, AT>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo, hi,
+                                (double)lo, (double)hi, c);
+}
+
+template <int F, int P, int MED>
+__device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b_first,
+                                            int64_t b_end, const AntPtrs &an, const Consts &c,
+                                            acc_t *tile, int64_t a_begin, int n_ant, int row_len,
+                                            int lo, int hi) {
+  if (at == 1)
+    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+  else if (at == 2)
+    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+  else
+    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+}
+
+// Persistent workgroups: take items until the counter passes the last one.
+// Every workgroup leaves the loop once the counter has handed out n_items
+// indices, so the grid always drains. The runtime switch over formalism,
+// medium and tile width keeps the union of their live registers, hence at
+// most 512 threads per workgroup (about 200 VGPRs, two waves per SIMD).
+template <int P>
+__global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  acc_t *tile = reinterpret_cast<acc_t *>(smem);
+  __shared__ int cur;
+  for (;;) {
+    __syncthreads();   // everyone has read cur and flushed the previous tile
+    if (threadIdx.x == 0) cur = atomicAdd(b.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(cur);
+    if (it >= b.n_items) break;
+    const WorkItem w = b.items[it];
+    const ShowerDesc &sd = b.sh[w.shower];
+    const Consts c = sd.c;
+    const AntPtrs an = sd.an;
+    const int at = sd.at, seg_len = sd.seg_len;
+    const int64_t a_begin = (int64_t)w.atile * at;
+    const int n_ant = (int)min((int64_t)at, an.m - a_begin);
+    const int lo = w.seg * seg_len;
+    const int hi = min(lo + seg_len, c.n_bins);
+    const int row_len = (hi - lo) * 3;
+    for (int i = threadIdx.x; i < at * row_len; i += blockDim.x) tile[i] = 0.0;
+    __syncthreads();
+    const double *rec = b.rec + sd.rec_block0 * (kRec * 64);
+    const int64_t b_first = (int64_t)w.split * sd.blocks_per_split + (threadIdx.x >> 6);
+    const int64_t b_end = min(sd.n_blocks, (int64_t)(w.split + 1) * sd.blocks_per_split);
+    const int kind = sd.formalism * 2 + c.medium;
+    if (kind == 0)
+      run_item_at<0, P, 0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    else if (kind == 1)
+      run_item_at<0, P, 1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    else if (kind == 2)
+      run_item_at<1, P, 0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    else
+      run_item_at<1, P, 1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    __syncthreads();
+    const int64_t slot = ((int64_t)w.atile * sd.n_segs + w.seg) * sd.splits + w.split;
+    acc_t *dst = b.partial + sd.part0 + slot * sd.slot_len;
+    for (int a = 0; a < n_ant; ++a)
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x)
+        dst[(int64_t)a * seg_len * 3 + i] = tile[a * row_len + i];
+  }
+}
+
+// One workgroup per (shower, antenna, segment): traces += sum over the
+// shower's splits (in index order) of the slots; ZHS differences are
+// prefix-scanned over the segment first.
+template <int P>
+__global__ void __launch_bounds__(256) batch_merge_kernel(BatchArgs b) {
+  using T = typename Prec<P>::out;
+  const MergeTask mt = b.merges[blockIdx.x];
+  const ShowerDesc &s = b.sh[mt.shower];
+  const int atile = mt.antenna / s.at, ai = mt.antenna % s.at;
+  const int lo = mt.seg * s.seg_len;
+  const int nb = min(lo + s.seg_len, s.c.n_bins) - lo;
+  const int splits = s.splits;
+  const int64_t stride = s.slot_len;
+  const acc_t *part = b.partial + s.part0 + ((int64_t)atile * s.n_segs + mt.seg) * splits * stride +
+                      (int64_t)ai * s.seg_len * 3;
+  T *out = reinterpret_cast<T *>(s.traces) + ((size_t)mt.antenna * s.c.n_bins + lo) * 3;
+  if (s.formalism == RT_ENDPOINT) {
+    for (int i = threadIdx.x; i < nb * 3; i += blockDim.x) {
+      double v = 0.0;
+      for (int sp = 0; sp < splits; ++sp) v += part[sp * stride + i];
+      out[i] = (T)((double)out[i] + v);
+    }
+    return;
+  }
+  __shared__ double carry[256][3];
+  const int per = (nb + blockDim.x - 1) / blockDim.x;
+  const int b0 = min((int)threadIdx.x * per, nb), b1 = min(b0 + per, nb);
+  double run[3] = {0.0, 0.0, 0.0};
+  for (int q = b0; q < b1; ++q)
+    for (int c = 0; c < 3; ++c)
+      for (int sp = 0; sp < splits; ++sp) run[c] += part[sp * stride + 3 * q + c];
+  for (int c = 0; c < 3; ++c) carry[threadIdx.x][c] = run[c];
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double acc = 0.0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      double x = carry[t][threadIdx.x];
+      carry[t][threadIdx.x] = acc;
+      acc += x;
+    }
+  }
+  __syncthreads();
+  for (int c = 0; c < 3; ++c) run[c] = carry[threadIdx.x][c];
+  for (int q = b0; q < b1; ++q)
+    for (int c = 0; c < 3; ++c) {
+      double d = 0.0;
+      for (int sp = 0; sp < splits; ++sp) d += part[sp * stride + 3 * q + c];
+      run[c] += d;
+      out[3 * q + c] = (T)((double)out[3 * q + c] + run[c]);
+    }
+}
+
+}  // namespace rt
+
+// ------------------------------------------------------------------ host side
+
+struct rt_batch {
+  int precision = 0;
+  int device = 0;
+  int block = 512;
+  int grid = 1;
+  bool direct = false;
+  size_t lds_bytes = 0;
+  std::vector<rt::ShowerDesc> sh;
+  std::vector<rt::WorkItem> items;
+  std::vector<rt::MergeTask> merges;
+  std::vector<int64_t> cum;
+  int64_t total_blocks = 0, total_partial = 0, total_pairs = 0;
+  rt::ShowerDesc *d_sh = nullptr;
+  rt::WorkItem *d_items = nullptr;
+  rt::MergeTask *d_merges = nullptr;
+  int64_t *d_cum = nullptr;
+  int *d_counter = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void *cap_ws = nullptr;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+};
+
+namespace rt {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t record_bytes(const rt_batch &b) {
+  return align256((size_t)b.total_blocks * kRec * 64 * sizeof(double));
+}
+
+size_t batch_workspace_bytes(const rt_batch &b) {
+  return record_bytes(b) + align256((size_t)b.total_partial * sizeof(acc_t));
+}
+
+static BatchArgs batch_args(const rt_batch &b, void *workspace) {
+  BatchArgs a;
+  a.sh = b.d_sh;
+  a.items = b.d_items;
+  a.merges = b.d_merges;
+  a.cum_blocks = b.d_cum;
+  a.n_showers = (int32_t)b.sh.size();
+  a.n_items = (int32_t)b.items.size();
+  a.counter = b.d_counter;
+  char *ws = reinterpret_cast<char *>(workspace);
+  a.rec = reinterpret_cast<double *>(ws);
+  a.partial = reinterpret_cast<double *>(ws + record_bytes(b));
+  a.total_blocks = b.total_blocks;
+  return a;
+}
+
+static void *deposit_fn(int precision) {
+  return precision == RT_FP64 ? (void *)batch_deposit_kernel<0> : (void *)batch_deposit_kernel<1>;
+}
+
+// reset counter, records, persistent deposit, merge
+static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t stream,
+                                hipEvent_t ev0, hipEvent_t ev1) {
+  if (b.items.empty()) return hipSuccess;
+  BatchArgs a = batch_args(b, workspace);
+  batch_reset_kernel<<<1, 64, 0, stream>>>(b.d_counter);
+  const unsigned pblocks = (unsigned)std::min<int64_t>((b.total_blocks * 64 + 255) / 256, 1 << 16);
+  if (b.precision == RT_FP64)
+    batch_prepare_kernel<0><<<pblocks, 256, 0, stream>>>(a);
+  else
+    batch_prepare_kernel<1><<<pblocks, 256, 0, stream>>>(a);
+  if (ev0) (void)hipEventRecord(ev0, stream);
+  if (b.precision == RT_FP64)
+    batch_deposit_kernel<0><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+  else
+    batch_deposit_kernel<1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+  if (ev1) (void)hipEventRecord(ev1, stream);
+  if (b.precision == RT_FP64)
+    batch_merge_kernel<0><<<(unsigned)b.merges.size(), 256, 0, stream>>>(a);
+  else
+    batch_merge_kernel<1><<<(unsigned)b.merges.size(), 256, 0, stream>>>(a);
+  return hipGetLastError();
+}
+
+// Tiles, splits, work items and merge tasks of a batch. Returns "" or an
+// error text.
+static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, int precision,
+                              double k, const rt_batch_options *opt, int num_cus,
+                              size_t lds_block, size_t lds_cu) {
+  b.precision = precision;
+  b.block = (opt && opt->block_threads > 0) ? opt->block_threads : 512;
+  b.direct = opt && opt->direct_launch != 0;
+  const int items_per_cu = (opt && opt->items_per_cu > 0) ? opt->items_per_cu : 4;
+  const int at_cap = (opt && opt->max_antennas_per_tile > 0) ? opt->max_antennas_per_tile : 3;
+  const size_t row_bytes = 3 * sizeof(acc_t);
+  const size_t budget = lds_block - 256;   // room for the kernel's own LDS words
+  const int max_bins = (int)(budget / row_bytes) / 64 * 64;
+  b.sh.resize(n);
+  int64_t max_slot = 0;
+  for (int s = 0; s < n; ++s) {
+    const rt_shower &in = showers[s];
+    ShowerDesc &d = b.sh[s];
+    const int B = in.det.n_bins;
+    const rt_tiling *user = (opt && opt->per_shower) ? &opt->per_shower[s] : nullptr;
+    int seg = user && user->bins_per_segment > 0 ? std::min(user->bins_per_segment, B) : B;
+    if (seg > max_bins) {   // equal segments, multiples of 64
+      int segs = (B + max_bins - 1) / max_bins;
+      seg = ((B + segs - 1) / segs + 63) / 64 * 64;
+    }
+    int at = user && user->antennas_per_block > 0 ? user->antennas_per_block
+                                                  : std::min<int>(at_cap, (int)(budget / ((size_t)seg * row_bytes)));
+    at = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)at, 3, in.det.n_antennas}));
+    if ((size_t)at * seg * row_bytes > budget)
+      return "the LDS tile of shower " + std::to_string(s) + " does not fit";
+    d.tr = track_ptrs(in.tracks);
+    d.an = ant_ptrs(in.det);
+    d.traces = in.traces;
+    d.formalism = in.formalism;
+    d.at = at;
+    d.seg_len = seg;
+    d.n_segs = (B + seg - 1) / seg;
+    d.n_atiles = (int)((in.det.n_antennas + at - 1) / at);
+    d.n_blocks = (in.tracks.n + 63) / 64;
+    d.slot_len = (int64_t)at * seg * 3;
+    Consts &c = d.c;
+    c.inv_c = 1.0 / 299792458.0;
+    c.inv_dt = 1.0 / in.det.dt;
+    c.k = k;
+    c.n_uniform = 1.0 + in.med.n0_minus_1;
+    c.n0m1 = in.med.n0_minus_1;
+    c.h = in.med.kind == RT_EXPONENTIAL ? in.med.scale_height : 1.0;
+    c.n0h = c.n0m1 * c.h;
+    c.nbins_d = (double)B;
+    c.n_bins = B;
+    c.medium = in.med.kind;
+    if (d.n_blocks > 0) max_slot = std::max(max_slot, d.slot_len);
+    b.total_pairs += in.tracks.n * in.det.n_antennas;
+  }
+  b.lds_bytes = (size_t)std::max<int64_t>(max_slot, 1) * sizeof(acc_t);
+  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(lds_cu / (b.lds_bytes + 256),
+                                                               512 / b.block));
+  b.grid = num_cus * per_cu;
+  // Track splits: items of similar cost (track x antenna evaluations, which
+  // every bin segment repeats), about items_per_cu of them per compute unit.
+  double total_cost = 0.0;
+  for (const ShowerDesc &d : b.sh)
+    total_cost += (double)d.n_blocks * 64 * d.at * d.n_atiles * d.n_segs;
+  const double target = std::max(1.0, total_cost / ((double)b.grid * items_per_cu));
+  b.cum.assign(n + 1, 0);
+  for (int s = 0; s < n; ++s) {
+    ShowerDesc &d = b.sh[s];
+    const rt_tiling *user = (opt && opt->per_shower) ? &opt->per_shower[s] : nullptr;
+    int64_t splits = user && user->track_splits > 0
+                         ? user->track_splits
+                         : (int64_t)std::ceil((double)d.n_blocks * 64 * d.at / target);
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, d.n_blocks));
+    d.blocks_per_split = std::max<int64_t>(1, (d.n_blocks + splits - 1) / splits);
+    d.splits = d.n_blocks == 0 ? 0 : (int32_t)((d.n_blocks + d.blocks_per_split - 1) / d.blocks_per_split);
+    d.rec_block0 = b.cum[s];
+    b.cum[s + 1] = b.cum[s] + d.n_blocks;
+    d.part0 = b.total_partial;
+    b.total_partial += (int64_t)d.n_atiles * d.n_segs * d.splits * d.slot_len;
+  }
+  b.total_blocks = b.cum[n];
+  // Work items, longest first; equal costs keep shower order, so the items
+  // of one shower run side by side and share its records in the caches.
+  std::vector<std::pair<int64_t, WorkItem>> all;
+  for (int s = 0; s < n; ++s) {
+    const ShowerDesc &d = b.sh[s];
+    for (int t = 0; t < d.n_atiles; ++t)
+      for (int g = 0; g < d.n_segs; ++g)
+        for (int p = 0; p < d.splits; ++p) {
+          int64_t blocks = std::min<int64_t>(d.n_blocks, (int64_t)(p + 1) * d.blocks_per_split) -
+                           (int64_t)p * d.blocks_per_split;
+          int64_t ants = std::min<int64_t>(d.at, d.an.m - (int64_t)t * d.at);
+          all.push_back({blocks * ants, WorkItem{s, t, g, p}});
+        }
+  }
+  if (all.size() > (size_t)INT32_MAX - 1024) return "too many work items";
+  std::stable_sort(all.begin(), all.end(),
+                   [](const std::pair<int64_t, WorkItem> &x, const std::pair<int64_t, WorkItem> &y) {
+                     return x.first > y.first;
+                   });
+  b.items.reserve(all.size());
+  for (auto &x : all) b.items.push_back(x.second);
+  for (int s = 0; s < n; ++s) {
+    if (b.sh[s].n_blocks == 0) continue;
+    for (int64_t a = 0; a < b.sh[s].an.m; ++a)
+      for (int g = 0; g < b.sh[s].n_segs; ++g) b.merges.push_back(MergeTask{s, (int32_t)a, g, 0});
+  }
+  if (b.merges.size() > (size_t)INT32_MAX) return "too many merge tasks";
+  return "";
+}
+
+template <class T>
+static hipError_t upload(T **dst, const std::vector<T> &src) {
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+static void release(rt_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  (void)hipFree(b->d_sh);
+  (void)hipFree(b->d_items);
+  (void)hipFree(b->d_merges);
+  (void)hipFree(b->d_cum);
+  (void)hipFree(b->d_counter);
+  delete b;
+}
+
+}  // namespace rt
+
+extern "C" {
+
+int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_showers, int precision,
+                    double k, const rt_batch_options *options) {
+  if (!batch) return rt_fail(RT_E_INVALID, "batch output pointer is NULL");
+  *batch = nullptr;
+  if (!showers || n_showers < 1) return rt_fail(RT_E_INVALID, "need at least one shower");
+  if (options) {
+    const int bt = options->block_threads;
+    if (bt != 0 && (bt < 64 || bt > 512 || bt % 64))
+      return rt_fail(RT_E_INVALID, "block_threads must be a multiple of 64 in [64, 512]");
+    if (options->items_per_cu < 0) return rt_fail(RT_E_INVALID, "items_per_cu must be >= 0");
+    if (options->max_antennas_per_tile < 0 || options->max_antennas_per_tile > 3)
+      return rt_fail(RT_E_INVALID, "max_antennas_per_tile must be in [0, 3]");
+  }
+  for (int32_t s = 0; s < n_showers; ++s) {
+    const rt_shower &sh = showers[s];
+    const std::string where = "shower " + std::to_string(s) + ": ";
+    int st = rt_check_setup(&sh.det, &sh.med, sh.formalism, precision, k);
+    if (st == RT_OK) st = rt_check_tracks(&sh.tracks, sh.det.n_antennas);
+    if (st != RT_OK) return rt_fail(st, where + rt_last_error());
+    if (sh.tracks.n >= ((int64_t)1 << 31))
+      return rt_fail(RT_E_UNSUPPORTED, where + "at most 2^31 - 1 tracks per shower");
+    if (sh.tracks.n > 0 && !sh.traces) return rt_fail(RT_E_INVALID, where + "traces is NULL");
+    if (options && options->per_shower) {
+      const rt_tiling &t = options->per_shower[s];
+      if (t.antennas_per_block < 0 || t.antennas_per_block > 3 || t.track_splits < 0 ||
+          t.bins_per_segment < 0 ||
+          (t.bins_per_segment > 0 && t.bins_per_segment % 64 && t.bins_per_segment != sh.det.n_bins))
+        return rt_fail(RT_E_INVALID, where + "per-shower tiling out of range (antennas_per_block "
+                                             "0-3, bins_per_segment a multiple of 64 or n_bins)");
+    }
+  }
+  int dev = 0, cus = 0;
+  size_t lds_block = 0, lds_cu = 0;
+  int st = rt_device_info(&dev, &cus, &lds_block, &lds_cu);
+  if (st != RT_OK) return st;
+  rt_batch *b = new (std::nothrow) rt_batch();
+  if (!b) return rt_fail(RT_E_INVALID, "out of host memory");
+  b->device = dev;
+  std::string err = rt::batch_plan(*b, showers, n_showers, precision, k, options, cus, lds_block,
+                                   lds_cu);
+  if (!err.empty()) {
+    delete b;
+    return rt_fail(RT_E_UNSUPPORTED, err);
+  }
+  (void)hipGetLastError();
+  hipError_t e = rt::upload(&b->d_sh, b->sh);
+  if (e == hipSuccess) e = rt::upload(&b->d_items, b->items);
+  if (e == hipSuccess) e = rt::upload(&b->d_merges, b->merges);
+  if (e == hipSuccess) e = rt::upload(&b->d_cum, b->cum);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, sizeof(int));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(rt::deposit_fn(precision), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)b->lds_bytes);
+  if (e == hipSuccess && !b->direct) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    rt::release(b);
+    return rt_hip_fail(e, "setting up the batch tables");
+  }
+  *batch = b;
+  return RT_OK;
+}
+
+int rt_batch_destroy(rt_batch *batch) {
+  if (batch) rt::release(batch);
+  return RT_OK;
+}
+
+int rt_batch_workspace_bytes(const rt_batch *batch, size_t *bytes) {
+  if (!batch || !bytes) return rt_fail(RT_E_INVALID, "batch or bytes is NULL");
+  *bytes = rt::batch_workspace_bytes(*batch);
+  return RT_OK;
+}
+
+int rt_batch_get_info(const rt_batch *batch, int64_t *n_items, int32_t *n_workgroups,
+                      int64_t *lds_bytes, int64_t *pairs) {
+  if (!batch) return rt_fail(RT_E_INVALID, "batch is NULL");
+  if (n_items) *n_items = (int64_t)batch->items.size();
+  if (n_workgroups) *n_workgroups = batch->grid;
+  if (lds_bytes) *lds_bytes = (int64_t)batch->lds_bytes;
+  if (pairs) *pairs = batch->total_pairs;
+  return RT_OK;
+}
+
+int rt_batch_set_timing_events(rt_batch *batch, void *start_event, void *stop_event) {
+  if (!batch) return rt_fail(RT_E_INVALID, "batch is NULL");
+  if ((start_event == nullptr) != (stop_event == nullptr))
+    return rt_fail(RT_E_INVALID, "give both events or neither");
+  batch->ev_start = (hipEvent_t)start_event;
+  batch->ev_stop = (hipEvent_t)stop_event;
+  return RT_OK;
+}
+
+int rt_batch_launch(rt_batch *batch, void *workspace, size_t workspace_bytes, void *stream) {
+  if (!batch) return rt_fail(RT_E_INVALID, "batch is NULL");
+  const size_t need = rt::batch_workspace_bytes(*batch);
+  if (need > 0 && (!workspace || workspace_bytes < need))
+    return rt_fail(RT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
+                                       std::to_string(workspace ? workspace_bytes : 0));
+  if (batch->items.empty()) return RT_OK;   // every shower is empty
+  hipStream_t s = (hipStream_t)stream;
+  (void)hipGetLastError();
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (s) {
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return rt_hip_fail(e, "querying the stream's capture state");
+  }
+  const bool timed = batch->ev_start != nullptr;
+  if (batch->direct || timed || cap != hipStreamCaptureStatusNone) {
+    hipError_t e = rt::batch_enqueue(*batch, workspace, s, batch->ev_start, batch->ev_stop);
+    batch->ev_start = batch->ev_stop = nullptr;
+    if (e != hipSuccess) return rt_hip_fail(e, "launching the batch kernels");
+    return RT_OK;
+  }
+  if (!batch->exec || batch->cap_ws != workspace) {
+    if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+    if (batch->graph) (void)hipGraphDestroy(batch->graph);
+    batch->exec = nullptr;
+    batch->graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(batch->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return rt_hip_fail(e, "beginning the graph capture");
+    hipError_t el = rt::batch_enqueue(*batch, workspace, batch->cap_stream, nullptr, nullptr);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(batch->cap_stream, &g);
+    if (el != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rt_hip_fail(el != hipSuccess ? el : e, "capturing the batch kernels");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return rt_hip_fail(e, "instantiating the batch graph");
+    }
+    batch->graph = g;
+    batch->exec = x;
+    batch->cap_ws = workspace;
+  }
+  hipError_t e = hipGraphLaunch(batch->exec, s);
+  if (e != hipSuccess) return rt_hip_fail(e, "launching the batch graph");
+  return RT_OK;
+}
+
+}  // extern "C"

@@ -67,5 +67,13 @@ hipError_t launch_propagate(const rt_plan &p, const rt_tracks &t, double *t_arri
 
 }  // namespace rt
 
-// Thread-local error text (api.hip).
+// Thread-local error text and shared argument checks (api.hip). The checks
+// set the error text and return an rt_status.
 void rt_set_error(const std::string &msg);
+int rt_fail(int status, const std::string &msg);
+int rt_hip_fail(hipError_t e, const char *what);
+int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, int precision,
+                   double k);
+int rt_check_tracks(const rt_tracks *t, int64_t n_antennas);
+// Current device, its compute units and LDS bytes per workgroup and per CU.
+int rt_device_info(int *dev, int *num_cus, size_t *lds_block, size_t *lds_cu);

@@ -61,6 +61,17 @@ class rt_tiling(C.Structure):
                 self.bins_per_segment, self.tracks_per_pass)
 
 
+class rt_shower(C.Structure):
+    _fields_ = [("det", rt_detector), ("med", rt_medium), ("formalism", C.c_int32),
+                ("tracks", rt_tracks), ("traces", C.c_void_p)]
+
+
+class rt_batch_options(C.Structure):
+    _fields_ = [("block_threads", C.c_int32), ("items_per_cu", C.c_int32),
+                ("max_antennas_per_tile", C.c_int32), ("direct_launch", C.c_int32),
+                ("per_shower", C.POINTER(rt_tiling))]
+
+
 _P = C.c_void_p
 _lib.rt_abi_version.restype = C.c_int
 _lib.rt_status_string.restype = C.c_char_p
@@ -77,6 +88,14 @@ _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
 _lib.rt_plan_set_timing_events.argtypes = [_P, _P, _P]
 _lib.rt_plan_vjp_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_zhs_vjp.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P, _P, _P, _P, C.c_size_t, _P]
+_lib.rt_batch_create.argtypes = [C.POINTER(_P), C.POINTER(rt_shower), C.c_int32, C.c_int,
+                                 C.c_double, C.POINTER(rt_batch_options)]
+_lib.rt_batch_destroy.argtypes = [_P]
+_lib.rt_batch_workspace_bytes.argtypes = [_P, C.POINTER(C.c_size_t)]
+_lib.rt_batch_get_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+_lib.rt_batch_launch.argtypes = [_P, _P, C.c_size_t, _P]
+_lib.rt_batch_set_timing_events.argtypes = [_P, _P, _P]
 
 
 class RadtraceError(RuntimeError):
@@ -225,16 +244,19 @@ def rt_accumulate(plan: int, tracks: rt_tracks, traces: torch.Tensor, workspace:
            "rt_accumulate")
 
 
+def _event_handle(ev):
+    if ev is None or isinstance(ev, int):
+        return ev
+    if not ev.cuda_event:   # torch creates events lazily: force creation
+        ev.record()
+    return ev.cuda_event
+
+
 def rt_plan_set_timing_events(plan: int, start_event, stop_event) -> None:
     """start_event / stop_event: torch.cuda.Event (timing enabled) or raw
     hipEvent_t handles; None clears."""
-    def handle(ev):
-        if ev is None or isinstance(ev, int):
-            return ev
-        if not ev.cuda_event:   # torch creates events lazily: force creation
-            ev.record()
-        return ev.cuda_event
-    _check(_lib.rt_plan_set_timing_events(plan, handle(start_event), handle(stop_event)),
+    _check(_lib.rt_plan_set_timing_events(plan, _event_handle(start_event),
+                                          _event_handle(stop_event)),
            "rt_plan_set_timing_events")
 
 
@@ -258,6 +280,48 @@ def rt_zhs_vjp(plan: int, tracks: rt_tracks, grad_traces: torch.Tensor, grad_qw:
                            _ptr(grad_p1), _ptr(grad_n0m1), _ptr(workspace),
                            workspace.numel() * workspace.element_size(), _stream(stream)),
            "rt_zhs_vjp")
+
+
+def rt_batch_create(showers, precision: int, k: float, options: Optional[rt_batch_options] = None
+                    ) -> int:
+    """showers: a sequence of rt_shower structs."""
+    arr = (rt_shower * len(showers))(*showers)
+    handle = _P()
+    _check(_lib.rt_batch_create(C.byref(handle), arr, len(showers), precision, float(k),
+                                C.byref(options) if options is not None else None),
+           "rt_batch_create")
+    return handle.value
+
+
+def rt_batch_destroy(batch: int) -> None:
+    _check(_lib.rt_batch_destroy(batch), "rt_batch_destroy")
+
+
+def rt_batch_workspace_bytes(batch: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.rt_batch_workspace_bytes(batch, C.byref(b)), "rt_batch_workspace_bytes")
+    return b.value
+
+
+def rt_batch_get_info(batch: int) -> dict:
+    items, lds, pairs = C.c_int64(), C.c_int64(), C.c_int64()
+    wgs = C.c_int32()
+    _check(_lib.rt_batch_get_info(batch, C.byref(items), C.byref(wgs), C.byref(lds),
+                                  C.byref(pairs)), "rt_batch_get_info")
+    return {"items": items.value, "workgroups": wgs.value, "lds_bytes": lds.value,
+            "pairs": pairs.value}
+
+
+def rt_batch_launch(batch: int, workspace: Optional[torch.Tensor], stream=None) -> None:
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(_lib.rt_batch_launch(batch, _ptr(workspace), nbytes, _stream(stream)),
+           "rt_batch_launch")
+
+
+def rt_batch_set_timing_events(batch: int, start_event, stop_event) -> None:
+    _check(_lib.rt_batch_set_timing_events(batch, _event_handle(start_event),
+                                           _event_handle(stop_event)),
+           "rt_batch_set_timing_events")
 
 
 # ------------------------------------------------------------------ convenience
@@ -335,3 +399,78 @@ class Plan:
         b = torch.empty(shape, dtype=torch.int32, device=self.det.x.device)
         rt_propagate(self.handle, tracks.struct(self.precision), t, b, stream)
         return t, b
+
+
+def _medium_struct(medium) -> rt_medium:
+    kind = RT_UNIFORM if medium.kind == "uniform" else RT_EXPONENTIAL
+    return rt_medium(kind, float(medium.n0m1), float(medium.h))
+
+
+@dataclass
+class BatchOptions:
+    """Launch shape of a batch (rt_batch_options); 0 keeps the automatic
+    choice. per_shower: None or a list of (antennas_per_block, track_splits,
+    bins_per_segment) per shower."""
+    block_threads: int = 0
+    items_per_cu: int = 0
+    max_antennas_per_tile: int = 0
+    direct_launch: int = 0
+    per_shower: Optional[list] = None
+
+    def struct(self):
+        o = rt_batch_options(self.block_threads, self.items_per_cu, self.max_antennas_per_tile,
+                             self.direct_launch, None)
+        keep = None
+        if self.per_shower is not None:
+            keep = (rt_tiling * len(self.per_shower))(
+                *[rt_tiling(a, s, 0, b, 0) for a, s, b in self.per_shower])
+            o.per_shower = C.cast(keep, C.POINTER(rt_tiling))
+        return o, keep
+
+
+class Batch:
+    """Many showers in one persistent launch (rt_batch_*). showers: a list of
+    (DeviceDetector, medium, formalism name, DeviceTracks). The batch owns one
+    trace tensor per shower (zeroed at construction; launches add to them) and
+    its workspace; it keeps references to every input tensor."""
+
+    def __init__(self, showers, precision: str = "mixed", k: float = 1.0,
+                 options: Optional[BatchOptions] = None):
+        self.precision = PRECISION[precision]
+        self.dtype = torch.float64 if self.precision == RT_FP64 else torch.float32
+        self.inputs = list(showers)
+        self.options = options or BatchOptions()
+        self.traces = []
+        structs = []
+        for det, medium, formalism, tracks in self.inputs:
+            tr = torch.zeros((det.m, det.n_bins, 3), dtype=self.dtype, device=det.x.device)
+            self.traces.append(tr)
+            structs.append(rt_shower(det.struct(), _medium_struct(medium), FORMALISM[formalism],
+                                     tracks.struct(self.precision), _ptr(tr)))
+        opt, keep = self.options.struct()
+        self.handle = rt_batch_create(structs, self.precision, k, opt)
+        self.info = rt_batch_get_info(self.handle)
+        need = rt_batch_workspace_bytes(self.handle)
+        device = self.traces[0].device if self.traces else "cuda"
+        self.workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.rt_batch_destroy(h)
+            self.handle = None
+
+    @property
+    def pairs(self) -> int:
+        return self.info["pairs"]
+
+    def zero_traces(self):
+        for t in self.traces:
+            t.zero_()
+
+    def launch(self, stream=None):
+        rt_batch_launch(self.handle, self.workspace, stream)
+        return self.traces
+
+    def set_timing_events(self, start_event, stop_event):
+        rt_batch_set_timing_events(self.handle, start_event, stop_event)

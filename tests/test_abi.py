@@ -106,3 +106,67 @@ def test_null_plan_arguments(rt):
     tr = rt.rt_tracks()
     assert rt._lib.rt_accumulate(None, C.byref(tr), None, None, 0, None) == rt.RT_E_INVALID
     assert rt._lib.rt_propagate(None, C.byref(tr), None, None, None) == rt.RT_E_INVALID
+
+
+def _shower(rt):
+    det, keep = _detector(rt)
+    med = rt.rt_medium(rt.RT_UNIFORM, 2.92e-4, 8000.0)
+    return rt.rt_shower(det, med, rt.RT_ENDPOINT, rt.rt_tracks(), None), keep
+
+
+@pytest.mark.parametrize("case", ["null_showers", "zero_showers", "bad_block", "bad_at",
+                                  "bad_items", "bad_detector", "bad_formalism", "null_traces",
+                                  "bad_per_shower", "bad_precision"])
+def test_batch_create_rejects_invalid_arguments(rt, case):
+    sh, keep = _shower(rt)
+    arr = (rt.rt_shower * 2)(sh, sh)
+    n, precision = 2, rt.RT_MIXED
+    opt = rt.rt_batch_options()
+    tl = (rt.rt_tiling * 2)()
+    if case == "null_showers":
+        arr = None
+    elif case == "zero_showers":
+        n = 0
+    elif case == "bad_block":
+        opt.block_threads = 1024
+    elif case == "bad_at":
+        opt.max_antennas_per_tile = 4
+    elif case == "bad_items":
+        opt.items_per_cu = -1
+    elif case == "bad_detector":
+        arr[1].det.dt = -1.0
+    elif case == "bad_formalism":
+        arr[0].formalism = 3
+    elif case == "null_traces":
+        buf = (C.c_double * 1)()
+        arr[1].tracks = rt.rt_tracks(1, *([C.addressof(buf)] * 12))
+    elif case == "bad_per_shower":
+        tl[1].bins_per_segment = 100
+        opt.per_shower = C.cast(tl, C.POINTER(rt.rt_tiling))
+    elif case == "bad_precision":
+        precision = 2
+    handle = C.c_void_p()
+    st = rt._lib.rt_batch_create(C.byref(handle), arr, n, precision, 1.0, C.byref(opt))
+    assert st == rt.RT_E_INVALID, rt.rt_last_error()
+    assert handle.value is None
+    if case in ("bad_detector", "null_traces", "bad_per_shower"):
+        assert rt.rt_last_error().startswith("shower 1:")
+
+
+def test_batch_create_without_gpu_reports_no_device(rt):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    sh, keep = _shower(rt)
+    handle = C.c_void_p()
+    st = rt._lib.rt_batch_create(C.byref(handle), C.byref(sh), 1, rt.RT_FP64, 1.0, None)
+    assert st == rt.RT_E_NO_DEVICE
+
+
+def test_null_batch_arguments(rt):
+    assert rt._lib.rt_batch_destroy(None) == rt.RT_OK
+    assert rt._lib.rt_batch_launch(None, None, 0, None) == rt.RT_E_INVALID
+    b = C.c_size_t()
+    assert rt._lib.rt_batch_workspace_bytes(None, C.byref(b)) == rt.RT_E_INVALID
+    assert rt._lib.rt_batch_get_info(None, None, None, None, None) == rt.RT_E_INVALID
+    assert rt._lib.rt_batch_set_timing_events(None, None, None) == rt.RT_E_INVALID
