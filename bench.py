@@ -7,6 +7,9 @@ precision (FP64 arrival time and bins, FP32 amplitudes and traces); one step
 is the Endpoint pass plus the ZHS pass over all tracks. The metric is
 antenna-track pairs per second over both formalisms.
 
+With --workload batched it measures instead 256 independent showers in one
+persistent, graph-replayed launch per step (launch shape from the autotuner).
+
 Prints one JSON line on stdout (progress goes to stderr). The roofline entry
 is for the dominant deposit kernel, timed with HIP events recorded on its own
 stream around every launch; the CPU baseline is the FP64 oracle on a bounded
@@ -107,6 +110,138 @@ def cpu_baseline(workload, n_sample):
             "seconds": {k: round(v, 3) for k, v in secs.items()}}
 
 
+def shower_ops(rt, dev_showers, n_sample=2048):
+    """Algorithmic FP64 and FP32 operations of a batch, from each shower's own
+    in-window fractions (library propagator on its first tracks)."""
+    f64 = f32 = 0.0
+    for det, md, f, dtr in dev_showers:
+        if dtr.n == 0:
+            continue
+        plan = rt.Plan(det, md, f, "mixed")
+        ends_in, box_in = in_window_fractions(rt, plan, dtr, min(dtr.n, n_sample))
+        a, b = ops_per_pair(f, ends_in, box_in)
+        pairs = dtr.n * det.m
+        f64 += a * pairs
+        f32 += b * pairs
+    return f64, f32
+
+
+def bench_batched(args):
+    """256 independent showers (track counts log-uniform in 1e4..1e6, 16..512
+    antennas, 2048..8192 bins, both formalisms and media) in one persistent,
+    graph-replayed launch per step, launch shape from the autotuner."""
+    import torch
+    from paper_2309_03717_amd import autotune
+    from paper_2309_03717_amd import radtrace as rt
+    from paper_2309_03717_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    showers = W.batched_showers(args.showers, max_tracks=args.tracks)
+    dev = []
+    for i, sh in enumerate(showers):
+        tr = sh.tracks(mixed=True)
+        dev.append((rt.DeviceDetector.from_array(sh.array), sh.medium, sh.formalism,
+                    rt.DeviceTracks.from_tracks(tr)))
+        if i % 64 == 63:
+            log(f"generated {i + 1}/{len(showers)} showers ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    n_tracks = sum(d[3].n for d in dev)
+    log(f"inputs resident: {len(dev)} showers, {n_tracks} tracks ({time.perf_counter() - t0:.1f} s)")
+
+    opt, timings, cached = autotune.tune_batch(dev, "mixed", k=rt.K_SI, sample_tracks=args.tune_sample,
+                                               log=log)
+    log(f"autotuned options {opt} ({'cache' if cached else f'{len(timings)} candidates timed'})")
+    batch = rt.Batch(dev, "mixed", k=rt.K_SI, options=opt)
+    log(f"batch: {batch.info}, workspace {batch.workspace.numel() / 1e9:.2f} GB")
+
+    def step():
+        batch.zero_traces()
+        batch.launch()
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(args.steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(stop) / args.steps
+    log(f"timed {args.steps} graph steps: {ms_step:.1f} ms/step")
+    # deposit kernel alone: the same launches enqueued directly with events
+    durs = []
+    for _ in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        batch.zero_traces()
+        batch.set_timing_events(a, b)
+        batch.launch()
+        durs.append((a, b))
+    torch.cuda.synchronize()
+    kernel_ms = sum(a.elapsed_time(b) for a, b in durs) / len(durs)
+    pairs = batch.pairs
+    f64, f32 = shower_ops(rt, dev)
+    achieved = (f64 + f32) / (kernel_ms / 1e3) / 1e12
+    peak = VALU_OPS_PEAK / 1e12
+    out = {"metric": METRIC, "value": pairs / (ms_step / 1e3), "unit": "pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": f"batched-{len(dev)}-showers" + (f"[max {args.tracks}]" if args.tracks else ""),
+                      "n_showers": len(dev), "n_tracks": n_tracks, "pairs": pairs,
+                      "precision": "mixed", "options": vars(opt), "launch": "hipGraph replay",
+                      "items": batch.info["items"], "workgroups": batch.info["workgroups"]},
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                        "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                        "kernel": "batch_deposit_kernel<mixed>", "kernel_ms_avg": round(kernel_ms, 3),
+                        "ops_per_pair": {"fp64": round(f64 / pairs, 3), "fp32": round(f32 / pairs, 3)}}}
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle._load()
+        cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+        k = min(16, len(showers))
+        t1 = time.perf_counter()
+        cpu_pairs = 0
+        for sh, d in zip(showers[:k], dev[:k]):
+            tr = sh.tracks(mixed=True).widened()
+            oracle.traces(sh.formalism, tr, sh.array, sh.medium, k=1.0, n_threads=cores)
+            cpu_pairs += tr.n * sh.array.m
+        secs = time.perf_counter() - t1
+        log(f"cpu baseline: {secs:.2f} s on {cores} threads")
+        out["cpu_baseline"] = {"value": cpu_pairs / secs, "unit": "pairs/s", "cores": cores,
+                               "kind": "oracle", "seconds": round(secs, 3),
+                               "sample": f"the first {k} showers of the batch, all their tracks and "
+                                         f"antennas ({cpu_pairs} pairs), FP64 oracle"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_copy(args):
+    """Calibration for hardware byte counters: a plain device-to-device copy
+    of a known size (args.copy_mib MiB read and written per launch)."""
+    import torch
+    torch.cuda.set_device(0)
+    n = args.copy_mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    print(json.dumps({"metric": "device copy bandwidth (read + write)", "value": 2 * n / (ms / 1e3),
+                      "unit": "B/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(ms, 4), "higher_is_better": True,
+                      "bytes_read_per_launch": n, "bytes_written_per_launch": n,
+                      "config": {"workload": f"copy-{args.copy_mib}MiB"}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,11 +253,24 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
+    ap.add_argument("--workload", default="grid4096", choices=["grid4096", "batched", "copy"],
+                    help="grid4096: 1e8 tracks x 4096 antennas (default); batched: 256 showers; "
+                         "copy: byte-counter calibration")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
+    ap.add_argument("--showers", type=int, default=256, help="batched: number of showers")
+    ap.add_argument("--tune-sample", type=int, default=1 << 16,
+                    help="batched: tracks per shower the autotuner times candidates on")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(antenna sharding across GPUs is described in the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "copy":
+        bench_copy(args)
+        return
 
     import torch
     from paper_2309_03717_amd import radtrace as rt

@@ -164,55 +164,23 @@ __global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
 }
 
 // One workgroup per (shower, antenna, segment): traces += sum over the
-// shower's splits (in index order) of the slots; ZHS differences are
-// prefix-scanned over the segment first.
+// shower's splits (in index order) of the slots, prefix-scanned for ZHS.
 template <int P>
-__global__ void __launch_bounds__(256) batch_merge_kernel(BatchArgs b) {
+__global__ void __launch_bounds__(kMergeThreads) batch_merge_kernel(BatchArgs b) {
   using T = typename Prec<P>::out;
   const MergeTask mt = b.merges[blockIdx.x];
   const ShowerDesc &s = b.sh[mt.shower];
   const int atile = mt.antenna / s.at, ai = mt.antenna % s.at;
   const int lo = mt.seg * s.seg_len;
   const int nb = min(lo + s.seg_len, s.c.n_bins) - lo;
-  const int splits = s.splits;
-  const int64_t stride = s.slot_len;
-  const acc_t *part = b.partial + s.part0 + ((int64_t)atile * s.n_segs + mt.seg) * splits * stride +
+  const acc_t *part = b.partial + s.part0 +
+                      ((int64_t)atile * s.n_segs + mt.seg) * s.splits * s.slot_len +
                       (int64_t)ai * s.seg_len * 3;
   T *out = reinterpret_cast<T *>(s.traces) + ((size_t)mt.antenna * s.c.n_bins + lo) * 3;
-  if (s.formalism == RT_ENDPOINT) {
-    for (int i = threadIdx.x; i < nb * 3; i += blockDim.x) {
-      double v = 0.0;
-      for (int sp = 0; sp < splits; ++sp) v += part[sp * stride + i];
-      out[i] = (T)((double)out[i] + v);
-    }
-    return;
-  }
-  __shared__ double carry[256][3];
-  const int per = (nb + blockDim.x - 1) / blockDim.x;
-  const int b0 = min((int)threadIdx.x * per, nb), b1 = min(b0 + per, nb);
-  double run[3] = {0.0, 0.0, 0.0};
-  for (int q = b0; q < b1; ++q)
-    for (int c = 0; c < 3; ++c)
-      for (int sp = 0; sp < splits; ++sp) run[c] += part[sp * stride + 3 * q + c];
-  for (int c = 0; c < 3; ++c) carry[threadIdx.x][c] = run[c];
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    double acc = 0.0;
-    for (int t = 0; t < (int)blockDim.x; ++t) {
-      double x = carry[t][threadIdx.x];
-      carry[t][threadIdx.x] = acc;
-      acc += x;
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < 3; ++c) run[c] = carry[threadIdx.x][c];
-  for (int q = b0; q < b1; ++q)
-    for (int c = 0; c < 3; ++c) {
-      double d = 0.0;
-      for (int sp = 0; sp < splits; ++sp) d += part[sp * stride + 3 * q + c];
-      run[c] += d;
-      out[3 * q + c] = (T)((double)out[3 * q + c] + run[c]);
-    }
+  if (s.formalism == RT_ENDPOINT)
+    merge_segment<0, T>(part, s.slot_len, s.splits, out, nb);
+  else
+    merge_segment<1, T>(part, s.slot_len, s.splits, out, nb);
 }
 
 }  // namespace rt
@@ -293,9 +261,9 @@ static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t 
     batch_deposit_kernel<1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
   if (ev1) (void)hipEventRecord(ev1, stream);
   if (b.precision == RT_FP64)
-    batch_merge_kernel<0><<<(unsigned)b.merges.size(), 256, 0, stream>>>(a);
+    batch_merge_kernel<0><<<(unsigned)b.merges.size(), kMergeThreads, 0, stream>>>(a);
   else
-    batch_merge_kernel<1><<<(unsigned)b.merges.size(), 256, 0, stream>>>(a);
+    batch_merge_kernel<1><<<(unsigned)b.merges.size(), kMergeThreads, 0, stream>>>(a);
   return hipGetLastError();
 }
 

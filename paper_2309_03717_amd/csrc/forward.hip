@@ -68,6 +68,7 @@ struct DepositArgs {
   int64_t n_blocks;        // wave blocks of tracks in this pass
   int64_t blocks_per_split;
   int n_atiles, n_segs, seg_len;
+  int accumulate;          // 0: first pass writes the partials; 1: later passes add
 };
 
 // F: 0 Endpoint, 1 ZHS.  P: 0 FP64, 1 mixed.  MED: 0 uniform, 1 exponential.
@@ -108,63 +109,29 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   for (int a = 0; a < n_ant; ++a) {
     acc_t *out = dst + (((size_t)split * g.an.m + (size_t)(a_begin + a)) * g.c.n_bins + lo) * 3;
     const acc_t *src = tile + a * row_len;
-    for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = src[i];
+    if (g.accumulate)
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] += src[i];
+    else
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = src[i];
   }
 }
 
 // ------------------------------------------------------------------ merge
 
 // One workgroup per (antenna, segment): traces += sum over splits (index
-// order) of the partials; for ZHS the summed differences are prefix-scanned
-// over the segment's bins first. Accumulation is in double precision.
+// order) of the partials, prefix-scanned over the segment for ZHS.
 template <int F, int P>
-__global__ void __launch_bounds__(256) merge_kernel(const void *partial, void *traces, int64_t m,
-                                                    int n_bins, int splits, int seg_len,
-                                                    int n_segs) {
+__global__ void __launch_bounds__(kMergeThreads) merge_kernel(const void *partial, void *traces,
+                                                              int64_t m, int n_bins, int splits,
+                                                              int seg_len, int n_segs) {
   using T = typename Prec<P>::out;
-  const acc_t *part = reinterpret_cast<const acc_t *>(partial);
-  T *out = reinterpret_cast<T *>(traces);
   const int64_t a = blockIdx.x / n_segs;
   const int seg = blockIdx.x % n_segs;
   const int lo = seg * seg_len;
   const int nb = min(lo + seg_len, n_bins) - lo;
-  const size_t plane = (size_t)m * n_bins * 3;
   const size_t base = ((size_t)a * n_bins + lo) * 3;
-  if (F == 0) {
-    for (int i = threadIdx.x; i < nb * 3; i += blockDim.x) {
-      double s = 0.0;
-      for (int sp = 0; sp < splits; ++sp) s += part[sp * plane + base + i];
-      out[base + i] = (T)((double)out[base + i] + s);
-    }
-    return;
-  }
-  __shared__ double carry[256][3];
-  const int per = (nb + blockDim.x - 1) / blockDim.x;
-  const int b0 = min((int)threadIdx.x * per, nb), b1 = min(b0 + per, nb);
-  double run[3] = {0.0, 0.0, 0.0};
-  for (int b = b0; b < b1; ++b)
-    for (int c = 0; c < 3; ++c)
-      for (int sp = 0; sp < splits; ++sp) run[c] += part[sp * plane + base + 3 * b + c];
-  for (int c = 0; c < 3; ++c) carry[threadIdx.x][c] = run[c];
-  __syncthreads();
-  if (threadIdx.x < 3) {
-    double acc = 0.0;
-    for (int t = 0; t < (int)blockDim.x; ++t) {
-      double x = carry[t][threadIdx.x];
-      carry[t][threadIdx.x] = acc;
-      acc += x;
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < 3; ++c) run[c] = carry[threadIdx.x][c];
-  for (int b = b0; b < b1; ++b)
-    for (int c = 0; c < 3; ++c) {
-      double d = 0.0;
-      for (int sp = 0; sp < splits; ++sp) d += part[sp * plane + base + 3 * b + c];
-      run[c] += d;
-      size_t o = base + 3 * b + c;
-      out[o] = (T)((double)out[o] + run[c]);
-    }
+  merge_segment<F, T>(reinterpret_cast<const acc_t *>(partial) + base, (int64_t)m * n_bins * 3,
+                      splits, reinterpret_cast<T *>(traces) + base, nb);
 }
 
 // ------------------------------------------------------------------ propagator
@@ -236,6 +203,11 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
     // of the workgroup over its tracks
     int64_t resident = (int64_t)p.num_cus * (int64_t)std::max<size_t>(1, p.lds_per_cu / t.lds_bytes);
     splits = (2 * resident + n_tiles - 1) / n_tiles;
+    // ZHS workgroups drift apart (a box costs more than a missed window, and
+    // which tracks land depends on the antenna), so the workgroups resident
+    // together stop sharing records in L2 over long track ranges: cap a
+    // split at kZhsSplitBlocks wave blocks
+    if (p.formalism == RT_ZHS) splits = std::max(splits, (nb + kZhsSplitBlocks - 1) / kZhsSplitBlocks);
     int64_t cap = std::max<int64_t>(1, nb / (4 * (t.block / 64)));
     if (splits > cap) splits = cap;
     if (splits < 1) splits = 1;
@@ -325,18 +297,24 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
   if (tl.lds_bytes > 65536)
     (void)hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)tl.lds_bytes);
+  // Passes run back to back; each workgroup adds its tile into the partial
+  // slot of its (split, tile), which only it touches within a pass, so the
+  // partials hold the sum over passes and one merge follows the last pass.
+  // The first pass has the most blocks, hence every split, and writes all
+  // slots.
   const int64_t pass_blocks = tl.pass_tracks / 64;
   if (p.ev_start) (void)hipEventRecord(p.ev_start, stream);
   for (int64_t b0 = 0; b0 < pa.n_blocks; b0 += pass_blocks) {
     g.rec = pa.rec + b0 * (kRec * 64);
     g.n_blocks = std::min(pass_blocks, pa.n_blocks - b0);
+    g.accumulate = b0 > 0;
     const int64_t splits = (g.n_blocks + tl.blocks_per_split - 1) / tl.blocks_per_split;
     const int64_t grid = (int64_t)tl.n_atiles * tl.n_segs * splits;
     fn<<<dim3((unsigned)grid), dim3(tl.block), tl.lds_bytes, stream>>>(g);
-    if (b0 + pass_blocks >= pa.n_blocks && p.ev_stop) (void)hipEventRecord(p.ev_stop, stream);
-    mf<<<dim3((unsigned)(p.det.n_antennas * tl.n_segs)), dim3(256), 0, stream>>>(
-        g.partial, traces, p.det.n_antennas, p.det.n_bins, (int)splits, tl.seg_len, tl.n_segs);
   }
+  if (p.ev_stop) (void)hipEventRecord(p.ev_stop, stream);
+  mf<<<dim3((unsigned)(p.det.n_antennas * tl.n_segs)), dim3(kMergeThreads), 0, stream>>>(
+      g.partial, traces, p.det.n_antennas, p.det.n_bins, tl.splits, tl.seg_len, tl.n_segs);
   return hipGetLastError();
 }
 

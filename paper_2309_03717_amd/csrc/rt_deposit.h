@@ -37,6 +37,32 @@ enum : int {
   R_AMP,                   // Endpoint: k qw / dt;  ZHS: k qw (t1 - t0) / dt
   R_BX, R_BY, R_BZ         // velocity (units of c)
 };
+// RT_MIXED records keep slots 0-9 (geometry, times, path indices), pack the
+// single-precision fields in pairs, (amplitude, bx) and (by, bz), and keep the
+// height factors e0, e1 in double precision in slots 12-13 (the Endpoint
+// source index 1 + (n0 - 1) e sits next to the Cherenkov pole, where a
+// rounded index would dominate the error). A wave reads 12 of the 16 slots,
+// plus the height factors where the exponential Endpoint needs the source
+// index or a tile antenna sits off the reference height.
+enum : int { M_AB = 10, M_YZ = 11, M_E0 = 12, M_E1 = 13 };
+
+__device__ __forceinline__ double pack2(float lo, float hi) {
+  return __longlong_as_double((long long)(((unsigned long long)__float_as_uint(hi) << 32) |
+                                          (unsigned long long)__float_as_uint(lo)));
+}
+__device__ __forceinline__ float lo32(double d) {
+  return __uint_as_float((unsigned)(unsigned long long)__double_as_longlong(d));
+}
+__device__ __forceinline__ float hi32(double d) {
+  return __uint_as_float((unsigned)((unsigned long long)__double_as_longlong(d) >> 32));
+}
+
+// Record slots a wave loads: all of an FP64 record; of a mixed record the
+// first 12, and the height factors when H.
+template <int P, bool H>
+constexpr int record_loads() {
+  return P == 0 ? kRec : (H ? M_E1 + 1 : M_YZ + 1);
+}
 
 // Builds the record of one track (fields as above). A track with any
 // non-finite field gets NaN times so that no antenna window accepts it.
@@ -77,6 +103,15 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
     v[R_NE0] = path_index(v[R_Z0], z_ref, v[R_E0], e_ref, c);
     v[R_NE1] = path_index(v[R_Z1], z_ref, v[R_E1], e_ref, c);
   }
+  if (P == 1) {
+    const double amp = v[R_AMP], bx = v[R_BX], by = v[R_BY], bz = v[R_BZ];
+    const double e0 = v[R_E0], e1 = v[R_E1];
+    v[M_AB] = pack2((float)amp, (float)bx);
+    v[M_YZ] = pack2((float)by, (float)bz);
+    v[M_E0] = e0;
+    v[M_E1] = e1;
+    v[14] = v[15] = 0.0;
+  }
 }
 
 __device__ __forceinline__ void put3(acc_t *row, int j, double vx, double vy, double vz) {
@@ -111,13 +146,10 @@ __device__ __forceinline__ double fast_rsq(double x) {
 // ((1 - n_src beta.r) R dt), evaluated as sc (d (beta.d) / R^2 - beta) / num
 // with num = R - n_src (beta.d) = (1 - n_src beta.r) R and sc = s k qw / dt.
 template <int P>
-__device__ __forceinline__ void endpoint_end(acc_t *row, int lo, double lo_d, double hi_d,
-                                             double sc, double px, double py, double pz,
-                                             double tp, double ax, double ay, double az,
-                                             double tau, double neff, double nsrc, double bx,
-                                             double by, double bz, const Consts &c) {
-  double dx, dy, dz, r, r2;
-  double u = arrival_bins(px, py, pz, tp, ax, ay, az, tau, neff, c, dx, dy, dz, r, r2);
+__device__ __forceinline__ void endpoint_amp(acc_t *row, int lo, double lo_d, double hi_d,
+                                             double u, double sc, double dx, double dy, double dz,
+                                             double r, double r2, double nsrc, double bx,
+                                             double by, double bz) {
   if (!(u >= lo_d && u < hi_d)) return;   // outside this segment of the window (or NaN)
   const int j = (int)u - lo;
   double bd = fma(bx, dx, fma(by, dy, bz * dz));
@@ -156,33 +188,23 @@ __device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double lo_d,
   double s = cz * rinv;
   double ix = fma(-dx, q, bx) * s, iy = fma(-dy, q, by) * s, iz = fma(-dz, q, bz) * s;
   double kl = floor(ulo), kh = floor(uhi);
-  if (kl == kh) {   // whole box inside one bin of this segment
-    int j = (int)kl;
-    put3(row, j - lo, ix, iy, iz);
-    if (j + 1 < hi) put3(row, j + 1 - lo, -ix, -iy, -iz);
-    return;
-  }
+  const bool one = kl == kh, two = kh == kl + 1.0;
   double w = uhi - ulo;
   double wi = P == 0 ? 1.0 / w : fast_rcp(w);
   double flo = (kl + 1.0) - ulo;   // share of bin kl, in (0, 1]
   double fhi = uhi - kh;           // share of bin kh, in [0, 1)
-  // clamp far-out indices before the int conversion (all fold or drop alike)
+  double a = flo * wi, bb = fhi * wi;
+  double s1 = one ? 1.0 : a;
+  double s2 = one ? -1.0 : (two ? -a : (1.0 - flo) * wi);
+  double s3 = two ? bb : -((1.0 - fhi) * wi);
+  double s4 = -bb;
   int jl = (int)fmax(kl, lo_d - 2.0);
   int jh = (int)fmin(kh, hi_d);
-  if (kh == kl + 1.0) {
-    double fa = flo * wi, fb = fhi * wi;
-    double ax_ = ix * fa, ay_ = iy * fa, az_ = iz * fa;
-    double bx_ = ix * fb, by_ = iy * fb, bz_ = iz * fb;
-    put3_clamped(row, jl, lo, hi, ax_, ay_, az_);
-    put3_clamped(row, jl + 1, lo, hi, bx_ - ax_, by_ - ay_, bz_ - az_);
-    put3_clamped(row, jl + 2, lo, hi, -bx_, -by_, -bz_);
-  } else {
-    double hx = ix * wi, hy = iy * wi, hz = iz * wi;
-    double gl = 1.0 - flo, gh = 1.0 - fhi;
-    put3_clamped(row, jl, lo, hi, hx * flo, hy * flo, hz * flo);
-    put3_clamped(row, jl + 1, lo, hi, hx * gl, hy * gl, hz * gl);
-    put3_clamped(row, jh, lo, hi, -hx * gh, -hy * gh, -hz * gh);
-    put3_clamped(row, jh + 1, lo, hi, -hx * fhi, -hy * fhi, -hz * fhi);
+  put3_clamped(row, jl, lo, hi, ix * s1, iy * s1, iz * s1);
+  put3_clamped(row, jl + 1, lo, hi, ix * s2, iy * s2, iz * s2);
+  if (!one) {
+    put3_clamped(row, jh, lo, hi, ix * s3, iy * s3, iz * s3);
+    put3_clamped(row, jh + 1, lo, hi, ix * s4, iy * s4, iz * s4);
   }
 }
 
@@ -195,30 +217,54 @@ struct Tile {
 
 // All deposits of one track record (this lane's track) into the tile
 // antennas selected by mask.
-template <int F, int P, int MED, int AT>
+// H: the height factors are present (always in FP64 records; in mixed
+// records when deposit_blocks loaded them).
+template <int F, int P, int MED, int AT, bool H>
 __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, const Tile<AT> &t,
                                                acc_t *tile, int row_len, int lo, int hi,
                                                double lo_d, double hi_d, const Consts &c) {
   const double x0 = v[R_X0], y0 = v[R_Y0], z0 = v[R_Z0], t0 = v[R_T0];
   const double x1 = v[R_X1], y1 = v[R_Y1], z1 = v[R_Z1], t1 = v[R_T1];
-  const double amp = v[R_AMP], bx = v[R_BX], by = v[R_BY], bz = v[R_BZ];
-  const double e0 = MED == 1 ? v[R_E0] : 0.0, e1 = MED == 1 ? v[R_E1] : 0.0;
+  constexpr bool kOff = MED == 1 && H;   // off-reference antennas can be handled
+  double amp, bx, by, bz, e0 = 0.0, e1 = 0.0;
+  if (P == 0) {
+    amp = v[R_AMP];
+    bx = v[R_BX];
+    by = v[R_BY];
+    bz = v[R_BZ];
+    if (MED == 1) {
+      e0 = v[R_E0];
+      e1 = v[R_E1];
+    }
+  } else {
+    amp = lo32(v[M_AB]);
+    bx = hi32(v[M_AB]);
+    by = lo32(v[M_YZ]);
+    bz = hi32(v[M_YZ]);
+    if (kOff) {
+      e0 = v[M_E0];
+      e1 = v[M_E1];
+    }
+  }
+  const double ns0 = MED == 1 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
+  const double ns1 = MED == 1 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
   if (F == 0) {
-    const double ns0 = MED == 1 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
-    const double ns1 = MED == 1 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
         double ne0 = v[R_NE0], ne1 = v[R_NE1];
-        if (MED == 1 && !t.at_ref[a]) {
+        if (kOff && !t.at_ref[a]) {
           ne0 = path_index(z0, t.az[a], e0, t.ea[a], c);
           ne1 = path_index(z1, t.az[a], e1, t.ea[a], c);
         }
         acc_t *row = tile + a * row_len;
-        endpoint_end<P>(row, lo, lo_d, hi_d, amp, x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a],
-                        t.tau[a], ne0, ns0, bx, by, bz, c);
-        endpoint_end<P>(row, lo, lo_d, hi_d, -amp, x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a],
-                        t.tau[a], ne1, ns1, bx, by, bz, c);
+        double dx0, dy0, dz0, r0, q0, dx1, dy1, dz1, r1, q1;
+        double u0 = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c,
+                                 dx0, dy0, dz0, r0, q0);
+        double u1 = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c,
+                                 dx1, dy1, dz1, r1, q1);
+        endpoint_amp<P>(row, lo, lo_d, hi_d, u0, amp, dx0, dy0, dz0, r0, q0, ns0, bx, by, bz);
+        endpoint_amp<P>(row, lo, lo_d, hi_d, u1, -amp, dx1, dy1, dz1, r1, q1, ns1, bx, by, bz);
       }
     }
   } else {
@@ -227,7 +273,7 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
         double ne0 = v[R_NE0], ne1 = v[R_NE1];
-        if (MED == 1 && !t.at_ref[a]) {
+        if (kOff && !t.at_ref[a]) {
           ne0 = path_index(z0, t.az[a], e0, t.ea[a], c);
           ne1 = path_index(z1, t.az[a], e1, t.ea[a], c);
         }
@@ -245,18 +291,23 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 
 // Deposits of the wave blocks [b_first, b_end) (stride `waves`, one block per
 // wave per step) of a record array into the LDS tile, with the next record
-// loaded before the current one is processed.
-template <int F, int P, int MED, int AT>
-__device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
-                                               int64_t waves, uint64_t mask, const Tile<AT> &t,
-                                               acc_t *tile, int row_len, int lo, int hi,
-                                               double lo_d, double hi_d, const Consts &c) {
+// loaded before the current one is processed. Only the slots the formalism
+// and precision use are read.
+template <int F, int P, int MED, int AT, bool H>
+__device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_first,
+                                                 int64_t b_end, int64_t waves, uint64_t mask,
+                                                 const Tile<AT> &t, acc_t *tile, int row_len,
+                                                 int lo, int hi, double lo_d, double hi_d,
+                                                 const Consts &c) {
+  constexpr int kLoad = record_loads<P, H>();
   const int lane = threadIdx.x & 63;
   double nx[kRec];
+#pragma unroll
+  for (int f = kLoad; f < kRec; ++f) nx[f] = 0.0;
   if (b_first < b_end) {
     const double *r = rec + b_first * (kRec * 64) + lane;
 #pragma unroll
-    for (int f = 0; f < kRec; ++f) nx[f] = r[f * 64];
+    for (int f = 0; f < kLoad; ++f) nx[f] = r[f * 64];
   }
   for (int64_t blk = b_first; blk < b_end; blk += waves) {
     double rv[kRec];
@@ -265,10 +316,29 @@ __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_firs
     if (blk + waves < b_end) {
       const double *r = rec + (blk + waves) * (kRec * 64) + lane;
 #pragma unroll
-      for (int f = 0; f < kRec; ++f) nx[f] = r[f * 64];
+      for (int f = 0; f < kLoad; ++f) nx[f] = r[f * 64];
     }
-    deposit_record<F, P, MED, AT>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
+    deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
   }
+}
+
+// As deposit_blocks_n, reading the height factors of mixed records only where
+// they are used: the exponential Endpoint (source index) and tiles with an
+// antenna off the reference height.
+template <int F, int P, int MED, int AT>
+__device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
+                                               int64_t waves, uint64_t mask, const Tile<AT> &t,
+                                               acc_t *tile, int row_len, int lo, int hi,
+                                               double lo_d, double hi_d, const Consts &c) {
+  bool off = false;
+#pragma unroll
+  for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
+  if (P == 0 || (MED == 1 && (F == 0 || off)))
+    deposit_blocks_n<F, P, MED, AT, true>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
+                                          hi, lo_d, hi_d, c);
+  else
+    deposit_blocks_n<F, P, MED, AT, false>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
+                                           hi, lo_d, hi_d, c);
 }
 
 // Loads the tile antennas [a_begin, a_begin + n_ant) (uniform per workgroup).
@@ -285,6 +355,82 @@ __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, in
     t.tau[a] = an.t_start[ai];
     t.ea[a] = MED == 1 ? height_factor(t.az[a], c) : 0.0;
     t.at_ref[a] = t.az[a] == z_ref;
+  }
+}
+
+// ------------------------------------------------------------------ merge
+
+constexpr int kMergeThreads = 256;
+
+// traces[0, nb) += the sum over `splits` partial slots (`stride` doubles
+// apart, added in slot order) of one segment, 3 components per bin. ZHS
+// slots hold differences (every box folded into the segment's first bin
+// where it starts earlier), so their sum is prefix-scanned over the segment:
+// chunks of kMergeThreads bins are summed with coalesced loads into LDS,
+// scanned across the workgroup (within each wave by lane shuffles, then over
+// the wave totals), offset by the carry of the chunks before, and added to
+// the traces with coalesced stores. One workgroup of kMergeThreads threads.
+template <int F, typename T>
+__device__ __forceinline__ void merge_segment(const acc_t *part, int64_t stride, int splits,
+                                              T *out, int nb) {
+  const int tid = threadIdx.x;
+  if (F == 0) {
+    for (int i = tid; i < nb * 3; i += kMergeThreads) {
+      double s = 0.0;
+      for (int sp = 0; sp < splits; ++sp) s += part[sp * stride + i];
+      out[i] = (T)((double)out[i] + s);
+    }
+    return;
+  }
+  constexpr int kWaves = kMergeThreads / 64;
+  __shared__ double buf[kMergeThreads * 3];
+  __shared__ double wsum[kWaves][3];
+  const int lane = tid & 63, wave = tid >> 6;
+  double carry[3] = {0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < nb; c0 += kMergeThreads) {
+    const int n = min(kMergeThreads, nb - c0);
+    const acc_t *p = part + 3 * (int64_t)c0;
+    for (int i = tid; i < 3 * n; i += kMergeThreads) {
+      double s = 0.0;
+      for (int sp = 0; sp < splits; ++sp) s += p[sp * stride + i];
+      buf[i] = s;
+    }
+    __syncthreads();
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = tid < n ? buf[3 * tid + c] : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double y = __shfl_up(v[c], off);
+        if (lane >= off) v[c] += y;
+      }
+    }
+    if (lane == 63)
+      for (int c = 0; c < 3; ++c) wsum[wave][c] = v[c];
+    __syncthreads();
+    double pre[3], tot[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pre[c] = carry[c];
+      for (int w = 0; w < wave; ++w) pre[c] += wsum[w][c];
+      tot[c] = pre[c];
+      for (int w = wave; w < kWaves; ++w) tot[c] += wsum[w][c];
+    }
+    // tot is the same in every wave only up to rounding order: take wave 0's
+    // value (pre = carry there) so that all threads carry the same number
+    __syncthreads();
+    if (tid < n)
+      for (int c = 0; c < 3; ++c) buf[3 * tid + c] = pre[c] + v[c];
+    if (tid == 0)
+      for (int c = 0; c < 3; ++c) wsum[0][c] = tot[c];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) carry[c] = wsum[0][c];
+    T *o = out + 3 * (int64_t)c0;
+    for (int i = tid; i < 3 * n; i += kMergeThreads) o[i] = (T)((double)o[i] + buf[i]);
+    __syncthreads();
   }
 }
 

@@ -24,6 +24,7 @@ namespace rt {
 constexpr int kMaxTile = 8;     // antennas per workgroup tile (template bound)
 constexpr int64_t kDefaultPass = 1 << 20;   // tracks per deposit pass by default
 constexpr int kXcds = 8;        // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr int64_t kZhsSplitBlocks = 2048;   // ZHS track split cap: 128K tracks
 
 struct Consts {
   double inv_c;       // 1 / c
@@ -61,6 +62,24 @@ __device__ __forceinline__ double path_index(double zp, double za, double ep, do
   return 1.0 + c.n0m1 * exp(-(((zp + za) * 0.5) / c.h));
 }
 
+// Correctly rounded sqrt: the hardware reciprocal square root refined by
+// Newton steps (the same operations as the compiler's own expansion, without
+// its range scaling); inputs outside (2^-767, inf) take the library sqrt.
+__device__ __forceinline__ double sqrt_rn(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = y * 0.5;
+  double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  double d = fma(-g, g, x);
+  h = fma(h, r, h);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  g = fma(d, h, g);
+  if (__builtin_expect(!(x > 0x1p-767 && x < __builtin_inf()), 0)) g = sqrt(x);
+  return g;
+}
+
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an
 // antenna at (ax,ay,az) whose bin 0 starts at tau. Returns u, the arrival in
 // bins; d = X - P, R and R^2 are returned for the amplitude.
@@ -72,7 +91,7 @@ __device__ __forceinline__ double arrival_bins(double px, double py, double pz, 
   dy = ay - py;
   dz = az - pz;
   r2 = (dx * dx + dy * dy) + dz * dz;
-  r = sqrt(r2);
+  r = sqrt_rn(r2);
   double t = tp + (neff * r) * c.inv_c;
   return (t - tau) * c.inv_dt;
 }
@@ -82,7 +101,7 @@ __device__ __forceinline__ double arrival_time(double px, double py, double pz, 
                                                double ax, double ay, double az, double neff,
                                                const Consts &c) {
   double dx = ax - px, dy = ay - py, dz = az - pz;
-  double r = sqrt((dx * dx + dy * dy) + dz * dz);
+  double r = sqrt_rn((dx * dx + dy * dy) + dz * dz);
   return tp + (neff * r) * c.inv_c;
 }
 

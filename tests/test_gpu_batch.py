@@ -18,7 +18,7 @@ from paper_2309_03717_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP64_BOUND = 1e-5
-MIXED_BOUND = 2e-4
+MIXED_BOUND = 1e-6
 
 
 @pytest.fixture(scope="module")

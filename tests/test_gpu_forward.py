@@ -17,8 +17,9 @@ from helpers import antennas
 pytestmark = pytest.mark.gpu
 
 FP64_BOUND = 1e-5
-# mixed mode: FP32 amplitudes and FP32 LDS accumulation (stated, measured bound)
-MIXED_BOUND = 2e-4
+# mixed mode: FP32 amplitude inputs (amplitude, beta), FP64 timing and source
+# index, FP64 accumulation; stated bound, measured below 1e-7 on these inputs
+MIXED_BOUND = 1e-6
 
 
 @pytest.fixture(scope="module")
