@@ -51,6 +51,19 @@ OPS = {
 VALU_OPS_PEAK = 256 * 64 * 2.4e9
 FP32_PEAK_PUBLISHED = 157.3e12
 
+# HBM-side bytes per deposit launch of 2^20 tracks on this workload, from the
+# FETCH_SIZE and WRITE_SIZE counter runs summarised in
+# profiles/deposit_grid4096_mixed_hbm_bytes.md (KiB per dispatch), scaled by
+# what the same counters read for a 1 GiB device copy (FETCH_SIZE reads half
+# the copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
+# they were taken on (hash below); otherwise the bench reports null.
+TRAFFIC_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
+TRAFFIC_HASH = "9d3d09ead2b26feb"
+TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.6, "write": 1048576.0 / 1048576.0}
+TRAFFIC_KIB = {"endpoint": {"fetch": 14995679.1, "write": 393216.0},
+               "zhs": {"fetch": 45127897.6, "write": 3145728.0}}
+TRAFFIC_PASS = 1 << 20
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -73,6 +86,25 @@ def in_window_fractions(rt, plan, dtr, n_sample):
     box_in = float(((hi >= 0) & (lo < plan.det.n_bins)).double().mean().item())
     del t, b, u, lo, hi
     return ends_in, box_in
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2309_03717_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(formalism, tiling):
+    """Counter-measured HBM bytes per deposit launch, or None when the kernel
+    sources or the launch shape differ from those the counters were taken
+    on."""
+    if kernel_source_hash() != TRAFFIC_HASH or tiling[4] != TRAFFIC_PASS:
+        return None
+    k = TRAFFIC_KIB[formalism]
+    return 1024.0 * (k["fetch"] * TRAFFIC_SCALE["fetch"] + k["write"] * TRAFFIC_SCALE["write"])
 
 
 def ops_per_pair(formalism, ends_in, box_in):
@@ -359,8 +391,11 @@ def main():
     dom = max(formalisms, key=lambda f: per[f]["kernel_ms_total_per_step"])
     achieved = per[dom]["achieved_tops"]
     peak = VALU_OPS_PEAK / 1e12
+    traffic = traffic_bytes(dom, plans[dom].tiling(chunk)) if n_total >= chunk else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": f"deposit_kernel<{dom},mixed,exponential>",
                 "kernel_ms_avg": round(per[dom]["kernel_ms_avg"], 3),
                 "ops_per_pair": per[dom]["ops_per_pair"],
