@@ -64,6 +64,7 @@ def _load():
                                       dp, dp, C.POINTER(C.c_int32)]
         lib.orc_zhs_vjp.argtypes = [C.POINTER(_Tracks), C.POINTER(_Antennas), C.POINTER(_Medium),
                                     C.c_double, dp, dp, dp, dp, dp, C.c_int]
+        lib.orc_endpoint_vjp.argtypes = lib.orc_zhs_vjp.argtypes
         lib.orc_version.restype = C.c_int
         _lib = lib
     return _lib
@@ -132,6 +133,17 @@ def propagate(tracks, array, medium):
 def zhs_vjp(tracks, array, medium, grad: np.ndarray, k: float = 1.0, n_threads: int = 1):
     """Gradients of sum(grad * A_zhs) with respect to qw [n], p0 [3, n],
     p1 [3, n] and n0m1 (scalar), with beta and the emission times fixed."""
+    return _vjp("orc_zhs_vjp", tracks, array, medium, grad, k, n_threads)
+
+
+def endpoint_vjp(tracks, array, medium, grad: np.ndarray, k: float = 1.0, n_threads: int = 1):
+    """Gradients of sum(grad * E_endpoint) with respect to qw [n], p0 [3, n],
+    p1 [3, n] and n0m1 (scalar), with beta, the emission times and the bins the
+    impulses land in held fixed."""
+    return _vjp("orc_endpoint_vjp", tracks, array, medium, grad, k, n_threads)
+
+
+def _vjp(name, tracks, array, medium, grad, k, n_threads):
     lib = _load()
     args = _Args(tracks, array, medium)
     g = _f64(grad)
@@ -141,8 +153,8 @@ def zhs_vjp(tracks, array, medium, grad: np.ndarray, k: float = 1.0, n_threads: 
     gp0 = np.zeros((3, n))
     gp1 = np.zeros((3, n))
     gn = np.zeros(1)
-    rc = lib.orc_zhs_vjp(C.byref(args.tr), C.byref(args.ar), C.byref(args.md), float(k), _dp(g),
-                         _dp(gq), _dp(gp0), _dp(gp1), _dp(gn), int(n_threads))
+    rc = getattr(lib, name)(C.byref(args.tr), C.byref(args.ar), C.byref(args.md), float(k),
+                            _dp(g), _dp(gq), _dp(gp0), _dp(gp1), _dp(gn), int(n_threads))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return {"qw": gq, "p0": gp0, "p1": gp1, "n0m1": float(gn[0])}

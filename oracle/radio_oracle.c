@@ -499,3 +499,125 @@ int orc_zhs_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_medium *
   free(th);
   return 0;
 }
+
+/* ----------------------------------------------------- Endpoint adjoint */
+
+typedef struct {
+  const orc_tracks *tr;
+  const orc_antennas *ar;
+  const orc_medium *md;
+  double k;
+  const double *grad;
+  double *g_qw, *g_p0, *g_p1, *g_n_track;
+  int64_t i_begin, i_end;
+} ep_vjp_job;
+
+/* Vector-Jacobian product of the Endpoint traces, per track: for
+ * L = sum G * E with E the Endpoint definition above, the derivatives with
+ * respect to qw, the two end points and n0m1, with beta and the emission
+ * times fixed. The bin an impulse lands in is piecewise constant in these
+ * parameters, so only the impulse value is differentiated: with r = d / R,
+ * b = beta.r, D = 1 - n_src b, V = r b - beta and A = s k qw / dt, an end's
+ * share of L is f = A (g.V) / (D R), g = G at its bin, and
+ *   df/dd_j = A [ (g.dV/dd_j) / (D R) + n_src (g.V) (db/dd_j) / (D^2 R)
+ *                 - (g.V) r_j / (D R^2) ],
+ *   dr_i/dd_j = (delta_ij - r_i r_j) / R,  db/dd_j = (beta_j - b r_j) / R,
+ *   df/dn_src = A (g.V) b / (D^2 R),
+ * with d = X - P (so df/dP = -df/dd) and n_src = 1 + n0m1 e(z_P), whose
+ * height derivative adds to the z component. */
+static void *ep_vjp_worker(void *arg) {
+  ep_vjp_job *job = (ep_vjp_job *)arg;
+  const orc_tracks *tr = job->tr;
+  const orc_antennas *ar = job->ar;
+  const orc_medium *md = job->md;
+  size_t trace_len = (size_t)ar->n_bins * 3;
+  for (int64_t i = job->i_begin; i < job->i_end; ++i) {
+    double gq = 0.0, gp[2][3] = {{0, 0, 0}, {0, 0, 0}}, gn = 0.0;
+    double beta[3] = {tr->bx[i], tr->by[i], tr->bz[i]};
+    for (int64_t a = 0; a < ar->m && track_is_finite(tr, i); ++a) {
+      const double *g_a = job->grad + (size_t)a * trace_len;
+      for (int end = 0; end < 2; ++end) {
+        double px = end ? tr->x1[i] : tr->x0[i];
+        double py = end ? tr->y1[i] : tr->y0[i];
+        double pz = end ? tr->z1[i] : tr->z0[i];
+        double tp = end ? tr->t1[i] : tr->t0[i];
+        double s = end ? -1.0 : 1.0;
+        path p = propagate(ar, md, a, px, py, pz, tp);
+        int64_t kb = bin_of(p.u, ar->n_bins);
+        if (kb < 0 || p.r == 0.0) continue;
+        double R = p.r;
+        double r[3] = {p.dx / R, p.dy / R, p.dz / R};
+        double b = (beta[0] * r[0] + beta[1] * r[1]) + beta[2] * r[2];
+        double n_src = index_at(md, pz);
+        double D = 1.0 - n_src * b;
+        if (D == 0.0) continue;
+        double V[3] = {r[0] * b - beta[0], r[1] * b - beta[1], r[2] * b - beta[2]};
+        const double *g = g_a + 3 * kb;
+        double gV = g[0] * V[0] + g[1] * V[1] + g[2] * V[2];
+        double gr = g[0] * r[0] + g[1] * r[1] + g[2] * r[2];
+        double A = s * job->k * tr->qw[i] / ar->dt;
+        /* weight: f is linear in qw */
+        gq += s * job->k / ar->dt * gV / (D * R);
+        for (int j = 0; j < 3; ++j) {
+          double db = (beta[j] - b * r[j]) / R;
+          /* g.dV/dd_j = sum_i g_i [ (delta_ij - r_i r_j) b / R + r_i db_j ] */
+          double gdV = (g[j] - gr * r[j]) * b / R + gr * db;
+          double df = A * (gdV / (D * R) + n_src * gV * db / (D * D * R) - gV * r[j] / (D * R * R));
+          gp[end][j] -= df;
+        }
+        double df_dn = A * gV * b / (D * D * R);
+        if (md->kind == 0) {
+          gn += df_dn;
+        } else {
+          double e = exp(-(pz / md->h));
+          gn += df_dn * e;
+          gp[end][2] += df_dn * md->n0m1 * e * (-1.0 / md->h);
+        }
+      }
+    }
+    job->g_qw[i] = gq;
+    for (int j = 0; j < 3; ++j) {
+      job->g_p0[(size_t)j * tr->n + i] = gp[0][j];
+      job->g_p1[(size_t)j * tr->n + i] = gp[1][j];
+    }
+    job->g_n_track[i] = gn;
+  }
+  return NULL;
+}
+
+/* Endpoint vector-Jacobian product; arguments and outputs as orc_zhs_vjp. */
+int orc_endpoint_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_medium *md,
+                     double k, const double *grad, double *g_qw, double *g_p0, double *g_p1,
+                     double *g_n0m1, int n_threads) {
+  if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
+  if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
+  *g_n0m1 = 0.0;
+  if (tr->n == 0) return 0;
+  double *gn = (double *)calloc((size_t)tr->n, sizeof(double));
+  if (!gn) return -1;
+  if (n_threads < 1) n_threads = 1;
+  ep_vjp_job *jobs = (ep_vjp_job *)calloc((size_t)n_threads, sizeof(ep_vjp_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+  if (!jobs || !th) { free(gn); free(jobs); free(th); return -1; }
+  int64_t per = (tr->n + n_threads - 1) / n_threads;
+  for (int w = 0; w < n_threads; ++w) {
+    int64_t lo = (int64_t)w * per, hi = lo + per;
+    if (lo > tr->n) lo = tr->n;
+    if (hi > tr->n) hi = tr->n;
+    ep_vjp_job j = {tr, ar, md, k, grad, g_qw, g_p0, g_p1, gn, lo, hi};
+    jobs[w] = j;
+  }
+  int started = 0;
+  for (int w = 1; w < n_threads; ++w)
+    if (pthread_create(&th[w], NULL, ep_vjp_worker, &jobs[w]) == 0) ++started; else break;
+  ep_vjp_worker(&jobs[0]);
+  for (int w = 1; w <= started; ++w) pthread_join(th[w], NULL);
+  for (int w = started + 1; w < n_threads; ++w) ep_vjp_worker(&jobs[w]);
+  double sum = 0.0;
+  for (int64_t i = 0; i < tr->n; ++i) sum += gn[i];
+  *g_n0m1 = sum;
+  free(gn);
+  free(jobs);
+  free(th);
+  return 0;
+}

@@ -398,3 +398,104 @@ def test_zhs_vjp_matches_central_differences(orc):
     fd = richardson(lambda v: _loss(orc, sub, ar, Medium(md.kind, v, md.h), g), md.n0m1, hn)
     an = orc.zhs_vjp(sub, ar, md, g)["n0m1"]
     assert an == pytest.approx(fd, rel=1e-5)
+
+
+# --------------------------------------------------------- Endpoint adjoint
+def _ep_loss(orc, tr, ar, md, g, k=1.0):
+    return float(np.sum(g * orc.traces("endpoint", tr, ar, md, k=k)))
+
+
+@pytest.mark.parametrize("cfg", [0, 3])
+def test_endpoint_vjp_weight_is_exact_linear_share(orc, cfg):
+    """E is linear in qw: dL/dqw_i = L_i / qw_i (uniform and exponential
+    media)."""
+    w = config(cfg)
+    tr = w.tracks(40)
+    g = np.random.default_rng(15).normal(size=(w.array.m, w.array.n_bins, 3))
+    grads = orc.endpoint_vjp(tr, w.array, w.medium, g, n_threads=3)
+    nonzero = 0
+    for i in range(tr.n):
+        li = _ep_loss(orc, tr.take([i]), w.array, w.medium, g)
+        assert grads["qw"][i] == pytest.approx(li / tr.qw[i], rel=1e-10, abs=1e-300)
+        nonzero += li != 0.0
+    assert nonzero >= 10
+
+
+@pytest.mark.parametrize("cfg", [0, 3])
+def test_endpoint_vjp_matches_central_differences(orc, cfg):
+    """Positions and n0 - 1 against Richardson-extrapolated central
+    differences of the forward oracle (steps h and 2h; h = 1e-3 m and 1e-6
+    relative), skipping shifts that move an impulse across a bin edge (the
+    loss jumps there; the adjoint holds bins fixed)."""
+    w = config(cfg)
+    md, ar = w.medium, w.array
+    tr = w.tracks(400)
+    _, u, b = orc.propagate(tr, ar, md)
+    reach = np.flatnonzero(((b >= 0).any(axis=0)).any(axis=1))[:10]
+    tr = tr.take(reach)
+    g = np.random.default_rng(21).normal(size=(ar.m, ar.n_bins, 3))
+    grads = orc.endpoint_vjp(tr, ar, md, g)
+
+    def richardson(f, x0, h):
+        c = lambda s: (f(x0 + s) - f(x0 - s)) / (2 * s)
+        return (4.0 * c(h) - c(2 * h)) / 3.0
+
+    h = 1e-3
+    checked = 0
+    for i in range(tr.n):
+        one = tr.take([i])
+        _, u0, _ = orc.propagate(one, ar, md)
+        scale = max(np.abs(grads["p0"][:, i]).max(), np.abs(grads["p1"][:, i]).max())
+        for end in (0, 1):
+            for c, comp in enumerate("xyz"):
+                key = f"{comp}{end}"
+                base = float(one.arrays()[key][0])
+                moved = lambda v: Tracks(**{**one.arrays(), key: np.array([v])})
+                if any((np.floor(orc.propagate(moved(base + s), ar, md)[1]) != np.floor(u0)).any()
+                       for s in (-2 * h, 2 * h)):
+                    continue
+                fd = richardson(lambda v: _ep_loss(orc, moved(v), ar, md, g), base, h)
+                an = grads["p0" if end == 0 else "p1"][c, i]
+                assert abs(an - fd) <= 1e-6 * abs(fd) + 1e-7 * scale, (i, key, an, fd)
+                checked += 1
+    assert checked > 30
+    hn = 1e-6 * md.n0m1
+    keep = [i for i in range(tr.n)
+            if all((np.floor(orc.propagate(tr.take([i]), ar, Medium(md.kind, md.n0m1 + s, md.h))[1])
+                    == np.floor(orc.propagate(tr.take([i]), ar, md)[1])).all() for s in (-2 * hn, 2 * hn))]
+    sub = tr.take(keep)
+    assert sub.n >= 5
+    fd = richardson(lambda v: _ep_loss(orc, sub, ar, Medium(md.kind, v, md.h), g), md.n0m1, hn)
+    an = orc.endpoint_vjp(sub, ar, md, g)["n0m1"]
+    assert an == pytest.approx(fd, rel=1e-5)
+
+
+def test_endpoint_vjp_inside_the_cherenkov_cone(orc):
+    """Dense medium (n = 1.5) with antennas inside and outside the cone of a
+    fast track (signed Doppler factor on both sides): central differences of
+    every coordinate of both ends."""
+    md = Medium("uniform", 0.5, 8000.0)
+    ang = np.radians([5.0, 20.0, 40.0, 60.0])
+    dist = np.array([300.0, 310.7, 322.9, 337.3])
+    pts = np.stack([dist * np.sin(ang), np.zeros_like(ang), -dist * np.cos(ang)], 1)
+    tr = track_along((0.0, 0.0, 0.0), (0.0, 0.0, -1.0), 2.0, 0.99, qw=-1.3)
+    t_ar = 300.0 * 1.5 / C_LIGHT
+    ar = antennas(pts, t_ar - 50.0123e-9, 0.05e-9, 4096)
+    g = np.random.default_rng(3).normal(size=(ar.m, ar.n_bins, 3))
+    grads = orc.endpoint_vjp(tr, ar, md, g)
+    h = 1e-4
+    _, u0, _ = orc.propagate(tr, ar, md)
+    checked = 0
+    for end in (0, 1):
+        for c, comp in enumerate("xyz"):
+            key = f"{comp}{end}"
+            base = float(tr.arrays()[key][0])
+            moved = lambda v: Tracks(**{**tr.arrays(), key: np.array([v])})
+            if any((np.floor(orc.propagate(moved(base + s), ar, md)[1]) != np.floor(u0)).any()
+                   for s in (-2 * h, 2 * h)):
+                continue
+            fd = (_ep_loss(orc, moved(base + h), ar, md, g) - _ep_loss(orc, moved(base - h), ar, md, g)) / (2 * h)
+            an = grads["p0" if end == 0 else "p1"][c, 0]
+            assert an == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(grads["p0"]).max()), key
+            checked += 1
+    assert checked >= 5
