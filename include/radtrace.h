@@ -196,7 +196,8 @@ int rt_plan_set_timing_events(rt_plan *plan, void *start_event, void *stop_event
 int rt_propagate(const rt_plan *plan, const rt_tracks *tracks, double *t_arrival, int32_t *bin,
                  void *stream);
 
-/* Device workspace (bytes) rt_zhs_vjp needs for n_tracks tracks. */
+/* Device workspace (bytes) rt_zhs_vjp or rt_endpoint_vjp (by the plan's
+ * formalism) needs for n_tracks tracks. */
 int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes);
 
 /* Vector-Jacobian product of the ZHS traces (the differentiable form of the
@@ -218,6 +219,20 @@ int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *b
 int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, double *grad_qw,
                double *grad_p0, double *grad_p1, double *grad_n0m1, void *workspace,
                size_t workspace_bytes, void *stream);
+
+/* Vector-Jacobian product of the Endpoint traces (plan must be RT_ENDPOINT):
+ * the derivatives of L = sum grad_traces * E with respect to each track's
+ * qw, start point P0, end point P1 and n0_minus_1, with the velocity, the
+ * emission times and the bin each impulse lands in held fixed (the bin is a
+ * piecewise-constant function of the parameters; the jumps where an arrival
+ * crosses a bin edge are not part of the derivative). Through the impulse
+ * s k qw [r x (r x beta)] / ((1 - n_src beta.r) R dt): the distance and
+ * direction to every antenna, and n_src = 1 + n0_minus_1 exp(-z_P / h) (its
+ * height derivative enters the z component). Arguments, layouts, outputs and
+ * errors as rt_zhs_vjp; workspace >= rt_plan_vjp_workspace_bytes. */
+int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces,
+                    double *grad_qw, double *grad_p0, double *grad_p1, double *grad_n0m1,
+                    void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------ batches
  *

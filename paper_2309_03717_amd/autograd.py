@@ -1,8 +1,10 @@
-"""Differentiable ZHS traces: a torch.autograd.Function whose forward is the
-library's ZHS deposit and whose backward is its hand-written adjoint
-(rt_zhs_vjp). Differentiable inputs: per-track weights qw [n], start points
-p0 [3, n], end points p1 [3, n] and the refractivity n0 - 1 (0-d tensor);
-the emission times, the velocities and the antenna array are held fixed.
+"""Differentiable traces: a torch.autograd.Function whose forward is the
+library's deposit (ZHS or Endpoint) and whose backward is the matching
+hand-written adjoint (rt_zhs_vjp, rt_endpoint_vjp). Differentiable inputs:
+per-track weights qw [n], start points p0 [3, n], end points p1 [3, n] and
+the refractivity n0 - 1 (0-d tensor); the emission times, the velocities and
+the antenna array are held fixed (and, for the Endpoint formalism, the bins
+the impulses land in).
 """
 from __future__ import annotations
 
@@ -12,11 +14,12 @@ from . import radtrace as rt
 from .workloads import Medium
 
 
-class ZHSTraces(torch.autograd.Function):
+class RadioTraces(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, qw, p0, p1, n0m1, t0, t1, beta, det, medium_kind, scale_height, precision, k):
+    def forward(ctx, qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium_kind, scale_height,
+                precision, k):
         medium = Medium(medium_kind, float(n0m1.detach().cpu()), float(scale_height))
-        plan = rt.Plan(det, medium, "zhs", precision, k)
+        plan = rt.Plan(det, medium, formalism, precision, k)
         in_dtype = torch.float64 if precision == "fp64" else torch.float32
         tracks = rt.DeviceTracks(
             x0=p0[0].detach().double().contiguous(), y0=p0[1].detach().double().contiguous(),
@@ -32,15 +35,30 @@ class ZHSTraces(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad):
-        gq, gp0, gp1, gn = ctx.plan.zhs_vjp(ctx.tracks, grad)
+        gq, gp0, gp1, gn = ctx.plan.vjp(ctx.tracks, grad)
         dq, d0, d1, dn = ctx.dtypes
         return (gq.to(dq), gp0.to(d0), gp1.to(d1), gn.reshape(()).to(dn),
-                None, None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None, None)
 
 
-def zhs_traces(qw, p0, p1, n0m1, *, t0, t1, beta, det: rt.DeviceDetector, medium_kind: str,
-               scale_height: float = 8000.0, precision: str = "mixed", k: float = 1.0):
-    """ZHS traces [M, n_bins, 3] of the given tracks, differentiable in qw,
-    p0, p1 and n0m1."""
-    return ZHSTraces.apply(qw, p0, p1, n0m1, t0, t1, beta, det, medium_kind, scale_height,
-                           precision, k)
+# kept for callers of the ZHS-only name
+ZHSTraces = RadioTraces
+
+
+def radio_traces(formalism: str, qw, p0, p1, n0m1, *, t0, t1, beta, det: rt.DeviceDetector,
+                 medium_kind: str, scale_height: float = 8000.0, precision: str = "mixed",
+                 k: float = 1.0):
+    """Traces [M, n_bins, 3] of the given tracks in the given formalism
+    ("zhs" or "endpoint"), differentiable in qw, p0, p1 and n0m1."""
+    return RadioTraces.apply(qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium_kind,
+                             scale_height, precision, k)
+
+
+def zhs_traces(qw, p0, p1, n0m1, **kw):
+    """ZHS traces, differentiable in qw, p0, p1 and n0m1."""
+    return radio_traces("zhs", qw, p0, p1, n0m1, **kw)
+
+
+def endpoint_traces(qw, p0, p1, n0m1, **kw):
+    """Endpoint traces, differentiable in qw, p0, p1 and n0m1 (bins fixed)."""
+    return radio_traces("endpoint", qw, p0, p1, n0m1, **kw)

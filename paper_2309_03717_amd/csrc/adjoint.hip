@@ -1,4 +1,4 @@
-// adjoint.hip -- vector-Jacobian product of the ZHS traces.
+// adjoint.hip -- vector-Jacobian products of the ZHS and Endpoint traces.
 //
 // For a scalar loss with upstream gradient G = dL/dA over the traces
 // [M][B][3], the share of one (track, antenna) pair is
@@ -215,6 +215,91 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
   if (threadIdx.x == 0) v.n0_part[blockIdx.x] = red[0];
 }
 
+// Endpoint: the impulse of a landing end is E = c W / num with d = X - P,
+// c = s k qw / dt, q = (beta.d) / R^2, W = d q - beta and
+// num = R - n_src (beta.d); the bin it lands in is piecewise constant in the
+// parameters and held fixed. For f = g.E (g = G at that bin):
+//   df/dd_j = (c / num) (g_j q + (g.d) dq/dd_j) - c (g.W) / num^2 dnum/dd_j,
+//   dq/dd_j = beta_j / R^2 - 2 (beta.d) d_j / R^4,  dnum/dd_j = d_j / R - n_src beta_j,
+//   df/dn_src = c (g.W) (beta.d) / num^2,
+// and dP = -dd; n_src = 1 + (n0 - 1) e(z_P) adds the height derivative of e.
+template <int P>
+__global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
+  using In = typename std::conditional<P == 0, double, float>::type;
+  const Consts &c = v.c;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double gn_local = 0.0;
+  if (i < v.tr.n) {
+    const double pos[2][4] = {{v.tr.x0[i], v.tr.y0[i], v.tr.z0[i], v.tr.t0[i]},
+                              {v.tr.x1[i], v.tr.y1[i], v.tr.z1[i], v.tr.t1[i]}};
+    const double b[3] = {(double)((const In *)v.tr.bx)[i], (double)((const In *)v.tr.by)[i],
+                         (double)((const In *)v.tr.bz)[i]};
+    const double qw = (double)((const In *)v.tr.qw)[i];
+    bool ok = isfinite(qw) && isfinite(b[0]) && isfinite(b[1]) && isfinite(b[2]);
+    for (int e = 0; e < 2; ++e)
+      for (int k = 0; k < 4; ++k) ok = ok && isfinite(pos[e][k]);
+    double gq = 0.0, gp[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    double hf[2] = {0.0, 0.0}, ns[2] = {c.n_uniform, c.n_uniform};
+    if (c.medium == 1)
+      for (int e = 0; e < 2; ++e) {
+        hf[e] = height_factor(pos[e][2], c);
+        ns[e] = fma(c.n0m1, hf[e], 1.0);
+      }
+    const double kdt = c.k * c.inv_dt;
+    for (int64_t a = 0; ok && a < v.an.m; ++a) {
+      const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
+      const double ea = c.medium == 1 ? height_factor(az, c) : 0.0;
+      const In *ga = (const In *)v.grad + (size_t)a * c.n_bins * 3;
+      for (int e = 0; e < 2; ++e) {
+        const double ne = c.medium == 1 ? path_index(pos[e][2], az, hf[e], ea, c) : c.n_uniform;
+        double d[3], r, r2;
+        const double u = arrival_bins(pos[e][0], pos[e][1], pos[e][2], pos[e][3], ax, ay, az, tau,
+                                      ne, c, d[0], d[1], d[2], r, r2);
+        if (!(u >= 0.0 && u < c.nbins_d)) continue;
+        const double bd = fma(b[0], d[0], fma(b[1], d[1], b[2] * d[2]));
+        const double num = fma(-ns[e], bd, r);
+        if (num == 0.0) continue;
+        const int j = (int)u;
+        const double g[3] = {(double)ga[3 * j], (double)ga[3 * j + 1], (double)ga[3 * j + 2]};
+        const double s = e == 0 ? 1.0 : -1.0;
+        const double q = bd / r2;
+        double w[3];
+        for (int k = 0; k < 3; ++k) w[k] = fma(d[k], q, -b[k]);
+        const double gw = fma(g[0], w[0], fma(g[1], w[1], g[2] * w[2]));
+        const double gd = fma(g[0], d[0], fma(g[1], d[1], g[2] * d[2]));
+        const double cc = s * kdt * qw;
+        gq += s * kdt * gw / num;
+        const double a1 = cc / num, a2 = cc * gw / (num * num);
+        for (int k = 0; k < 3; ++k) {
+          const double dq = b[k] / r2 - 2.0 * bd * d[k] / (r2 * r2);
+          const double dnum = d[k] / r - ns[e] * b[k];
+          gp[e][k] -= a1 * (g[k] * q + gd * dq) - a2 * dnum;
+        }
+        const double dfn = a2 * bd;   // d f / d n_src
+        if (c.medium == 1) {
+          gn_local += dfn * hf[e];
+          gp[e][2] -= dfn * c.n0m1 * hf[e] / c.h;
+        } else {
+          gn_local += dfn;
+        }
+      }
+    }
+    v.g_qw[i] = gq;
+    for (int k = 0; k < 3; ++k) {
+      v.g_p0[(size_t)k * v.tr.n + i] = gp[0][k];
+      v.g_p1[(size_t)k * v.tr.n + i] = gp[1][k];
+    }
+  }
+  __shared__ double red[kVjpBlock];
+  red[threadIdx.x] = gn_local;
+  __syncthreads();
+  for (int s = kVjpBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) v.n0_part[blockIdx.x] = red[0];
+}
+
 __global__ void __launch_bounds__(256) n0_sum_kernel(const double *part, int64_t n, double *out) {
   __shared__ double red[256];
   double s = 0.0;
@@ -230,10 +315,15 @@ __global__ void __launch_bounds__(256) n0_sum_kernel(const double *part, int64_t
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ZHS: [Phi tables][per-workgroup n0 partials]; Endpoint: the partials only.
+static size_t phi_bytes(const rt_plan &p) {
+  if (p.formalism != RT_ZHS) return 0;
+  return align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double));
+}
+
 size_t vjp_workspace_bytes(const rt_plan &p, int64_t n) {
   const int64_t blocks = (n + kVjpBlock - 1) / kVjpBlock;
-  return align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double)) +
-         align256((size_t)std::max<int64_t>(blocks, 1) * sizeof(double));
+  return phi_bytes(p) + align256((size_t)std::max<int64_t>(blocks, 1) * sizeof(double));
 }
 
 hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, double *g_qw,
@@ -241,13 +331,14 @@ hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, do
                       hipStream_t stream) {
   char *ws = reinterpret_cast<char *>(workspace);
   double *phi = reinterpret_cast<double *>(ws);
-  ws += align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double));
-  double *part = reinterpret_cast<double *>(ws);
+  double *part = reinterpret_cast<double *>(ws + phi_bytes(p));
   const unsigned m = (unsigned)p.det.n_antennas;
-  if (p.precision == RT_FP64)
-    phi_kernel<double><<<m, 256, 0, stream>>>((const double *)grad, phi, p.det.n_bins);
-  else
-    phi_kernel<float><<<m, 256, 0, stream>>>((const float *)grad, phi, p.det.n_bins);
+  if (p.formalism == RT_ZHS) {
+    if (p.precision == RT_FP64)
+      phi_kernel<double><<<m, 256, 0, stream>>>((const double *)grad, phi, p.det.n_bins);
+    else
+      phi_kernel<float><<<m, 256, 0, stream>>>((const float *)grad, phi, p.det.n_bins);
+  }
   VjpArgs v;
   v.tr = track_ptrs(t);
   v.an = ant_ptrs(p.det);
@@ -259,10 +350,17 @@ hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, do
   v.g_p1 = g_p1;
   v.n0_part = part;
   const int64_t blocks = (t.n + kVjpBlock - 1) / kVjpBlock;
-  if (p.precision == RT_FP64)
-    vjp_kernel<0><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
-  else
-    vjp_kernel<1><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+  if (p.formalism == RT_ZHS) {
+    if (p.precision == RT_FP64)
+      vjp_kernel<0><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+    else
+      vjp_kernel<1><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+  } else {
+    if (p.precision == RT_FP64)
+      ep_vjp_kernel<0><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+    else
+      ep_vjp_kernel<1><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+  }
   n0_sum_kernel<<<1, 256, 0, stream>>>(part, blocks, g_n0);
   return hipGetLastError();
 }

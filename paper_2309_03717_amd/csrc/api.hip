@@ -219,11 +219,32 @@ int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *b
   return RT_OK;
 }
 
+static int vjp_call(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces,
+                    double *grad_qw, double *grad_p0, double *grad_p1, double *grad_n0m1,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
 int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, double *grad_qw,
                double *grad_p0, double *grad_p1, double *grad_n0m1, void *workspace,
                size_t workspace_bytes, void *stream) {
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ZHS) return fail(RT_E_INVALID, "rt_zhs_vjp needs an RT_ZHS plan");
+  return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
+                  workspace_bytes, stream);
+}
+
+int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces,
+                    double *grad_qw, double *grad_p0, double *grad_p1, double *grad_n0m1,
+                    void *workspace, size_t workspace_bytes, void *stream) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  if (plan->formalism != RT_ENDPOINT)
+    return fail(RT_E_INVALID, "rt_endpoint_vjp needs an RT_ENDPOINT plan");
+  return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
+                  workspace_bytes, stream);
+}
+
+static int vjp_call(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces,
+                    double *grad_qw, double *grad_p0, double *grad_p1, double *grad_n0m1,
+                    void *workspace, size_t workspace_bytes, void *stream) {
   int s = check_tracks(plan, tracks);
   if (s != RT_OK) return s;
   if (!grad_traces || !grad_n0m1) return fail(RT_E_INVALID, "grad_traces or grad_n0m1 is NULL");
@@ -237,7 +258,7 @@ int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, 
   (void)hipGetLastError();
   hipError_t e = rt::launch_vjp(*plan, *tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1,
                                 workspace, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "launching the ZHS adjoint kernels");
+  if (e != hipSuccess) return hip_fail(e, "launching the adjoint kernels");
   return RT_OK;
 }
 

@@ -88,6 +88,7 @@ _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
 _lib.rt_plan_set_timing_events.argtypes = [_P, _P, _P]
 _lib.rt_plan_vjp_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_zhs_vjp.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P, _P, _P, _P, C.c_size_t, _P]
+_lib.rt_endpoint_vjp.argtypes = _lib.rt_zhs_vjp.argtypes
 _lib.rt_batch_create.argtypes = [C.POINTER(_P), C.POINTER(rt_shower), C.c_int32, C.c_int,
                                  C.c_double, C.POINTER(rt_batch_options)]
 _lib.rt_batch_destroy.argtypes = [_P]
@@ -282,6 +283,15 @@ def rt_zhs_vjp(plan: int, tracks: rt_tracks, grad_traces: torch.Tensor, grad_qw:
            "rt_zhs_vjp")
 
 
+def rt_endpoint_vjp(plan: int, tracks: rt_tracks, grad_traces: torch.Tensor,
+                    grad_qw: torch.Tensor, grad_p0: torch.Tensor, grad_p1: torch.Tensor,
+                    grad_n0m1: torch.Tensor, workspace: torch.Tensor, stream=None) -> None:
+    _check(_lib.rt_endpoint_vjp(plan, C.byref(tracks), _ptr(grad_traces), _ptr(grad_qw),
+                                _ptr(grad_p0), _ptr(grad_p1), _ptr(grad_n0m1), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream)),
+           "rt_endpoint_vjp")
+
+
 def rt_batch_create(showers, precision: int, k: float, options: Optional[rt_batch_options] = None
                     ) -> int:
     """showers: a sequence of rt_shower structs."""
@@ -379,6 +389,19 @@ class Plan:
     def zhs_vjp(self, tracks: DeviceTracks, grad_traces: torch.Tensor, stream=None):
         """Gradients (qw [n], p0 [3, n], p1 [3, n], n0m1 [1]) of sum(grad * A),
         all float64, for a ZHS plan."""
+        if self.formalism != RT_ZHS:
+            raise ValueError("zhs_vjp needs a ZHS plan")
+        return self.vjp(tracks, grad_traces, stream)
+
+    def endpoint_vjp(self, tracks: DeviceTracks, grad_traces: torch.Tensor, stream=None):
+        """Gradients (qw [n], p0 [3, n], p1 [3, n], n0m1 [1]) of sum(grad * E),
+        all float64, for an Endpoint plan (landing bins held fixed)."""
+        if self.formalism != RT_ENDPOINT:
+            raise ValueError("endpoint_vjp needs an Endpoint plan")
+        return self.vjp(tracks, grad_traces, stream)
+
+    def vjp(self, tracks: DeviceTracks, grad_traces: torch.Tensor, stream=None):
+        """The vector-Jacobian product of the plan's formalism."""
         dev = self.det.x.device
         n = tracks.n
         g = grad_traces.to(self.dtype).contiguous()
@@ -390,7 +413,8 @@ class Plan:
         gn = torch.empty(1, dtype=torch.float64, device=dev)
         ws = torch.empty(max(rt_plan_vjp_workspace_bytes(self.handle, n), 256), dtype=torch.uint8,
                          device=dev)
-        rt_zhs_vjp(self.handle, tracks.struct(self.precision), g, gq, gp0, gp1, gn, ws, stream)
+        fn = rt_zhs_vjp if self.formalism == RT_ZHS else rt_endpoint_vjp
+        fn(self.handle, tracks.struct(self.precision), g, gq, gp0, gp1, gn, ws, stream)
         return gq, gp0, gp1, gn
 
     def propagate(self, tracks: DeviceTracks, stream=None):
