@@ -249,6 +249,68 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adjoint(args):
+    """Differentiable workload: 1e6 tracks x 64 antennas (8 x 8 grid, 75 m),
+    4096 bins x 0.1 ns, exponential medium, mixed precision. One step is the
+    forward traces plus the vector-Jacobian product of a trace loss, for the
+    ZHS and the Endpoint formalism; the metric counts forward + adjoint
+    pairs."""
+    import torch
+    from paper_2309_03717_amd import radtrace as rt
+    from paper_2309_03717_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.config(3)
+    n = args.tracks or w.n_tracks
+    tr = w.tracks(n, mixed=True)
+    dtr = rt.DeviceTracks.from_tracks(tr)
+    det = rt.DeviceDetector.from_array(w.array)
+    plans = {f: rt.Plan(det, w.medium, f, "mixed") for f in ("zhs", "endpoint")}
+    grad = torch.randn((w.array.m, w.array.n_bins, 3), device="cuda", dtype=torch.float32,
+                       generator=torch.Generator(device="cuda").manual_seed(3))
+    torch.cuda.synchronize()
+    times = {}
+
+    def step(record):
+        for f, plan in plans.items():
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
+            plan.traces(dtr)
+            ev[1].record()
+            plan.vjp(dtr, grad)
+            ev[2].record()
+            if record:
+                times.setdefault(f, []).append(ev)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        step(True)
+    b.record()
+    torch.cuda.synchronize()
+    ms_step = a.elapsed_time(b) / args.steps
+    pairs = n * w.array.m
+    per = {}
+    for f, evs in times.items():
+        fw = sum(e[0].elapsed_time(e[1]) for e in evs) / len(evs)
+        bw = sum(e[1].elapsed_time(e[2]) for e in evs) / len(evs)
+        per[f] = {"forward_ms": round(fw, 3), "vjp_ms": round(bw, 3),
+                  "forward_pairs_per_s": pairs / (fw / 1e3), "vjp_pairs_per_s": pairs / (bw / 1e3)}
+    out = {"metric": "antenna-track pairs/sec, forward + adjoint (ZHS, Endpoint)",
+           "value": 2 * 2 * pairs / (ms_step / 1e3), "unit": "pairs/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": w.name if n == w.n_tracks else f"{w.name}[{n}]",
+                      "n_tracks": n, "n_antennas": w.array.m, "n_bins": w.array.n_bins,
+                      "precision": "mixed"},
+           "per_formalism": per}
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """Calibration for hardware byte counters: a plain device-to-device copy
     of a known size (args.copy_mib MiB read and written per launch)."""
@@ -285,8 +347,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 17)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
-    ap.add_argument("--workload", default="grid4096", choices=["grid4096", "batched", "copy"],
+    ap.add_argument("--workload", default="grid4096",
+                    choices=["grid4096", "batched", "adjoint", "copy"],
                     help="grid4096: 1e8 tracks x 4096 antennas (default); batched: 256 showers; "
+                         "adjoint: forward + VJP on 1e6 tracks x 64 antennas; "
                          "copy: byte-counter calibration")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--showers", type=int, default=256, help="batched: number of showers")
@@ -302,6 +366,9 @@ def main():
         return
     if args.workload == "copy":
         bench_copy(args)
+        return
+    if args.workload == "adjoint":
+        bench_adjoint(args)
         return
 
     import torch

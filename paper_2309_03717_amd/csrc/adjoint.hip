@@ -134,12 +134,18 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
     const double e1 = c.medium == 1 ? height_factor(z1, c) : 0.0;
     const double mx = (x0 + x1) * 0.5, my = (y0 + y1) * 0.5, mz = (z0 + z1) * 0.5;
     const double kdt = c.k * (t1 - t0);   // I = kdt * qw * beta_perp / R_m
+    // path indices and their derivatives depend on the antenna height only:
+    // recomputed when it changes (a uniform test: every lane sees the same
+    // antenna)
+    double z_prev = __builtin_nan(""), ne0 = 0, dnz0 = 0, dnn0 = 0, ne1 = 0, dnz1 = 0, dnn1 = 0;
     for (int64_t a = 0; ok && a < v.an.m; ++a) {
       const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
-      const double ea = c.medium == 1 ? height_factor(az, c) : 0.0;
-      double ne0, dnz0, dnn0, ne1, dnz1, dnn1;
-      index_derivatives(z0, az, e0, ea, c, ne0, dnz0, dnn0);
-      index_derivatives(z1, az, e1, ea, c, ne1, dnz1, dnn1);
+      if (!(az == z_prev)) {
+        const double ea = c.medium == 1 ? height_factor(az, c) : 0.0;
+        index_derivatives(z0, az, e0, ea, c, ne0, dnz0, dnn0);
+        index_derivatives(z1, az, e1, ea, c, ne1, dnz1, dnn1);
+        z_prev = az;
+      }
       double d0x, d0y, d0z, r0, r02, d1x, d1y, d1z, r1, r12;
       const double us = arrival_bins(x0, y0, z0, t0, ax, ay, az, tau, ne0, c, d0x, d0y, d0z, r0, r02);
       const double ue = arrival_bins(x1, y1, z1, t1, ax, ay, az, tau, ne1, c, d1x, d1y, d1z, r1, r12);
@@ -151,22 +157,23 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
       const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
       if (r2 == 0.0) continue;
       const double r = sqrt(r2);
+      const double ir = 1.0 / r, ir2 = ir * ir;
       const double bd = (b[0] * d[0] + b[1] * d[1]) + b[2] * d[2];
       double iu[3];   // integral per unit weight
-      for (int k = 0; k < 3; ++k) iu[k] = kdt * (b[k] - bd / r2 * d[k]) / r;
+      for (int k = 0; k < 3; ++k) iu[k] = kdt * (b[k] - bd * ir2 * d[k]) * ir;
       GradView<In> gv{(const In *)v.grad + (size_t)a * c.n_bins * 3,
                       v.phi + (size_t)a * 3 * (c.n_bins + 1), c.n_bins, c.nbins_d};
       const bool same_bin = floor(ulo) == floor(uhi);
-      const double w = uhi - ulo;
+      const double iw = 1.0 / (uhi - ulo);
       double gbar[3], dl_dlo = 0.0, dl_dhi = 0.0;
       for (int k = 0; k < 3; ++k) {
         if (same_bin) {
           gbar[k] = gv.value(k, ulo);
         } else {
-          gbar[k] = (gv.cumulative(k, uhi) - gv.cumulative(k, ulo)) / w;
+          gbar[k] = (gv.cumulative(k, uhi) - gv.cumulative(k, ulo)) * iw;
           const double ik = qw * iu[k] * c.inv_dt;
-          dl_dhi += ik * (gv.value(k, uhi) - gbar[k]) / w;
-          dl_dlo += ik * (gbar[k] - gv.value(k, ulo)) / w;
+          dl_dhi += ik * (gv.value(k, uhi) - gbar[k]) * iw;
+          dl_dlo += ik * (gbar[k] - gv.value(k, ulo)) * iw;
         }
       }
       // weight: the pair's loss share is linear in qw
@@ -179,10 +186,10 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
       const double kk = kdt * qw;
       const double gb = (gam[0] * b[0] + gam[1] * b[1]) + gam[2] * b[2];
       const double gd = (gam[0] * d[0] + gam[1] * d[1]) + gam[2] * d[2];
-      const double r3 = r2 * r, r5 = r3 * r2;
+      const double ir3 = ir2 * ir, ir5 = ir3 * ir2;
       for (int k = 0; k < 3; ++k) {
-        const double dl_dd = kk * (-(gb * d[k] + gd * b[k] + bd * gam[k]) / r3 +
-                                   3.0 * bd * gd * d[k] / r5);
+        const double dl_dd = kk * (-(gb * d[k] + gd * b[k] + bd * gam[k]) * ir3 +
+                                   3.0 * bd * gd * d[k] * ir5);
         gp0[k] -= 0.5 * dl_dd;   // d = X - (P0 + P1) / 2
         gp1[k] -= 0.5 * dl_dd;
       }
@@ -190,12 +197,13 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
       const double dl_ds = (start_lo ? dl_dlo : dl_dhi) * c.inv_dt * c.inv_c;
       const double dl_de = (start_lo ? dl_dhi : dl_dlo) * c.inv_dt * c.inv_c;
       // d (n_eff R) / d P = -n_eff d / R + R dn_eff/dz e_z
-      gp0[0] += dl_ds * (-ne0 * d0x / r0);
-      gp0[1] += dl_ds * (-ne0 * d0y / r0);
-      gp0[2] += dl_ds * (-ne0 * d0z / r0 + r0 * dnz0);
-      gp1[0] += dl_de * (-ne1 * d1x / r1);
-      gp1[1] += dl_de * (-ne1 * d1y / r1);
-      gp1[2] += dl_de * (-ne1 * d1z / r1 + r1 * dnz1);
+      const double n0r = ne0 / r0, n1r = ne1 / r1;
+      gp0[0] += dl_ds * (-n0r * d0x);
+      gp0[1] += dl_ds * (-n0r * d0y);
+      gp0[2] += dl_ds * (-n0r * d0z + r0 * dnz0);
+      gp1[0] += dl_de * (-n1r * d1x);
+      gp1[1] += dl_de * (-n1r * d1y);
+      gp1[2] += dl_de * (-n1r * d1z + r1 * dnz1);
       gn_local += dl_ds * r0 * dnn0 + dl_de * r1 * dnn1;
     }
     v.g_qw[i] = gq;
@@ -246,12 +254,17 @@ __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
         ns[e] = fma(c.n0m1, hf[e], 1.0);
       }
     const double kdt = c.k * c.inv_dt;
+    double z_prev = __builtin_nan(""), nes[2] = {c.n_uniform, c.n_uniform};
     for (int64_t a = 0; ok && a < v.an.m; ++a) {
       const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
-      const double ea = c.medium == 1 ? height_factor(az, c) : 0.0;
+      if (c.medium == 1 && !(az == z_prev)) {   // uniform test: one antenna per step
+        const double ea = height_factor(az, c);
+        for (int e = 0; e < 2; ++e) nes[e] = path_index(pos[e][2], az, hf[e], ea, c);
+        z_prev = az;
+      }
       const In *ga = (const In *)v.grad + (size_t)a * c.n_bins * 3;
       for (int e = 0; e < 2; ++e) {
-        const double ne = c.medium == 1 ? path_index(pos[e][2], az, hf[e], ea, c) : c.n_uniform;
+        const double ne = nes[e];
         double d[3], r, r2;
         const double u = arrival_bins(pos[e][0], pos[e][1], pos[e][2], pos[e][3], ax, ay, az, tau,
                                       ne, c, d[0], d[1], d[2], r, r2);
@@ -262,17 +275,18 @@ __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
         const int j = (int)u;
         const double g[3] = {(double)ga[3 * j], (double)ga[3 * j + 1], (double)ga[3 * j + 2]};
         const double s = e == 0 ? 1.0 : -1.0;
-        const double q = bd / r2;
+        const double ir2 = 1.0 / r2, ir = r * ir2, inum = 1.0 / num;
+        const double q = bd * ir2;
         double w[3];
         for (int k = 0; k < 3; ++k) w[k] = fma(d[k], q, -b[k]);
         const double gw = fma(g[0], w[0], fma(g[1], w[1], g[2] * w[2]));
         const double gd = fma(g[0], d[0], fma(g[1], d[1], g[2] * d[2]));
         const double cc = s * kdt * qw;
-        gq += s * kdt * gw / num;
-        const double a1 = cc / num, a2 = cc * gw / (num * num);
+        gq += s * kdt * gw * inum;
+        const double a1 = cc * inum, a2 = a1 * gw * inum;
         for (int k = 0; k < 3; ++k) {
-          const double dq = b[k] / r2 - 2.0 * bd * d[k] / (r2 * r2);
-          const double dnum = d[k] / r - ns[e] * b[k];
+          const double dq = (b[k] - 2.0 * q * d[k]) * ir2;
+          const double dnum = d[k] * ir - ns[e] * b[k];
           gp[e][k] -= a1 * (g[k] * q + gd * dq) - a2 * dnum;
         }
         const double dfn = a2 * bd;   // d f / d n_src
