@@ -249,6 +249,60 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_shower(args):
+    """Shower-like, time-ordered tracks (workloads.shower_tracks) on the
+    4096-antenna grid, mixed precision, both formalisms, against random
+    tracks of the grid workload with the same count: the lanes of a wave now
+    land in neighbouring bins, which stresses the LDS accumulation."""
+    import torch
+    from paper_2309_03717_amd import radtrace as rt
+    from paper_2309_03717_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.config(2)
+    n = args.tracks or (1 << 24)
+    chunk = w.chunk
+    det = rt.DeviceDetector.from_array(w.array)
+    plans = {f: rt.Plan(det, w.medium, f, "mixed", k=rt.K_SI) for f in ("endpoint", "zhs")}
+    res = {}
+    for kind in ("shower", "random"):
+        chunks = []
+        for lo in range(0, n, chunk):
+            m = min(chunk, n - lo)
+            t = (W.shower_tracks(W.SHOWER_SEED, m, start=lo) if kind == "shower"
+                 else w.tracks(m, start=lo)).to_mixed()
+            chunks.append(rt.DeviceTracks.from_tracks(t))
+        traces = {f: plans[f].new_traces() for f in plans}
+        for f in plans:   # warm-up
+            plans[f].accumulate(chunks[0], traces[f])
+        torch.cuda.synchronize()
+        for f, plan in plans.items():
+            evs = []
+            for _ in range(args.steps):
+                traces[f].zero_()
+                for c in chunks:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    rt.rt_plan_set_timing_events(plan.handle, a, b)
+                    plan.accumulate(c, traces[f])
+                    evs.append((a, b))
+            torch.cuda.synchronize()
+            ms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+            res.setdefault(kind, {})[f] = {"deposit_ms": round(ms, 3),
+                                           "pairs_per_s": n * w.array.m / (ms / 1e3)}
+        log(f"{kind}: {res[kind]}")
+        del chunks
+    tot = {k: 2 * n * w.array.m / sum(v[f]["deposit_ms"] for f in v) * 1e3 for k, v in res.items()}
+    out = {"metric": "antenna-track pairs/sec (Endpoint, ZHS), shower-like vs random tracks",
+           "value": tot["shower"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": 1, "ms_per_step": round(sum(v["deposit_ms"] for v in res["shower"].values()), 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64+f32", "data": "synthetic",
+           "config": {"workload": f"shower-{n}trk-grid4096-expn-mixed", "n_tracks": n,
+                      "n_antennas": w.array.m},
+           "random_tracks_value": tot["random"], "per_kind": res}
+    print(json.dumps(out), flush=True)
+
+
 def bench_adjoint(args):
     """Differentiable workload: 1e6 tracks x 64 antennas (8 x 8 grid, 75 m),
     4096 bins x 0.1 ns, exponential medium, mixed precision. One step is the
@@ -348,9 +402,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
     ap.add_argument("--workload", default="grid4096",
-                    choices=["grid4096", "batched", "adjoint", "copy"],
+                    choices=["grid4096", "batched", "adjoint", "shower", "copy"],
                     help="grid4096: 1e8 tracks x 4096 antennas (default); batched: 256 showers; "
                          "adjoint: forward + VJP on 1e6 tracks x 64 antennas; "
+                         "shower: shower-like vs random tracks on the grid; "
                          "copy: byte-counter calibration")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--showers", type=int, default=256, help="batched: number of showers")
@@ -369,6 +424,9 @@ def main():
         return
     if args.workload == "adjoint":
         bench_adjoint(args)
+        return
+    if args.workload == "shower":
+        bench_shower(args)
         return
 
     import torch

@@ -224,6 +224,73 @@ def draw_tracks(seed: int, n: int, recipe: TrackRecipe, start: int = 0) -> Track
     return parts[0] if len(parts) == 1 else Tracks.concat(parts)
 
 
+@dataclass(frozen=True)
+class ShowerRecipe:
+    """A shower-like track stream (a stand-in for the particle tracks of one
+    air shower, whose data the paper uses but does not publish): a thin
+    particle front moving down a vertical axis at c, a longitudinal profile
+    peaking at ``h_max`` (Gaussian in height, truncated), an exponential
+    lateral density, a front that thickens away from the axis, short tracks
+    close to the axis direction and a negative charge excess. Within each
+    seeded block the tracks are ordered by emission time, so neighbouring
+    tracks (the lanes of one wave) arrive at an antenna almost together."""
+    h_max: float = 4_000.0       # m
+    h_sigma: float = 1_500.0     # m
+    z_lo: float = 300.0          # m, profile truncation
+    z_hi: float = 12_000.0
+    r_scale: float = 30.0        # m, lateral exponential scale
+    front_ns: float = 1.0        # ns, front thickness on the axis, x (1 + r / 10 m)
+    cap_deg: float = 5.0         # direction within this angle of straight down
+    len_lo: float = 0.1          # m
+    len_hi: float = 2.0
+    beta_lo: float = 0.99
+    beta_hi: float = 0.99999
+    neg_frac: float = 0.6        # fraction of negative tracks
+
+
+def _draw_shower_block(rng: np.random.Generator, n: int, r: ShowerRecipe) -> Tracks:
+    # fixed draw order: charge, height, radius, azimuth, front delay,
+    # cos(theta), phi, length, beta
+    q = np.where(rng.random(n) < r.neg_frac, -1.0, 1.0)
+    z0 = np.clip(rng.normal(r.h_max, r.h_sigma, n), r.z_lo, r.z_hi)
+    rad = rng.exponential(r.r_scale, n)
+    az = rng.uniform(0.0, 2.0 * math.pi, n)
+    delay = np.abs(rng.normal(0.0, r.front_ns * 1e-9, n)) * (1.0 + rad / 10.0)
+    cos_t = rng.uniform(math.cos(math.radians(r.cap_deg)), 1.0, n)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    length = rng.uniform(r.len_lo, r.len_hi, n)
+    beta = rng.uniform(r.beta_lo, r.beta_hi, n)
+    x0, y0 = rad * np.cos(az), rad * np.sin(az)
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    ux, uy, uz = sin_t * np.cos(phi), sin_t * np.sin(phi), -cos_t
+    x1, y1, z1 = x0 + length * ux, y0 + length * uy, z0 + length * uz
+    t0 = (Z_AXIS - z0) / C_LIGHT + delay
+    t1 = t0 + length / (beta * C_LIGHT)
+    order = np.argsort(t0, kind="stable")
+    return Tracks(x0, y0, z0, t0, x1, y1, z1, t1, beta * ux, beta * uy, beta * uz, q).take(order)
+
+
+def shower_tracks(seed: int, n: int, recipe: ShowerRecipe = ShowerRecipe(),
+                  start: int = 0) -> Tracks:
+    """Tracks [start, start + n) of a shower-like stream (same block seeding
+    as draw_tracks)."""
+    if n <= 0:
+        z = np.zeros(0)
+        return Tracks(*([z] * 12))
+    parts = []
+    b0, b1 = start // BLOCK, (start + n - 1) // BLOCK
+    for b in range(b0, b1 + 1):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, b])))
+        blk = _draw_shower_block(rng, BLOCK, recipe)
+        lo = max(start, b * BLOCK) - b * BLOCK
+        hi = min(start + n, (b + 1) * BLOCK) - b * BLOCK
+        parts.append(blk.slice(lo, hi))
+    return parts[0] if len(parts) == 1 else Tracks.concat(parts)
+
+
+SHOWER_SEED = SEED_BASE + 5
+
+
 # --------------------------------------------------------------------------- workloads
 @dataclass
 class Workload:

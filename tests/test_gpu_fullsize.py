@@ -159,3 +159,22 @@ def test_batched_256_showers_sampled(rt, orc):
         print("shower", i, sh.formalism, sh.medium.kind, sh.n_tracks, sh.array.m, sh.array.n_bins,
               "max rel L2", err.max())
         assert err.max() <= MIXED_BOUND
+
+
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_shower_like_stream_sampled_antennas(rt, orc, formalism):
+    """A time-ordered, shower-like chunk of 2^22 tracks on the 4096-antenna
+    grid (neighbouring lanes land in neighbouring bins at antennas near the
+    axis): sampled antennas, centre ones included, against the oracle."""
+    w = W.config(2)
+    tr = W.shower_tracks(W.SHOWER_SEED, 1 << 22).to_mixed()
+    k = 4.80320471518522e-18
+    got, _ = gpu_full(rt, w.array, w.medium, formalism, "mixed", tr, k)
+    idx = np.unique(np.concatenate([sample_antennas(w.array.m, nx=64),
+                                    [2015, 2016, 2079, 2080, 2081, 2144]]))
+    ref = orc.traces(formalism, tr.widened(), sub_array(w.array, idx), w.medium, k=k,
+                     n_threads=THREADS)
+    err = rel_l2(got[idx], ref)
+    print(formalism, "shower-like: max rel L2", err.max())
+    assert np.abs(ref).max() > 0
+    assert err.max() <= MIXED_BOUND

@@ -3,6 +3,7 @@ distributions of the synthetic workloads."""
 import math
 
 import numpy as np
+import pytest
 
 from paper_2309_03717_amd import workloads as W
 
@@ -73,3 +74,19 @@ def test_batched_showers_recipe():
         assert 0.1e-9 <= s.array.dt <= 0.5e-9
     assert {s.formalism for s in sh} == {"endpoint", "zhs"}
     assert {s.medium.kind for s in sh} == {"uniform", "exponential"}
+
+
+def test_shower_stream_is_reproducible_time_ordered_and_regenerable():
+    a = W.shower_tracks(W.SHOWER_SEED, 3 * W.BLOCK // 2)
+    b = W.shower_tracks(W.SHOWER_SEED, W.BLOCK // 4, start=W.BLOCK + 100)
+    for f in W.TRACK_FIELDS:
+        assert np.array_equal(getattr(a, f)[W.BLOCK + 100:W.BLOCK + 100 + W.BLOCK // 4],
+                              getattr(b, f))
+    blk = a.slice(0, W.BLOCK)
+    assert np.all(np.diff(blk.t0) >= 0)            # time-ordered within a block
+    assert (a.qw < 0).mean() == pytest.approx(0.6, abs=0.01)
+    assert np.all(a.t1 > a.t0)
+    r = np.hypot(a.x0, a.y0)
+    assert np.median(r) == pytest.approx(30.0 * np.log(2), rel=0.05)
+    L = np.sqrt((a.x1 - a.x0) ** 2 + (a.y1 - a.y0) ** 2 + (a.z1 - a.z0) ** 2)
+    assert L.min() >= 0.1 - 1e-9 and L.max() <= 2.0 + 1e-9
