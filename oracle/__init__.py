@@ -45,7 +45,9 @@ class _Antennas(C.Structure):
 
 
 class _Medium(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("n0m1", C.c_double), ("h", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("n0m1", C.c_double), ("h", C.c_double),
+                ("f", C.POINTER(C.c_double)), ("n_f", C.c_int32), ("z0", C.c_double),
+                ("dz", C.c_double)]
 
 
 _lib = None
@@ -89,7 +91,13 @@ class _Args:
         a = [_f64(array.x), _f64(array.y), _f64(array.z), _f64(array.t_start)]
         self.keep += a
         self.ar = _Antennas(array.m, *[_dp(v) for v in a], float(array.dt), int(array.n_bins))
-        self.md = _Medium(medium.code, float(medium.n0m1), float(medium.h))
+        if medium.kind == "tabulated":
+            f = _f64(np.asarray(medium.table, dtype=np.float64))
+            self.keep.append(f)
+            self.md = _Medium(medium.code, float(medium.n0m1), float(medium.h), _dp(f), f.size,
+                              float(medium.z0), float(medium.dz))
+        else:
+            self.md = _Medium(medium.code, float(medium.n0m1), float(medium.h), None, 0, 0.0, 1.0)
 
 
 _Tracks._fields_names = staticmethod(lambda: [f for f, _ in _Tracks._fields_[1:]])

@@ -43,6 +43,12 @@
  * are always visited in order, so the result is bit-identical for any thread
  * count or bunch size (§5, Figs. 6 and 7).
  *
+ * Media: uniform, exponential (the closed forms above) and tabulated: n(z) =
+ * 1 + n0m1 f(z) with f piecewise linear through equally spaced nodes, whose
+ * path mean is the exact integral of f over the path divided by its height
+ * difference, evaluated in a fixed operation order (tab_F) that is part of
+ * the timing chain.
+ *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared -pthread -lm
  */
 #include <math.h>
@@ -71,19 +77,55 @@ typedef struct {
 } orc_antennas;
 
 typedef struct {
-  int32_t kind;  /* 0: uniform n = 1 + n0m1; 1: exponential n = 1 + n0m1 exp(-z/h) */
-  double n0m1;   /* refractivity at z = 0 */
+  int32_t kind;  /* 0: uniform n = 1 + n0m1; 1: exponential n = 1 + n0m1 exp(-z/h);
+                    2: tabulated n = 1 + n0m1 f(z) */
+  double n0m1;   /* refractivity scale (at z = 0 for the exponential profile) */
   double h;      /* scale height (m), exponential only */
+  /* tabulated only: f(z) is piecewise linear through f[i] at z0 + i dz
+   * (i = 0 .. n_f - 1, n_f >= 2) and constant beyond the first and last node */
+  const double *f;
+  int32_t n_f;
+  double z0, dz;
 } orc_medium;
 
 int orc_version(void) { return ORC_VERSION; }
 
 /* ------------------------------------------------------------------ medium */
 
+/* Tabulated profile: f(z), interpolated linearly between nodes. */
+static double tab_f(const orc_medium *md, double z) {
+  double t = (z - md->z0) * (1.0 / md->dz);
+  int64_t last = md->n_f - 1;
+  if (!(t > 0.0)) return md->f[0];
+  if (t >= (double)last) return md->f[last];
+  int64_t i = (int64_t)floor(t);
+  double w = t - (double)i;
+  return md->f[i] + w * (md->f[i + 1] - md->f[i]);
+}
+
+/* Tabulated profile: F(z), the integral of f from z0 to z, exact for the
+ * piecewise-linear f: trapezoids of the whole cells below z, summed from the
+ * first node up, plus the part of z's own cell; linear with slope f[0] below
+ * z0 and f[last] above the last node. */
+static double tab_F(const orc_medium *md, double z) {
+  const double *f = md->f;
+  const double dz = md->dz;
+  int64_t last = md->n_f - 1;
+  double t = (z - md->z0) * (1.0 / dz);
+  if (!(t > 0.0)) return f[0] * (z - md->z0);
+  int64_t i = t >= (double)last ? last : (int64_t)floor(t);
+  double acc = 0.0;
+  for (int64_t j = 1; j <= i; ++j) acc += (0.5 * dz) * (f[j - 1] + f[j]);
+  if (i == last) return acc + f[last] * (z - (md->z0 + (double)last * dz));
+  double w = t - (double)i;
+  return acc + dz * (w * f[i] + (0.5 * w * w) * (f[i + 1] - f[i]));
+}
+
 /* Local refractive index n(z) at the emission point (§2: the propagator is
  * built from an environment; media of varying properties, §1). */
 static double index_at(const orc_medium *md, double z) {
   if (md->kind == 0) return 1.0 + md->n0m1;
+  if (md->kind == 2) return 1.0 + md->n0m1 * tab_f(md, z);
   return 1.0 + md->n0m1 * exp(-(z / md->h));
 }
 
@@ -93,6 +135,10 @@ static double index_at(const orc_medium *md, double z) {
 static double effective_index(const orc_medium *md, double zp, double za) {
   if (md->kind == 0) return 1.0 + md->n0m1;
   double dz = zp - za;
+  if (md->kind == 2) {   /* the mean of n along the path, from the integral F */
+    if (fabs(dz) >= 1e-3) return 1.0 + md->n0m1 * ((tab_F(md, zp) - tab_F(md, za)) / dz);
+    return 1.0 + md->n0m1 * tab_f(md, (zp + za) * 0.5);
+  }
   if (fabs(dz) >= 1e-3) {
     double ep = exp(-(zp / md->h));
     double ea = exp(-(za / md->h));
@@ -125,6 +171,12 @@ static path propagate(const orc_antennas *ar, const orc_medium *md, int64_t a,
   p.t = tp + (neff * p.r) * inv_c;
   p.u = (p.t - ar->t_start[a]) * inv_dt;
   return p;
+}
+
+/* A tabulated medium needs at least two nodes and a positive spacing. */
+static int medium_ok(const orc_medium *md) {
+  if (md->kind != 2) return md->kind == 0 || md->kind == 1;
+  return md->f && md->n_f >= 2 && md->dz > 0.0;
 }
 
 /* Bin of u, or -1 outside [0, n_bins) (NaN is outside). */
@@ -270,7 +322,7 @@ static void *loop_worker(void *arg) {
 int orc_traces(int formalism, const orc_tracks *tr, const orc_antennas *ar, const orc_medium *md,
                double k, double *traces, int n_threads, int64_t bunch) {
   if (!tr || !ar || !md || !traces || (formalism != 0 && formalism != 1)) return -1;
-  if (ar->m < 0 || tr->n < 0 || ar->n_bins < 0 || !(ar->dt > 0.0)) return -1;
+  if (ar->m < 0 || tr->n < 0 || ar->n_bins < 0 || !(ar->dt > 0.0) || !medium_ok(md)) return -1;
   if (ar->m == 0 || tr->n == 0 || ar->n_bins == 0) return 0;
   if (n_threads < 1) n_threads = 1;
   if (bunch <= 0) bunch = (ar->m + n_threads - 1) / n_threads;
@@ -298,7 +350,7 @@ int orc_traces(int formalism, const orc_tracks *tr, const orc_antennas *ar, cons
  * (end * n + i) * m + a. Any output pointer may be NULL. */
 int orc_propagate(const orc_tracks *tr, const orc_antennas *ar, const orc_medium *md,
                   double *t_out, double *u_out, int32_t *bin_out) {
-  if (!tr || !ar || !md || !(ar->dt > 0.0)) return -1;
+  if (!tr || !ar || !md || !(ar->dt > 0.0) || !medium_ok(md)) return -1;
   for (int end = 0; end < 2; ++end)
     for (int64_t i = 0; i < tr->n; ++i)
       for (int64_t a = 0; a < ar->m; ++a) {
@@ -469,6 +521,7 @@ int orc_zhs_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_medium *
                 int n_threads) {
   if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
   if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
+  if (md->kind == 2) return -1; /* adjoints are defined for the closed-form media */
   *g_n0m1 = 0.0;
   if (tr->n == 0) return 0;
   double *gn = (double *)calloc((size_t)tr->n, sizeof(double));
@@ -591,6 +644,7 @@ int orc_endpoint_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_med
                      double *g_n0m1, int n_threads) {
   if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
   if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
+  if (md->kind == 2) return -1; /* adjoints are defined for the closed-form media */
   *g_n0m1 = 0.0;
   if (tr->n == 0) return 0;
   double *gn = (double *)calloc((size_t)tr->n, sizeof(double));

@@ -39,19 +39,28 @@ BETA_W_FIELDS = TRACK_FIELDS[8:]     # float64 (FP64 mode) or float32 (mixed mod
 # --------------------------------------------------------------------------- media
 @dataclass(frozen=True)
 class Medium:
-    """Refractive-index model n(z): ``uniform`` n = 1 + n0m1, or
-    ``exponential`` n = 1 + n0m1 * exp(-z / h)."""
+    """Refractive-index model n(z): ``uniform`` n = 1 + n0m1, ``exponential``
+    n = 1 + n0m1 * exp(-z / h), or ``tabulated`` n = 1 + n0m1 * f(z) with f
+    piecewise linear through ``table`` (values at z0 + i * dz, constant beyond
+    the first and last node)."""
     kind: str = "uniform"
     n0m1: float = N0_AIR
     h: float = H_AIR
+    table: Optional[tuple] = None
+    z0: float = 0.0
+    dz: float = 1.0
 
     def __post_init__(self):
-        if self.kind not in ("uniform", "exponential"):
+        if self.kind not in ("uniform", "exponential", "tabulated"):
             raise ValueError(f"unknown medium kind {self.kind!r}")
+        if self.kind == "tabulated":
+            if self.table is None or len(self.table) < 2 or not self.dz > 0:
+                raise ValueError("a tabulated medium needs >= 2 nodes and dz > 0")
+            object.__setattr__(self, "table", tuple(float(v) for v in self.table))
 
     @property
     def code(self) -> int:
-        return 0 if self.kind == "uniform" else 1
+        return {"uniform": 0, "exponential": 1, "tabulated": 2}[self.kind]
 
 
 def _mean_index(medium: Medium, z_lo: float, z_hi: float) -> float:
@@ -62,7 +71,11 @@ def _mean_index(medium: Medium, z_lo: float, z_hi: float) -> float:
     if medium.kind == "uniform" or z_hi == z_lo:
         return 1.0 + medium.n0m1
     z = np.linspace(z_lo, z_hi, 4097)
-    n = 1.0 + medium.n0m1 * np.exp(-z / medium.h)
+    if medium.kind == "tabulated":
+        nodes = medium.z0 + medium.dz * np.arange(len(medium.table))
+        n = 1.0 + medium.n0m1 * np.interp(z, nodes, np.asarray(medium.table))
+    else:
+        n = 1.0 + medium.n0m1 * np.exp(-z / medium.h)
     return float(np.trapezoid(n, z) / (z_hi - z_lo))
 
 
@@ -309,6 +322,16 @@ class Workload:
         n = self.n_tracks - start if n is None else n
         t = draw_tracks(self.seed, n, self.recipe, start)
         return t.to_mixed() if mixed else t
+
+
+def layered_air(dz: float = 50.0, top: float = 20_000.0) -> Medium:
+    """A tabulated atmosphere (a stand-in for a measured refractivity profile):
+    exponential with an 8 km scale height up to 10 km and a 6.3 km one above,
+    sampled every ``dz`` metres from 0 to ``top``."""
+    z = np.arange(0.0, top + 0.5 * dz, dz)
+    f = np.where(z < 10_000.0, np.exp(-z / 8_000.0),
+                 math.exp(-10_000.0 / 8_000.0) * np.exp(-(z - 10_000.0) / 6_300.0))
+    return Medium("tabulated", N0_AIR, H_AIR, tuple(f), 0.0, dz)
 
 
 UNIFORM_AIR = Medium("uniform", N0_AIR, H_AIR)

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 from scipy import integrate
 
-from paper_2309_03717_amd.workloads import (C_LIGHT, Medium, Tracks, config, draw_tracks,
+from paper_2309_03717_amd.workloads import (C_LIGHT, N0_AIR, Medium, Tracks, config, draw_tracks,
                                             RECIPE_WIDE, EXPONENTIAL_AIR, UNIFORM_AIR)
 from helpers import antennas, one_track, track_along, UNIFORM
 
@@ -499,3 +499,77 @@ def test_endpoint_vjp_inside_the_cherenkov_cone(orc):
             assert an == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(grads["p0"]).max()), key
             checked += 1
     assert checked >= 5
+
+
+# ----------------------------------------------------------------- tabulated medium
+_TAB = Medium("tabulated", 3.1e-4, 8000.0, (1.0, 0.83, 0.61, 0.64, 0.40, 0.21, 0.17), -200.0, 500.0)
+
+
+def _tab_f(md, z):
+    nodes = md.z0 + md.dz * np.arange(len(md.table))
+    return float(np.interp(z, nodes, np.asarray(md.table)))
+
+
+@pytest.mark.parametrize("zp,za", [(2_300.0, 0.0), (5_000.0, -900.0), (9_000.0, 2_500.0),
+                                   (130.0, 20.0), (-500.0, -350.0), (1_800.0004, 1_800.0),
+                                   (1_050.0, 1_300.0)])
+def test_tabulated_index_is_path_mean(orc, zp, za):
+    """Tabulated medium (piecewise-linear profile, constant beyond its nodes):
+    n_eff = (t - T) c / R equals the mean of n(z) along the path by adaptive
+    quadrature, across node boundaries, below the first and above the last
+    node, inside one cell and in the |dz| < 1 mm branch."""
+    md = _TAB
+    p = np.array([80.0, 35.0, zp])
+    x = np.array([-15.0, 10.0, za])
+    tr = one_track(p, p + [0, 0, -1.0], (0, 0, -0.99), t0=2e-6)
+    ar = antennas([x], 0.0, 1e-9, 10)
+    t, _, _ = orc.propagate(tr, ar, md)
+    r = float(np.linalg.norm(x - p))
+    neff = (t[0, 0, 0] - 2e-6) * C_LIGHT / r
+    if abs(zp - za) >= 1e-3:
+        nodes = list(md.z0 + md.dz * np.arange(len(md.table)))
+        lo, hi = min(za, zp), max(za, zp)
+        mean = integrate.quad(lambda z: md.n0m1 * _tab_f(md, z), lo, hi, points=nodes, limit=200,
+                              epsabs=0, epsrel=1e-13)[0] / (hi - lo)
+    else:
+        mean = md.n0m1 * _tab_f(md, 0.5 * (zp + za))
+    assert (neff - 1.0) == pytest.approx(mean, rel=1e-9)
+
+
+def test_tabulated_constant_profile_equals_uniform(orc):
+    """f = 1 everywhere: the tabulated propagator and fields equal the uniform
+    medium's up to rounding of the path integral."""
+    w = config(0)
+    tr = w.tracks(300)
+    flat = Medium("tabulated", w.medium.n0m1, 8000.0, (1.0, 1.0), 0.0, 1000.0)
+    t_u, _, b_u = orc.propagate(tr, w.array, w.medium)
+    t_t, _, b_t = orc.propagate(tr, w.array, flat)
+    assert np.allclose(t_t, t_u, rtol=4e-16, atol=0)
+    assert (b_t != b_u).mean() < 1e-3
+    for f in ("endpoint", "zhs"):
+        a = orc.traces(f, tr, w.array, w.medium)
+        b = orc.traces(f, tr, w.array, flat)
+        assert np.linalg.norm(b - a) <= 1e-6 * np.linalg.norm(a)
+
+
+def test_tabulated_exponential_samples_approach_closed_form(orc):
+    """A 10-m table of exp(-z/h): its path means agree with the exponential
+    closed form within the interpolation error (relative h^-2 dz^2 / 8)."""
+    z = np.arange(0.0, 20_000.0 + 5.0, 10.0)
+    md_t = Medium("tabulated", N0_AIR, 8000.0, tuple(np.exp(-z / 8000.0)), 0.0, 10.0)
+    w = config(1)
+    tr = w.tracks(200)
+    t_e, _, _ = orc.propagate(tr, w.array, w.medium)
+    t_t, _, _ = orc.propagate(tr, w.array, md_t)
+    T = np.stack([tr.t0, tr.t1])[:, :, None]
+    # (n_eff - 1) R / c differs by at most 1e-6 relative
+    assert np.all(np.abs((t_t - T) - (t_e - T)) <= 2e-6 * N0_AIR * (t_e - T) + 1e-18)
+
+
+def test_adjoints_reject_tabulated_media(orc):
+    w = config(3)
+    tr = w.tracks(4)
+    g = np.zeros((w.array.m, w.array.n_bins, 3))
+    for fn in (orc.zhs_vjp, orc.endpoint_vjp):
+        with pytest.raises(ValueError):
+            fn(tr, w.array, _TAB, g)
