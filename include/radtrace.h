@@ -72,15 +72,27 @@ typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
  * (§2, Listing 2; "media with varying properties", §1):
  *   RT_UNIFORM:     n(z) = 1 + n0_minus_1
  *   RT_EXPONENTIAL: n(z) = 1 + n0_minus_1 * exp(-z / scale_height)
+ *   RT_TABULATED:   n(z) = 1 + n0_minus_1 * f(z), f piecewise linear through
+ *                   table[i] at table_z0 + i * table_dz, constant beyond the
+ *                   first and last node (a measured or layered atmosphere)
  * The straight path from height zp to an antenna at height za sees the path
- * mean n_eff = 1 + n0_minus_1 * scale_height * (exp(-za/h) - exp(-zp/h)) /
- * (zp - za) (the local index at the midpoint height when |zp - za| < 1 mm). */
-typedef enum { RT_UNIFORM = 0, RT_EXPONENTIAL = 1 } rt_medium_kind;
+ * mean of n: n_eff = 1 + n0_minus_1 * scale_height * (exp(-za/h) -
+ * exp(-zp/h)) / (zp - za) for the exponential profile, 1 + n0_minus_1 *
+ * (F(zp) - F(za)) / (zp - za) for the tabulated one with F the exact integral
+ * of f (whole-cell trapezoids summed from the first node up, plus the part of
+ * the last cell); the local index at the midpoint height when |zp - za| <
+ * 1 mm. The adjoints and batches accept the uniform and exponential media. */
+typedef enum { RT_UNIFORM = 0, RT_EXPONENTIAL = 1, RT_TABULATED = 2 } rt_medium_kind;
 
 typedef struct {
   int32_t kind;          /* rt_medium_kind */
-  double n0_minus_1;     /* refractivity at z = 0, >= 0 */
+  double n0_minus_1;     /* refractivity scale, >= 0 (at z = 0 if exponential) */
   double scale_height;   /* metres, > 0 (exponential only) */
+  const double *table;   /* device, n_table finite values (tabulated only); the
+                            plan keeps the pointer: it must outlive the plan */
+  int32_t n_table;       /* 2 .. 1048576 (tabulated only) */
+  double table_z0;       /* height of table[0] (m) */
+  double table_dz;       /* node spacing (m), > 0 */
 } rt_medium;
 
 /* The antenna collection (§2, "detector" in Listing 2). Device arrays of

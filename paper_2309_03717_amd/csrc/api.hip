@@ -51,12 +51,19 @@ int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, 
     return fail(RT_E_INVALID, "formalism must be RT_ENDPOINT or RT_ZHS");
   if (precision != RT_FP64 && precision != RT_MIXED)
     return fail(RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
-  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL)
-    return fail(RT_E_INVALID, "medium kind must be RT_UNIFORM or RT_EXPONENTIAL");
+  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL && med->kind != RT_TABULATED)
+    return fail(RT_E_INVALID, "medium kind must be RT_UNIFORM, RT_EXPONENTIAL or RT_TABULATED");
   if (!(med->n0_minus_1 >= 0.0) || !is_finite(med->n0_minus_1))
     return fail(RT_E_INVALID, "n0_minus_1 must be finite and >= 0");
   if (med->kind == RT_EXPONENTIAL && (!(med->scale_height > 0.0) || !is_finite(med->scale_height)))
     return fail(RT_E_INVALID, "scale_height must be finite and > 0");
+  if (med->kind == RT_TABULATED) {
+    if (!med->table) return fail(RT_E_INVALID, "a tabulated medium needs its table");
+    if (med->n_table < 2 || med->n_table > (1 << 20))
+      return fail(RT_E_INVALID, "n_table must be in [2, 1048576]");
+    if (!(med->table_dz > 0.0) || !is_finite(med->table_dz) || !is_finite(med->table_z0))
+      return fail(RT_E_INVALID, "table_dz must be finite and > 0, table_z0 finite");
+  }
   if (!is_finite(k)) return fail(RT_E_INVALID, "k must be finite");
   return RT_OK;
 }
@@ -81,6 +88,20 @@ int rt_device_info(int *dev, int *num_cus, size_t *lds_block, size_t *lds_cu) {
 }
 
 int rt_fail(int status, const std::string &msg) { return fail(status, msg); }
+
+void rt_fill_table(const rt_medium &med, rt::Consts &c) {
+  c.tab = c.tabF = nullptr;
+  c.n_tab = 0;
+  c.tz0 = 0.0;
+  c.tdz = c.tinv_dz = 1.0;
+  if (med.kind == RT_TABULATED) {
+    c.tab = med.table;
+    c.n_tab = med.n_table;
+    c.tz0 = med.table_z0;
+    c.tdz = med.table_dz;
+    c.tinv_dz = 1.0 / med.table_dz;
+  }
+}
 int rt_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
 
 extern "C" {
@@ -137,6 +158,7 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
   c.nbins_d = (double)det->n_bins;
   c.n_bins = det->n_bins;
   c.medium = med->kind;
+  rt_fill_table(*med, c);
   *plan = p;
   return RT_OK;
 }
@@ -228,6 +250,8 @@ int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, 
                size_t workspace_bytes, void *stream) {
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ZHS) return fail(RT_E_INVALID, "rt_zhs_vjp needs an RT_ZHS plan");
+  if (plan->med.kind == RT_TABULATED)
+    return fail(RT_E_UNSUPPORTED, "the adjoints take the uniform and exponential media");
   return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
                   workspace_bytes, stream);
 }
@@ -238,6 +262,8 @@ int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ENDPOINT)
     return fail(RT_E_INVALID, "rt_endpoint_vjp needs an RT_ENDPOINT plan");
+  if (plan->med.kind == RT_TABULATED)
+    return fail(RT_E_UNSUPPORTED, "the adjoints take the uniform and exponential media");
   return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
                   workspace_bytes, stream);
 }

@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
     const int64_t i = g - s.rec_block0 * 64;
     const Consts c = s.c;
     const double z_ref = s.an.z[0];
-    const double e_ref = c.medium == 1 ? height_factor(z_ref, c) : 0.0;
+    const double e_ref = c.medium != 0 ? path_factor(z_ref, c) : 0.0;
     double v[kRec];
     if (s.formalism == RT_ENDPOINT)
       make_record<0, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
@@ -318,6 +318,7 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     c.nbins_d = (double)B;
     c.n_bins = B;
     c.medium = in.med.kind;
+    rt_fill_table(in.med, c);
     if (d.n_blocks > 0) max_slot = std::max(max_slot, d.slot_len);
     b.total_pairs += in.tracks.n * in.det.n_antennas;
   }
@@ -423,6 +424,8 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
     if (sh.tracks.n >= ((int64_t)1 << 31))
       return rt_fail(RT_E_UNSUPPORTED, where + "at most 2^31 - 1 tracks per shower");
     if (sh.tracks.n > 0 && !sh.traces) return rt_fail(RT_E_INVALID, where + "traces is NULL");
+    if (sh.med.kind == RT_TABULATED)
+      return rt_fail(RT_E_UNSUPPORTED, where + "batches take the uniform and exponential media");
     if (options && options->per_shower) {
       const rt_tiling &t = options->per_shower[s];
       if (t.antennas_per_block < 0 || t.antennas_per_block > 3 || t.track_splits < 0 ||

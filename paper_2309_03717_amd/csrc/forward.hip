@@ -46,7 +46,7 @@ struct PrepArgs {
 template <int F, int P>
 __global__ void __launch_bounds__(256) prepare_kernel(PrepArgs g) {
   const double z_ref = g.an.z[0];
-  const double e_ref = g.c.medium == 1 ? height_factor(z_ref, g.c) : 0.0;
+  const double e_ref = g.c.medium != 0 ? path_factor(z_ref, g.c) : 0.0;
   const int64_t n_pad = g.n_blocks * 64;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -71,7 +71,8 @@ struct DepositArgs {
   int accumulate;          // 0: first pass writes the partials; 1: later passes add
 };
 
-// F: 0 Endpoint, 1 ZHS.  P: 0 FP64, 1 mixed.  MED: 0 uniform, 1 exponential.
+// F: 0 Endpoint, 1 ZHS.  P: 0 FP64, 1 mixed.  MED: 0 uniform, 1 exponential,
+// 2 tabulated.
 // AT: antennas per tile.
 template <int F, int P, int MED, int AT>
 __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(TrackPtrs tr, AntPtrs an
       double pz = e ? tr.z1[i] : tr.z0[i];
       double tp = e ? tr.t1[i] : tr.t0[i];
       double neff = c.n_uniform;
-      if (c.medium == 1) neff = path_index(pz, az, height_factor(pz, c), height_factor(az, c), c);
+      if (c.medium != 0) neff = path_index(pz, az, path_factor(pz, c), path_factor(az, c), c);
       double t = arrival_time(px, py, pz, tp, ax, ay, az, neff, c);
       double u = (t - tau) * c.inv_dt;
       size_t o = ((size_t)e * tr.n + i) * an.m + a;
@@ -167,9 +168,25 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int64_t wave_blocks(int64_t n) { return (n + 63) / 64; }
 
-// Workspace: [records][partials]
+// Workspace: [records][partials][tabulated profile's cumulative integral]
 size_t prep_bytes(const rt_plan &, int64_t n) {
   return align256((size_t)wave_blocks(n) * kRec * 64 * sizeof(double));
+}
+
+static size_t table_bytes(const rt_plan &p) {
+  return p.med.kind == RT_TABULATED ? align256((size_t)p.med.n_table * sizeof(double)) : 0;
+}
+
+// F at the nodes of a tabulated profile: trapezoids summed from the first
+// node up, one thread (the order every lookup relies on).
+__global__ void tab_cells_kernel(const double *f, int n, double dz, double *cells) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  cells[0] = 0.0;
+  for (int j = 1; j < n; ++j) {
+    acc += (0.5 * dz) * (f[j - 1] + f[j]);
+    cells[j] = acc;
+  }
 }
 
 Tiling choose_tiling(const rt_plan &p, int64_t n) {
@@ -222,7 +239,8 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
 size_t workspace_bytes(const rt_plan &p, int64_t n) {
   Tiling t = choose_tiling(p, n);
   return prep_bytes(p, n) +
-         align256((size_t)t.splits * p.det.n_antennas * p.det.n_bins * 3 * acc_bytes(p.precision));
+         align256((size_t)t.splits * p.det.n_antennas * p.det.n_bins * 3 * acc_bytes(p.precision)) +
+         table_bytes(p);
 }
 
 TrackPtrs track_ptrs(const rt_tracks &t) {
@@ -248,13 +266,15 @@ static DepositFn pick_at(int at) {
   }
 }
 
+template <int F, int P>
+static DepositFn pick_med(int med, int at) {
+  if (med == 2) return pick_at<F, P, 2>(at);
+  return med ? pick_at<F, P, 1>(at) : pick_at<F, P, 0>(at);
+}
+
 static DepositFn pick_deposit(int f, int prec, int med, int at) {
-  if (f == RT_ENDPOINT) {
-    if (prec == RT_FP64) return med ? pick_at<0, 0, 1>(at) : pick_at<0, 0, 0>(at);
-    return med ? pick_at<0, 1, 1>(at) : pick_at<0, 1, 0>(at);
-  }
-  if (prec == RT_FP64) return med ? pick_at<1, 0, 1>(at) : pick_at<1, 0, 0>(at);
-  return med ? pick_at<1, 1, 1>(at) : pick_at<1, 1, 0>(at);
+  if (f == RT_ENDPOINT) return prec == RT_FP64 ? pick_med<0, 0>(med, at) : pick_med<0, 1>(med, at);
+  return prec == RT_FP64 ? pick_med<1, 0>(med, at) : pick_med<1, 1>(med, at);
 }
 
 static PrepFn pick_prep(int f, int prec) {
@@ -273,10 +293,16 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
                           hipStream_t stream) {
   const Tiling tl = choose_tiling(p, t.n);
   char *ws = reinterpret_cast<char *>(workspace);
+  Consts c = p.c;
+  if (p.med.kind == RT_TABULATED) {
+    double *cells = reinterpret_cast<double *>(ws + workspace_bytes(p, t.n) - table_bytes(p));
+    tab_cells_kernel<<<1, 64, 0, stream>>>(c.tab, c.n_tab, c.tdz, cells);
+    c.tabF = cells;
+  }
   PrepArgs pa;
   pa.tr = track_ptrs(t);
   pa.an = ant_ptrs(p.det);
-  pa.c = p.c;
+  pa.c = c;
   pa.rec = reinterpret_cast<double *>(ws);
   pa.n_blocks = wave_blocks(t.n);
   {
@@ -285,13 +311,13 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
   }
   DepositArgs g;
   g.an = pa.an;
-  g.c = p.c;
+  g.c = c;
   g.partial = ws + prep_bytes(p, t.n);
   g.blocks_per_split = tl.blocks_per_split;
   g.n_atiles = tl.n_atiles;
   g.n_segs = tl.n_segs;
   g.seg_len = tl.seg_len;
-  const int med = p.med.kind == RT_EXPONENTIAL ? 1 : 0;
+  const int med = p.med.kind;   // 0 uniform, 1 exponential, 2 tabulated
   DepositFn fn = pick_deposit(p.formalism, p.precision, med, tl.at);
   MergeFn mf = pick_merge(p.formalism, p.precision);
   if (tl.lds_bytes > 65536)

@@ -66,7 +66,9 @@ constexpr int record_loads() {
 
 // Builds the record of one track (fields as above). A track with any
 // non-finite field gets NaN times so that no antenna window accepts it.
-// z_ref, e_ref: height of antenna 0 and its height factor.
+// z_ref, e_ref: height of antenna 0 and its path factor. In non-uniform media
+// the "height factor" slots hold local_factor (n = 1 + n0m1 * it at the end
+// point): exp(-(z / h)) or, tabulated, f(z).
 template <int F, int P>
 __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool present,
                                             const Consts &c, double z_ref, double e_ref,
@@ -97,11 +99,13 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
   }
   v[R_E0] = v[R_E1] = 0.0;
   v[R_NE0] = v[R_NE1] = c.n_uniform;
-  if (c.medium == 1) {
-    v[R_E0] = height_factor(v[R_Z0], c);
-    v[R_E1] = height_factor(v[R_Z1], c);
-    v[R_NE0] = path_index(v[R_Z0], z_ref, v[R_E0], e_ref, c);
-    v[R_NE1] = path_index(v[R_Z1], z_ref, v[R_E1], e_ref, c);
+  if (c.medium != 0) {
+    v[R_E0] = local_factor(v[R_Z0], c);
+    v[R_E1] = local_factor(v[R_Z1], c);
+    const double p0 = c.medium == 2 ? tab_F(v[R_Z0], c) : v[R_E0];
+    const double p1 = c.medium == 2 ? tab_F(v[R_Z1], c) : v[R_E1];
+    v[R_NE0] = path_index(v[R_Z0], z_ref, p0, e_ref, c);
+    v[R_NE1] = path_index(v[R_Z1], z_ref, p1, e_ref, c);
   }
   if (P == 1) {
     const double amp = v[R_AMP], bx = v[R_BX], by = v[R_BY], bz = v[R_BZ];
@@ -225,14 +229,14 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
                                                double lo_d, double hi_d, const Consts &c) {
   const double x0 = v[R_X0], y0 = v[R_Y0], z0 = v[R_Z0], t0 = v[R_T0];
   const double x1 = v[R_X1], y1 = v[R_Y1], z1 = v[R_Z1], t1 = v[R_T1];
-  constexpr bool kOff = MED == 1 && H;   // off-reference antennas can be handled
+  constexpr bool kOff = MED != 0 && H;   // off-reference antennas can be handled
   double amp, bx, by, bz, e0 = 0.0, e1 = 0.0;
   if (P == 0) {
     amp = v[R_AMP];
     bx = v[R_BX];
     by = v[R_BY];
     bz = v[R_BZ];
-    if (MED == 1) {
+    if (MED != 0) {
       e0 = v[R_E0];
       e1 = v[R_E1];
     }
@@ -246,16 +250,18 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
       e1 = v[M_E1];
     }
   }
-  const double ns0 = MED == 1 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
-  const double ns1 = MED == 1 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
+  const double ns0 = MED != 0 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
+  const double ns1 = MED != 0 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
   if (F == 0) {
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
         double ne0 = v[R_NE0], ne1 = v[R_NE1];
         if (kOff && !t.at_ref[a]) {
-          ne0 = path_index(z0, t.az[a], e0, t.ea[a], c);
-          ne1 = path_index(z1, t.az[a], e1, t.ea[a], c);
+          const double p0 = MED == 2 ? tab_F(z0, c) : e0;
+          const double p1 = MED == 2 ? tab_F(z1, c) : e1;
+          ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
+          ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
         }
         acc_t *row = tile + a * row_len;
         double dx0, dy0, dz0, r0, q0, dx1, dy1, dz1, r1, q1;
@@ -274,8 +280,10 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
       if ((mask >> a) & 1) {
         double ne0 = v[R_NE0], ne1 = v[R_NE1];
         if (kOff && !t.at_ref[a]) {
-          ne0 = path_index(z0, t.az[a], e0, t.ea[a], c);
-          ne1 = path_index(z1, t.az[a], e1, t.ea[a], c);
+          const double p0 = MED == 2 ? tab_F(z0, c) : e0;
+          const double p1 = MED == 2 ? tab_F(z1, c) : e1;
+          ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
+          ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
         }
         double dx, dy, dz, rr, r2;
         double us = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c, dx,
@@ -333,7 +341,7 @@ __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_firs
   bool off = false;
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
-  if (P == 0 || (MED == 1 && (F == 0 || off)))
+  if (P == 0 || (MED != 0 && (F == 0 || off)))
     deposit_blocks_n<F, P, MED, AT, true>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
                                           hi, lo_d, hi_d, c);
   else
@@ -353,7 +361,7 @@ __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, in
     t.ay[a] = an.y[ai];
     t.az[a] = an.z[ai];
     t.tau[a] = an.t_start[ai];
-    t.ea[a] = MED == 1 ? height_factor(t.az[a], c) : 0.0;
+    t.ea[a] = MED != 0 ? path_factor_m<MED>(t.az[a], c) : 0.0;
     t.at_ref[a] = t.az[a] == z_ref;
   }
 }

@@ -10,6 +10,8 @@
 //     n_eff = 1 + (n0m1*h) * ((eX - eP) / (zP - zX))     (exponential,
 //             e = exp(-(z / h)), |zP - zX| >= 1e-3 m)
 //     n_eff = 1 + n0m1 * exp(-(((zP + zX) * 0.5) / h))   (|zP - zX| < 1e-3 m)
+//     n_eff = 1 + n0m1 * ((F(zP) - F(zX)) / (zP - zX))   (tabulated, F below;
+//             1 + n0m1 * f((zP + zX) * 0.5) when |zP - zX| < 1e-3 m)
 //     t = T + (n_eff * R) * (1 / c);   u = (t - t_start) * (1 / dt)
 //     in the window iff 0 <= u < n_bins; bin = floor(u)
 // The exponential form is the mean of n(z) = 1 + n0m1 exp(-z/h) along the
@@ -34,7 +36,12 @@ struct Consts {
   double n0m1, h, n0h;  // n0h = n0m1 * h
   double nbins_d;     // (double) n_bins
   int32_t n_bins;
-  int32_t medium;     // 0 uniform, 1 exponential
+  int32_t medium;     // 0 uniform, 1 exponential, 2 tabulated
+  // tabulated profile: f at tz0 + i tdz (i < n_tab), and its cumulative
+  // integral at the nodes (tabF, or null: summed on the fly)
+  const double *tab, *tabF;
+  int32_t n_tab;
+  double tz0, tdz, tinv_dz;   // tinv_dz = 1 / tdz
 };
 
 struct TrackPtrs {
@@ -53,12 +60,78 @@ __device__ __forceinline__ double height_factor(double z, const Consts &c) {
   return exp(-(z / c.h));
 }
 
-// Path-mean refractive index from emission height zp (height factor ep) to an
-// antenna at height za (height factor ea).
-__device__ __forceinline__ double path_index(double zp, double za, double ep, double ea,
+// Tabulated profile: f(z), linear between nodes, constant beyond the ends.
+__device__ __forceinline__ double tab_f(double z, const Consts &c) {
+  const double t = (z - c.tz0) * c.tinv_dz;
+  const int last = c.n_tab - 1;
+  if (!(t > 0.0)) return c.tab[0];
+  if (t >= (double)last) return c.tab[last];
+  const int i = (int)floor(t);
+  const double w = t - (double)i;
+  return c.tab[i] + w * (c.tab[i + 1] - c.tab[i]);
+}
+
+// Trapezoids of the first i cells, summed from the first node up.
+__device__ __forceinline__ double tab_cells(int i, const Consts &c) {
+  if (c.tabF) return c.tabF[i];
+  double acc = 0.0;
+  for (int j = 1; j <= i; ++j) acc += (0.5 * c.tdz) * (c.tab[j - 1] + c.tab[j]);
+  return acc;
+}
+
+// Tabulated profile: F(z) = integral of f from tz0 to z (exact for the
+// piecewise-linear f; slope f at the ends beyond the nodes).
+__device__ __forceinline__ double tab_F(double z, const Consts &c) {
+  const double t = (z - c.tz0) * c.tinv_dz;
+  const int last = c.n_tab - 1;
+  if (!(t > 0.0)) return c.tab[0] * (z - c.tz0);
+  const int i = t >= (double)last ? last : (int)floor(t);
+  const double acc = tab_cells(i, c);
+  if (i == last) return acc + c.tab[last] * (z - (c.tz0 + (double)last * c.tdz));
+  const double w = t - (double)i;
+  return acc + c.tdz * (w * c.tab[i] + (0.5 * w * w) * (c.tab[i + 1] - c.tab[i]));
+}
+
+// n(z) - 1 = n0m1 * local_factor(z) (non-uniform media).
+__device__ __forceinline__ double local_factor(double z, const Consts &c) {
+  return c.medium == 2 ? tab_f(z, c) : height_factor(z, c);
+}
+
+// The per-height value path_index takes: the height factor (exponential) or
+// the integral F (tabulated).
+__device__ __forceinline__ double path_factor(double z, const Consts &c) {
+  return c.medium == 2 ? tab_F(z, c) : height_factor(z, c);
+}
+
+// Compile-time forms for the deposit kernels (MED: 1 exponential, 2
+// tabulated), so that each kernel carries the code of its own medium only.
+template <int MED>
+__device__ __forceinline__ double path_factor_m(double z, const Consts &c) {
+  return MED == 2 ? tab_F(z, c) : height_factor(z, c);
+}
+
+template <int MED>
+__device__ __forceinline__ double path_index_m(double zp, double za, double pp, double pa,
+                                               const Consts &c) {
+  double dz = zp - za;
+  if (MED == 2) {
+    if (fabs(dz) >= 1e-3) return 1.0 + c.n0m1 * ((pp - pa) / dz);
+    return 1.0 + c.n0m1 * tab_f((zp + za) * 0.5, c);
+  }
+  if (fabs(dz) >= 1e-3) return 1.0 + c.n0h * ((pa - pp) / dz);
+  return 1.0 + c.n0m1 * exp(-(((zp + za) * 0.5) / c.h));
+}
+
+// Path-mean refractive index from emission height zp to an antenna at height
+// za, given their path factors pp and pa (non-uniform media).
+__device__ __forceinline__ double path_index(double zp, double za, double pp, double pa,
                                              const Consts &c) {
   double dz = zp - za;
-  if (fabs(dz) >= 1e-3) return 1.0 + c.n0h * ((ea - ep) / dz);
+  if (c.medium == 2) {
+    if (fabs(dz) >= 1e-3) return 1.0 + c.n0m1 * ((pp - pa) / dz);
+    return 1.0 + c.n0m1 * tab_f((zp + za) * 0.5, c);
+  }
+  if (fabs(dz) >= 1e-3) return 1.0 + c.n0h * ((pa - pp) / dz);
   return 1.0 + c.n0m1 * exp(-(((zp + za) * 0.5) / c.h));
 }
 

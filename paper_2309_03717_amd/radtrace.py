@@ -28,14 +28,17 @@ _lib = C.CDLL(LIB_PATH)
 RT_OK, RT_E_INVALID, RT_E_UNSUPPORTED, RT_E_NO_DEVICE, RT_E_HIP, RT_E_WORKSPACE = range(6)
 RT_ENDPOINT, RT_ZHS = 0, 1
 RT_FP64, RT_MIXED = 0, 1
-RT_UNIFORM, RT_EXPONENTIAL = 0, 1
+RT_UNIFORM, RT_EXPONENTIAL, RT_TABULATED = 0, 1, 2
+MEDIUM_KIND = {"uniform": RT_UNIFORM, "exponential": RT_EXPONENTIAL, "tabulated": RT_TABULATED}
 FORMALISM = {"endpoint": RT_ENDPOINT, "zhs": RT_ZHS}
 PRECISION = {"fp64": RT_FP64, "mixed": RT_MIXED}
 K_SI = 4.80320471518522e-18
 
 
 class rt_medium(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("n0_minus_1", C.c_double), ("scale_height", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("n0_minus_1", C.c_double), ("scale_height", C.c_double),
+                ("table", C.c_void_p), ("n_table", C.c_int32), ("table_z0", C.c_double),
+                ("table_dz", C.c_double)]
 
 
 class rt_detector(C.Structure):
@@ -204,10 +207,14 @@ def rt_last_error() -> str:
 
 
 def rt_plan_create(det: DeviceDetector, medium_kind: int, n0_minus_1: float, scale_height: float,
-                   formalism: int, precision: int, k: float) -> int:
+                   formalism: int, precision: int, k: float, table: Optional[torch.Tensor] = None,
+                   table_z0: float = 0.0, table_dz: float = 1.0) -> int:
+    """table: device float64 tensor of the tabulated profile (kept alive by
+    the caller for the plan's lifetime)."""
     handle = _P()
     d = det.struct()
-    m = rt_medium(medium_kind, n0_minus_1, scale_height)
+    m = rt_medium(medium_kind, n0_minus_1, scale_height, _ptr(table),
+                  0 if table is None else table.numel(), table_z0, table_dz)
     _check(_lib.rt_plan_create(C.byref(handle), C.byref(d), C.byref(m), formalism, precision,
                                float(k)), "rt_plan_create")
     return handle.value
@@ -345,9 +352,11 @@ class Plan:
         self.medium = medium
         self.formalism = FORMALISM[formalism]
         self.precision = PRECISION[precision]
-        kind = RT_UNIFORM if medium.kind == "uniform" else RT_EXPONENTIAL
-        self.handle = rt_plan_create(det, kind, float(medium.n0m1), float(medium.h),
-                                     self.formalism, self.precision, k)
+        self._table = _device_table(medium, det.x.device)
+        self.handle = rt_plan_create(det, MEDIUM_KIND[medium.kind], float(medium.n0m1),
+                                     float(medium.h), self.formalism, self.precision, k,
+                                     self._table, float(getattr(medium, "z0", 0.0)),
+                                     float(getattr(medium, "dz", 1.0)))
         self._ws = None
         self.dtype = torch.float64 if self.precision == RT_FP64 else torch.float32
 
@@ -425,9 +434,16 @@ class Plan:
         return t, b
 
 
-def _medium_struct(medium) -> rt_medium:
-    kind = RT_UNIFORM if medium.kind == "uniform" else RT_EXPONENTIAL
-    return rt_medium(kind, float(medium.n0m1), float(medium.h))
+def _device_table(medium, device) -> Optional[torch.Tensor]:
+    if medium.kind != "tabulated":
+        return None
+    return torch.tensor(medium.table, dtype=torch.float64, device=device)
+
+
+def _medium_struct(medium, table: Optional[torch.Tensor] = None) -> rt_medium:
+    return rt_medium(MEDIUM_KIND[medium.kind], float(medium.n0m1), float(medium.h), _ptr(table),
+                     0 if table is None else table.numel(), float(getattr(medium, "z0", 0.0)),
+                     float(getattr(medium, "dz", 1.0)))
 
 
 @dataclass
@@ -466,11 +482,15 @@ class Batch:
         self.options = options or BatchOptions()
         self.traces = []
         structs = []
+        self._tables = []
         for det, medium, formalism, tracks in self.inputs:
             tr = torch.zeros((det.m, det.n_bins, 3), dtype=self.dtype, device=det.x.device)
             self.traces.append(tr)
-            structs.append(rt_shower(det.struct(), _medium_struct(medium), FORMALISM[formalism],
-                                     tracks.struct(self.precision), _ptr(tr)))
+            table = _device_table(medium, det.x.device)
+            self._tables.append(table)
+            structs.append(rt_shower(det.struct(), _medium_struct(medium, table),
+                                     FORMALISM[formalism], tracks.struct(self.precision),
+                                     _ptr(tr)))
         opt, keep = self.options.struct()
         self.handle = rt_batch_create(structs, self.precision, k, opt)
         self.info = rt_batch_get_info(self.handle)

@@ -170,3 +170,22 @@ def test_null_batch_arguments(rt):
     assert rt._lib.rt_batch_workspace_bytes(None, C.byref(b)) == rt.RT_E_INVALID
     assert rt._lib.rt_batch_get_info(None, None, None, None, None) == rt.RT_E_INVALID
     assert rt._lib.rt_batch_set_timing_events(None, None, None) == rt.RT_E_INVALID
+
+
+@pytest.mark.parametrize("case", ["no_table", "one_node", "zero_dz", "nan_z0"])
+def test_plan_create_rejects_invalid_tables(rt, case):
+    det, keep = _detector(rt)
+    buf = (C.c_double * 4)(1.0, 0.9, 0.8, 0.7)
+    med = rt.rt_medium(rt.RT_TABULATED, 2.92e-4, 8000.0, C.addressof(buf), 4, 0.0, 100.0)
+    if case == "no_table":
+        med.table = None
+    elif case == "one_node":
+        med.n_table = 1
+    elif case == "zero_dz":
+        med.table_dz = 0.0
+    elif case == "nan_z0":
+        med.table_z0 = float("nan")
+    handle = C.c_void_p()
+    st = rt._lib.rt_plan_create(C.byref(handle), C.byref(det), C.byref(med), rt.RT_ENDPOINT,
+                                rt.RT_FP64, 1.0)
+    assert st == rt.RT_E_INVALID, rt.rt_last_error()

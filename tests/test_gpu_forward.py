@@ -250,3 +250,58 @@ def test_repeat_calls_agree(rt):
         a = gpu_traces(rt, formalism, "fp64", tr, w.array, w.medium)
         b = gpu_traces(rt, formalism, "fp64", tr, w.array, w.medium)
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-13 * np.abs(a).max())
+
+
+# ----------------------------------------------------------------- tabulated medium
+def tilted_star(medium):
+    """The 160-antenna star with antenna heights 0 .. 190 m (off the
+    reference height, so the per-pair path index is exercised)."""
+    x, y, _ = W.star_layout(8, 20, 25.0)
+    z = (np.arange(x.size) % 20) * 10.0
+    return W.make_array(x, y, z, medium, 0.1e-9, 4096)
+
+
+def test_tabulated_propagator_bit_exact(rt, orc):
+    import torch
+    md = W.layered_air()
+    arr = tilted_star(md)
+    tr = W.config(1).tracks(800)
+    det = rt.DeviceDetector.from_array(arr)
+    plan = rt.Plan(det, md, "endpoint", "fp64")
+    t, b = plan.propagate(rt.DeviceTracks.from_tracks(tr))
+    torch.cuda.synchronize()
+    t_ref, _, b_ref = orc.propagate(tr, arr, md)
+    assert np.array_equal(b.cpu().numpy(), b_ref)
+    assert np.array_equal(t.cpu().numpy(), t_ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_tabulated_medium_traces(rt, orc, formalism, precision):
+    """Layered (tabulated) atmosphere on the star with antennas at several
+    heights: traces against the oracle."""
+    md = W.layered_air()
+    arr = tilted_star(md)
+    tr = W.config(1).tracks(20_000)
+    got = gpu_traces(rt, formalism, precision, tr, arr, md)
+    ref = oracle_traces(orc, formalism, precision, tr, arr, md)
+    err = rel_l2(got, ref)
+    print(formalism, precision, "tabulated: max rel L2", err.max())
+    assert np.abs(ref).max() > 0
+    assert err.max() <= (FP64_BOUND if precision == "fp64" else MIXED_BOUND)
+
+
+def test_tabulated_medium_rejected_by_adjoint_and_batch(rt):
+    import torch
+    md = W.layered_air()
+    arr = tilted_star(md)
+    tr = W.config(1).tracks(100)
+    det = rt.DeviceDetector.from_array(arr)
+    plan = rt.Plan(det, md, "zhs", "fp64")
+    g = torch.zeros((arr.m, arr.n_bins, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(rt.RadtraceError) as e:
+        plan.vjp(rt.DeviceTracks.from_tracks(tr), g)
+    assert e.value.status == rt.RT_E_UNSUPPORTED
+    with pytest.raises(rt.RadtraceError) as e:
+        rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
+    assert e.value.status == rt.RT_E_UNSUPPORTED
