@@ -409,6 +409,9 @@ def main():
                          "copy: byte-counter calibration")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--showers", type=int, default=256, help="batched: number of showers")
+    ap.add_argument("--medium", default="exponential", choices=["exponential", "layered"],
+                    help="grid4096: the exponential profile (default) or the tabulated "
+                         "two-layer atmosphere")
     ap.add_argument("--tune-sample", type=int, default=1 << 16,
                     help="batched: tracks per shower the autotuner times candidates on")
     args = ap.parse_args()
@@ -451,7 +454,8 @@ def main():
     chunks = [rt.DeviceTracks(**{f: fields[f][c] for f in W.TRACK_FIELDS})
               for c in range(len(fields["x0"]))]
     det = rt.DeviceDetector.from_array(w.array)
-    plans = {f: rt.Plan(det, w.medium, f, "mixed", k=rt.K_SI) for f in formalisms}
+    medium = W.layered_air() if args.medium == "layered" else w.medium
+    plans = {f: rt.Plan(det, medium, f, "mixed", k=rt.K_SI) for f in formalisms}
     if args.tiling:
         for p in plans.values():
             p.set_tiling(*[int(x) for x in args.tiling.split(",")])
@@ -516,7 +520,8 @@ def main():
     dom = max(formalisms, key=lambda f: per[f]["kernel_ms_total_per_step"])
     achieved = per[dom]["achieved_tops"]
     peak = VALU_OPS_PEAK / 1e12
-    traffic = traffic_bytes(dom, plans[dom].tiling(chunk)) if n_total >= chunk else None
+    traffic = (traffic_bytes(dom, plans[dom].tiling(chunk))
+               if n_total >= chunk and args.medium == "exponential" else None)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": None if traffic is None else round(traffic),
@@ -530,9 +535,11 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64+f32", "data": "synthetic",
-           "config": {"workload": w.name if n_total == w.n_tracks else f"{w.name}[{n_total}]",
+           "config": {"workload": (w.name if n_total == w.n_tracks else f"{w.name}[{n_total}]")
+                      + ("" if args.medium == "exponential" else "+layered"),
                       "n_tracks": n_total, "n_antennas": w.array.m, "n_bins": w.array.n_bins,
-                      "dt_ns": w.array.dt * 1e9, "medium": w.medium.kind,
+                      "dt_ns": w.array.dt * 1e9,
+                      "medium": w.medium.kind if args.medium == "exponential" else "tabulated (layered)",
                       "precision": "mixed", "formalisms": formalisms, "chunk": chunk,
                       "tiling": {f: plans[f].tiling(chunk) for f in formalisms}},
            "per_formalism": {f: {"pairs_per_s": pairs_per_formalism / (per[f]["kernel_ms_total_per_step"] / 1e3),
