@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2309_03717_amd import workloads as W
-from helpers import antennas
+from helpers import antennas, one_track
 
 pytestmark = pytest.mark.gpu
 
@@ -305,3 +305,53 @@ def test_tabulated_medium_rejected_by_adjoint_and_batch(rt):
     with pytest.raises(rt.RadtraceError) as e:
         rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
     assert e.value.status == rt.RT_E_UNSUPPORTED
+
+
+# ----------------------------------------------------------------- degenerate cases
+def test_degenerate_tracks(rt, orc):
+    """Zero-length tracks (the two Endpoint impulses cancel, the ZHS box has
+    zero integral), beta = 0, qw = 0, an antenna exactly at a track end
+    (R = 0: that impulse is skipped) and an antenna exactly on the Cherenkov
+    cone (n beta = 1 along the line of sight: 1 - n beta.r = 0, skipped):
+    GPU equals the oracle, whose definitions settle each case."""
+    md = W.Medium("uniform", 1.0, 8000.0)           # n = 2
+    ant = np.array([[0.0, 0.0, 0.0], [30.0, 0.0, 0.0], [0.0, 0.0, -400.0]])
+    tracks = [
+        one_track((5.0, 1.0, 100.0), (5.0, 1.0, 100.0), (0.0, 0.0, -0.9), t0=1e-7, t1=1e-7),
+        one_track((1.0, 2.0, 300.0), (1.0, 2.0, 299.0), (0.0, 0.0, 0.0), t0=1e-7, t1=2e-7),
+        one_track((1.0, 2.0, 300.0), (1.0, 2.0, 299.0), (0.0, 0.0, -0.99), t0=1e-7, qw=0.0),
+        one_track((0.0, 0.0, 0.0), (0.0, 0.0, -2.0), (0.0, 0.0, -0.9), t0=1e-7),   # starts on antenna 0
+        one_track((0.0, 0.0, 0.0), (0.0, 0.0, -4.0), (0.0, 0.0, -0.5), t0=1e-7),   # cone for antenna 2
+        one_track((3.0, 4.0, 200.0), (3.0, 4.0, 190.0), (0.0, 0.0, -0.99), t0=5e-8),  # ordinary
+    ]
+    tr = W.Tracks.concat(tracks)
+    arr = antennas(ant, 0.0, 0.1e-9, 65536)
+    for formalism in ("endpoint", "zhs"):
+        ref = orc.traces(formalism, tr, arr, md)
+        got = gpu_traces(rt, formalism, "fp64", tr, arr, md)
+        assert np.isfinite(got).all()
+        assert np.abs(ref).max() > 0
+        assert rel_l2(got, ref).max() <= FP64_BOUND, formalism
+        for i in (0, 1, 2):   # zero-length, beta = 0, qw = 0 contribute nothing
+            one = orc.traces(formalism, tr.take([i]), arr, md)
+            assert not gpu_traces(rt, formalism, "fp64", tr.take([i]), arr, md).any() and not one.any()
+
+
+def test_large_array_and_long_traces(rt, orc):
+    """10,000 antennas (the paper's largest array) with 8192-bin traces (two
+    automatic LDS segments per trace): sampled antennas against the oracle,
+    both formalisms."""
+    x, y, z = W.grid_layout(100, 100, 40.0)
+    md = W.EXPONENTIAL_AIR
+    arr = W.make_array(x, y, z, md, 0.2e-9, 8192)
+    tr = W.config(1).tracks(3_000)
+    idx = np.array([0, 99, 4950, 5050, 9900, 9999, 1234, 7777])
+    sub = antennas(np.stack([x, y, z], 1)[idx], arr.t_start[idx], arr.dt, arr.n_bins)
+    for formalism in ("endpoint", "zhs"):
+        det = rt.DeviceDetector.from_array(arr)
+        plan = rt.Plan(det, md, formalism, "mixed")
+        assert plan.tiling(tr.n)[3] < arr.n_bins          # segmented
+        got = gpu_traces(rt, formalism, "mixed", tr, arr, md)[idx]
+        ref = oracle_traces(orc, formalism, "mixed", tr, sub, md)
+        assert np.abs(ref).max() > 0
+        assert rel_l2(got, ref).max() <= MIXED_BOUND, formalism
