@@ -208,7 +208,10 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
   t.at = at;
   t.n_atiles = (int)((M + at - 1) / at);
   t.lds_bytes = (size_t)at * seg * 3 * acc;
-  t.block = p.block_user > 0 ? p.block_user : 512;
+  // 1024 threads: with one workgroup per CU (the trace tile fills most of
+  // the LDS) this keeps four waves per SIMD to hide the LDS atomics and the
+  // record loads; the deposit kernels are built for at most 128 VGPRs
+  t.block = p.block_user > 0 ? p.block_user : 1024;
   t.pass_tracks = p.pass_user > 0 ? p.pass_user : kDefaultPass;
   const int64_t n_tiles = (int64_t)t.n_atiles * t.n_segs;
   const int64_t nb = std::max<int64_t>(1, wave_blocks(std::min(n, t.pass_tracks)));
