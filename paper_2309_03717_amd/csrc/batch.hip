@@ -97,8 +97,8 @@ __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int
   load_tile<AT, MED>(an, a_begin, n_ant, c, t);
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
-  deposit_blocks<F, P, MED, AT>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo, hi,
-                                (double)lo, (double)hi, c);
+  deposit_blocks<F, P, MED, AT, true>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo, hi,
+                                      (double)lo, (double)hi, c);
 }
 
 template <int F, int P, int MED>

@@ -102,8 +102,8 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int64_t waves = blockDim.x >> 6;
   const int64_t b_first = (int64_t)split * g.blocks_per_split + (threadIdx.x >> 6);
   const int64_t b_end = min(g.n_blocks, (int64_t)(split + 1) * g.blocks_per_split);
-  deposit_blocks<F, P, MED, AT>(g.rec, b_first, b_end, waves, mask, t, tile, row_len, lo, hi, lo_d,
-                                hi_d, g.c);
+  deposit_blocks<F, P, MED, AT, F == 0>(g.rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
+                                        hi, lo_d, hi_d, g.c);
   __syncthreads();
 
   acc_t *dst = reinterpret_cast<acc_t *>(g.partial);

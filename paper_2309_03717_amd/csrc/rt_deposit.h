@@ -298,10 +298,13 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 }
 
 // Deposits of the wave blocks [b_first, b_end) (stride `waves`, one block per
-// wave per step) of a record array into the LDS tile, with the next record
-// loaded before the current one is processed. Only the slots the formalism
-// and precision use are read.
-template <int F, int P, int MED, int AT, bool H>
+// wave per step) of a record array into the LDS tile. Only the slots the
+// formalism and precision use are read. PF: load the next record before
+// processing the current one. That pays where record delivery bounds the loop
+// (the Endpoint deposit) or few waves share a SIMD (the 512-thread batch
+// kernel); the single-plan ZHS deposit, with more arithmetic per record and
+// four waves per SIMD, runs faster without the register copies it costs.
+template <int F, int P, int MED, int AT, bool H, bool PF>
 __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_first,
                                                  int64_t b_end, int64_t waves, uint64_t mask,
                                                  const Tile<AT> &t, acc_t *tile, int row_len,
@@ -309,6 +312,16 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
                                                  const Consts &c) {
   constexpr int kLoad = record_loads<P, H>();
   const int lane = threadIdx.x & 63;
+  if (!PF) {
+    for (int64_t blk = b_first; blk < b_end; blk += waves) {
+      double rv[kRec];
+      const double *r = rec + blk * (kRec * 64) + lane;
+#pragma unroll
+      for (int f = 0; f < kRec; ++f) rv[f] = f < kLoad ? r[f * 64] : 0.0;
+      deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
+    }
+    return;
+  }
   double nx[kRec];
 #pragma unroll
   for (int f = kLoad; f < kRec; ++f) nx[f] = 0.0;
@@ -333,7 +346,7 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
 // As deposit_blocks_n, reading the height factors of mixed records only where
 // they are used: the exponential Endpoint (source index) and tiles with an
 // antenna off the reference height.
-template <int F, int P, int MED, int AT>
+template <int F, int P, int MED, int AT, bool PF>
 __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
                                                int64_t waves, uint64_t mask, const Tile<AT> &t,
                                                acc_t *tile, int row_len, int lo, int hi,
@@ -342,11 +355,11 @@ __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_firs
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
   if (P == 0 || (MED != 0 && (F == 0 || off)))
-    deposit_blocks_n<F, P, MED, AT, true>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
-                                          hi, lo_d, hi_d, c);
+    deposit_blocks_n<F, P, MED, AT, true, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
+                                              lo, hi, lo_d, hi_d, c);
   else
-    deposit_blocks_n<F, P, MED, AT, false>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
-                                           hi, lo_d, hi_d, c);
+    deposit_blocks_n<F, P, MED, AT, false, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
+                                               lo, hi, lo_d, hi_d, c);
 }
 
 // Loads the tile antennas [a_begin, a_begin + n_ant) (uniform per workgroup).

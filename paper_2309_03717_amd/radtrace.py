@@ -362,7 +362,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and _lib is not None:   # module globals are cleared at interpreter exit
             _lib.rt_plan_destroy(h)
             self.handle = None
 
@@ -500,7 +500,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and _lib is not None:   # module globals are cleared at interpreter exit
             _lib.rt_batch_destroy(h)
             self.handle = None
 
