@@ -12,8 +12,9 @@ persistent, graph-replayed launch per step (launch shape from the autotuner).
 
 Prints one JSON line on stdout (progress goes to stderr). The roofline entry
 is for the dominant deposit kernel, timed with HIP events recorded on its own
-stream around every launch; the CPU baseline is the FP64 oracle on a bounded
-sample of the same workload on this host's cores.
+stream around every launch; the fp64 entry times the same deposits in FP64
+mode on the first chunks (mixed vs FP64); the CPU baseline is the FP64 oracle
+on a bounded sample of the same workload on this host's cores.
 """
 import argparse
 import json
@@ -412,6 +413,8 @@ def main():
     ap.add_argument("--medium", default="exponential", choices=["exponential", "layered"],
                     help="grid4096: the exponential profile (default) or the tabulated "
                          "two-layer atmosphere")
+    ap.add_argument("--fp64-chunks", type=int, default=2,
+                    help="grid4096: chunks of the workload also timed in FP64 mode (0: none)")
     ap.add_argument("--tune-sample", type=int, default=1 << 16,
                     help="batched: tracks per shower the autotuner times candidates on")
     args = ap.parse_args()
@@ -546,9 +549,49 @@ def main():
                                  **{k: (round(v, 4) if isinstance(v, float) else v)
                                     for k, v in per[f].items()}} for f in formalisms},
            "roofline": roofline}
+    if args.fp64_chunks > 0:
+        out["fp64"] = fp64_leg(rt, det, medium, chunks[:args.fp64_chunks], formalisms,
+                               w.array.m, {f: out["per_formalism"][f]["pairs_per_s"]
+                                           for f in formalisms})
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n_total))
     print(json.dumps(out), flush=True)
+
+
+def fp64_leg(rt, det, medium, chunks, formalisms, m, mixed_rate):
+    """The same deposits in FP64 mode (every operation in double, double
+    traces) on the first chunks of the workload, with the float32-rounded beta
+    and qw of the mixed inputs widened: kernel pairs/s per formalism (HIP events
+    around the deposits, one warm-up call first) and the mixed/FP64 ratio."""
+    import torch
+    from paper_2309_03717_amd import workloads as W
+    wide = [rt.DeviceTracks(**{f: (getattr(c, f).double() if f in W.BETA_W_FIELDS
+                                   else getattr(c, f)) for f in W.TRACK_FIELDS})
+            for c in chunks]
+    res = {"tracks": sum(c.n for c in wide), "note": "first chunks of the workload, "
+           "kernel time of the deposits, same inputs as the mixed run widened to double"}
+    for f in formalisms:
+        plan = rt.Plan(det, medium, f, "fp64", k=rt.K_SI)
+        tr = plan.new_traces()
+        plan.accumulate(wide[0], tr)
+        torch.cuda.synchronize()
+        ev = []
+        for c in wide:
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            rt.rt_plan_set_timing_events(plan.handle, s, e)
+            plan.accumulate(c, tr)
+            ev.append((s, e))
+        torch.cuda.synchronize()
+        ms = sum(s.elapsed_time(e) for s, e in ev)
+        rate = res["tracks"] * m / (ms / 1e3)
+        res[f] = {"pairs_per_s": rate, "kernel_ms": round(ms, 3),
+                  "mixed_over_fp64": round(mixed_rate[f] / rate, 3),
+                  "tiling": plan.tiling(wide[0].n)}
+        log(f"fp64 {f}: {rate / 1e9:.1f} G pairs/s ({ms:.1f} ms for {res['tracks']} tracks)")
+        del plan, tr
+    del wide
+    torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

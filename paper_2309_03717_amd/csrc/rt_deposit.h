@@ -171,20 +171,22 @@ __device__ __forceinline__ void endpoint_amp(acc_t *row, int lo, double lo_d, do
 }
 
 // ZHS box of one segment at one antenna. us, ue: arrival of start and end in
-// bins. The box [u_lo, u_hi] of time integral I = k qw beta_perp (t1-t0) /
+// bins; (dx0, dy0, dz0), (dx1, dy1, dz1): antenna minus start and end point.
+// The box [u_lo, u_hi] of time integral I = k qw beta_perp (t1-t0) /
 // R_mid has bin averages Ibar * overlap / (u_hi - u_lo), Ibar = I / dt; it is
 // deposited as at most four differences whose prefix sum is that average,
 // each bounded by |Ibar|.
 template <int P>
 __device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double lo_d, double hi_d,
-                                        double us, double ue, double mx, double my, double mz,
-                                        double ax, double ay, double az, double cz, double bx,
+                                        double us, double ue, double dx0, double dy0, double dz0,
+                                        double dx1, double dy1, double dz1, double cz, double bx,
                                         double by, double bz) {
   double ulo = us < ue ? us : ue;
   double uhi = us < ue ? ue : us;
   if (!(uhi >= lo_d && ulo < hi_d)) return;   // outside this segment (or NaN)
-  // midpoint geometry: Ibar = cz * beta_perp / R_m, cz = k qw (t1 - t0) / dt
-  double dx = ax - mx, dy = ay - my, dz = az - mz;
+  // midpoint geometry: Ibar = cz * beta_perp / R_m, cz = k qw (t1 - t0) / dt;
+  // X - M is the mean of the end offsets X - P0, X - P1 the timing computed
+  double dx = (dx0 + dx1) * 0.5, dy = (dy0 + dy1) * 0.5, dz = (dz0 + dz1) * 0.5;
   double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
   if (r2 == 0.0) return;
   double rinv = P == 0 ? 1.0 / sqrt(r2) : fast_rsq(r2);
@@ -274,7 +276,6 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
       }
     }
   } else {
-    const double mx = (x0 + x1) * 0.5, my = (y0 + y1) * 0.5, mz = (z0 + z1) * 0.5;
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
@@ -285,13 +286,13 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
           ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
           ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
         }
-        double dx, dy, dz, rr, r2;
-        double us = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c, dx,
-                                 dy, dz, rr, r2);
-        double ue = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c, dx,
-                                 dy, dz, rr, r2);
-        zhs_box<P>(tile + a * row_len, lo, hi, lo_d, hi_d, us, ue, mx, my, mz, t.ax[a], t.ay[a],
-                   t.az[a], amp, bx, by, bz);
+        double dx0, dy0, dz0, dx1, dy1, dz1, rr, r2;
+        double us = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c, dx0,
+                                 dy0, dz0, rr, r2);
+        double ue = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c, dx1,
+                                 dy1, dz1, rr, r2);
+        zhs_box<P>(tile + a * row_len, lo, hi, lo_d, hi_d, us, ue, dx0, dy0, dz0, dx1, dy1, dz1,
+                   amp, bx, by, bz);
       }
     }
   }
