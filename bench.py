@@ -46,6 +46,11 @@ OPS = {
     # height 4, deposit values 14)
     "zhs": {"timing": 28, "box_fp64": 16, "box_fp32": 45},
 }
+# Spherical Earth: the path mean of n per track end by 8-point quadrature, 19
+# FP64 operations per node (the node point 6, rho^2 5, the radius sum and its
+# sqrt 2, the height quotient 2, the exponent quotient 1, exp 1, the weighted
+# sum 2) and 2 to scale the sum: 154 per end on top of the timing chain.
+SPHERICAL_TIMING_PER_END = 8 * 19 + 2
 # MI355X VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12
 # lane-operations/s for FP64 and for unpacked FP32 (packed FP32 is disabled in
 # this build); the published 78.6 TFLOP/s counts an FMA as two operations.
@@ -108,18 +113,19 @@ def traffic_bytes(formalism, tiling):
     return 1024.0 * (k["fetch"] * TRAFFIC_SCALE["fetch"] + k["write"] * TRAFFIC_SCALE["write"])
 
 
-def ops_per_pair(formalism, ends_in, box_in):
+def ops_per_pair(formalism, ends_in, box_in, medium="exponential"):
     o = OPS[formalism]
+    extra = 2 * SPHERICAL_TIMING_PER_END if medium == "spherical" else 0
     if formalism == "endpoint":
-        f64 = 2 * (o["timing_per_end"] + ends_in * o["amp_per_end_fp64"])
+        f64 = 2 * (o["timing_per_end"] + ends_in * o["amp_per_end_fp64"]) + extra
         f32 = 2 * ends_in * o["amp_per_end_fp32"]
     else:
-        f64 = o["timing"] + box_in * o["box_fp64"]
+        f64 = o["timing"] + box_in * o["box_fp64"] + extra
         f32 = box_in * o["box_fp32"]
     return f64, f32
 
 
-def cpu_baseline(workload, n_sample):
+def cpu_baseline(workload, n_sample, medium=None):
     import oracle
     oracle._load()
     try:
@@ -131,7 +137,7 @@ def cpu_baseline(workload, n_sample):
     secs = {}
     for f in ("endpoint", "zhs"):
         t0 = time.perf_counter()
-        oracle.traces(f, tr, workload.array, workload.medium, k=1.0, n_threads=cores)
+        oracle.traces(f, tr, workload.array, medium or workload.medium, k=1.0, n_threads=cores)
         secs[f] = time.perf_counter() - t0
         log(f"cpu baseline {f}: {secs[f]:.2f} s on {cores} threads")
     pairs = tr.n * workload.array.m
@@ -410,9 +416,11 @@ def main():
                          "copy: byte-counter calibration")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--showers", type=int, default=256, help="batched: number of showers")
-    ap.add_argument("--medium", default="exponential", choices=["exponential", "layered"],
-                    help="grid4096: the exponential profile (default) or the tabulated "
-                         "two-layer atmosphere")
+    ap.add_argument("--medium", default="exponential",
+                    choices=["exponential", "layered", "spherical"],
+                    help="grid4096: the exponential profile (default), the tabulated "
+                         "two-layer atmosphere, or the exponential profile over a spherical "
+                         "Earth (path mean by quadrature per pair)")
     ap.add_argument("--fp64-chunks", type=int, default=2,
                     help="grid4096: chunks of the workload also timed in FP64 mode (0: none)")
     ap.add_argument("--tune-sample", type=int, default=1 << 16,
@@ -457,7 +465,8 @@ def main():
     chunks = [rt.DeviceTracks(**{f: fields[f][c] for f in W.TRACK_FIELDS})
               for c in range(len(fields["x0"]))]
     det = rt.DeviceDetector.from_array(w.array)
-    medium = W.layered_air() if args.medium == "layered" else w.medium
+    medium = {"exponential": w.medium, "layered": W.layered_air(),
+              "spherical": W.SPHERICAL_AIR}[args.medium]
     plans = {f: rt.Plan(det, medium, f, "mixed", k=rt.K_SI) for f in formalisms}
     if args.tiling:
         for p in plans.values():
@@ -511,7 +520,7 @@ def main():
         durs = [s.elapsed_time(e) / passes for s, e in kernel_events[f]]
         n_launch = len(durs)
         avg_ms = sum(durs) / n_launch
-        f64, f32 = ops_per_pair(f, ends_in, box_in)
+        f64, f32 = ops_per_pair(f, ends_in, box_in, args.medium)
         pairs_per_launch = pairs_per_formalism * args.steps / (n_launch * passes)
         achieved = (f64 + f32) * pairs_per_launch / (avg_ms / 1e3)
         per[f] = {"kernel_ms_avg": avg_ms, "launches": n_launch * passes,
@@ -529,7 +538,7 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "kernel": f"deposit_kernel<{dom},mixed,exponential>",
+                "kernel": f"deposit_kernel<{dom},mixed,{medium.kind}>",
                 "kernel_ms_avg": round(per[dom]["kernel_ms_avg"], 3),
                 "ops_per_pair": per[dom]["ops_per_pair"],
                 "in_window": {"endpoint_ends": round(ends_in, 4), "zhs_boxes": round(box_in, 4)}}
@@ -539,10 +548,11 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f64+f32", "data": "synthetic",
            "config": {"workload": (w.name if n_total == w.n_tracks else f"{w.name}[{n_total}]")
-                      + ("" if args.medium == "exponential" else "+layered"),
+                      + ("" if args.medium == "exponential" else "+" + args.medium),
                       "n_tracks": n_total, "n_antennas": w.array.m, "n_bins": w.array.n_bins,
                       "dt_ns": w.array.dt * 1e9,
-                      "medium": w.medium.kind if args.medium == "exponential" else "tabulated (layered)",
+                      "medium": {"exponential": "exponential", "layered": "tabulated (layered)",
+                                 "spherical": "exponential over a spherical Earth"}[args.medium],
                       "precision": "mixed", "formalisms": formalisms, "chunk": chunk,
                       "tiling": {f: plans[f].tiling(chunk) for f in formalisms}},
            "per_formalism": {f: {"pairs_per_s": pairs_per_formalism / (per[f]["kernel_ms_total_per_step"] / 1e3),
@@ -554,7 +564,7 @@ def main():
                                w.array.m, {f: out["per_formalism"][f]["pairs_per_s"]
                                            for f in formalisms})
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n_total))
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n_total), medium)
     print(json.dumps(out), flush=True)
 
 

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define RT_ABI_VERSION 1
+#define RT_ABI_VERSION 2
 
 typedef enum {
   RT_OK = 0,
@@ -75,24 +75,44 @@ typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
  *   RT_TABULATED:   n(z) = 1 + n0_minus_1 * f(z), f piecewise linear through
  *                   table[i] at table_z0 + i * table_dz, constant beyond the
  *                   first and last node (a measured or layered atmosphere)
+ *   RT_SPHERICAL:   n(p) = 1 + n0_minus_1 * exp(-h(p) / scale_height) with h
+ *                   the height above a spherical Earth of radius earth_radius
+ *                   centred at (0, 0, -earth_radius): z = 0 is the ground at
+ *                   the origin of the array frame, and the ground falls away
+ *                   with horizontal distance (a curved-Earth atmosphere)
  * The straight path from height zp to an antenna at height za sees the path
  * mean of n: n_eff = 1 + n0_minus_1 * scale_height * (exp(-za/h) -
  * exp(-zp/h)) / (zp - za) for the exponential profile, 1 + n0_minus_1 *
  * (F(zp) - F(za)) / (zp - za) for the tabulated one with F the exact integral
  * of f (whole-cell trapezoids summed from the first node up, plus the part of
  * the last cell); the local index at the midpoint height when |zp - za| <
- * 1 mm. The adjoints and batches accept the uniform and exponential media. */
-typedef enum { RT_UNIFORM = 0, RT_EXPONENTIAL = 1, RT_TABULATED = 2 } rt_medium_kind;
+ * 1 mm. Over the spherical Earth the path mean has no closed form: it is
+ * taken by 8-point Gauss-Legendre quadrature along the straight path from the
+ * emission point P to the antenna X,
+ *   n_eff = 1 + n0_minus_1 * sum_k w_k exp(-h(P + s_k (X - P)) / scale_height)
+ * with the nodes s_k and weights w_k of the rule on [0, 1] (ascending s_k,
+ * sum w_k = 1; accurate to double rounding for these profiles), and h(q) =
+ * rho2 / (sqrt(rho2 + R^2) + R), rho2 = (qx^2 + qy^2) + qz (qz + 2R), which is
+ * |q - C| - R without cancellation. The adjoints and batches accept the
+ * uniform and exponential media. */
+typedef enum {
+  RT_UNIFORM = 0,
+  RT_EXPONENTIAL = 1,
+  RT_TABULATED = 2,
+  RT_SPHERICAL = 3
+} rt_medium_kind;
 
 typedef struct {
   int32_t kind;          /* rt_medium_kind */
-  double n0_minus_1;     /* refractivity scale, >= 0 (at z = 0 if exponential) */
-  double scale_height;   /* metres, > 0 (exponential only) */
+  double n0_minus_1;     /* refractivity scale, >= 0 (at z = 0 if exponential
+                            or spherical) */
+  double scale_height;   /* metres, > 0 (exponential and spherical only) */
   const double *table;   /* device, n_table finite values (tabulated only); the
                             plan keeps the pointer: it must outlive the plan */
   int32_t n_table;       /* 2 .. 1048576 (tabulated only) */
   double table_z0;       /* height of table[0] (m) */
   double table_dz;       /* node spacing (m), > 0 */
+  double earth_radius;   /* metres, finite and >= 1000 (spherical only) */
 } rt_medium;
 
 /* The antenna collection (§2, "detector" in Listing 2). Device arrays of

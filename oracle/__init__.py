@@ -47,10 +47,11 @@ class _Antennas(C.Structure):
 class _Medium(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n0m1", C.c_double), ("h", C.c_double),
                 ("f", C.POINTER(C.c_double)), ("n_f", C.c_int32), ("z0", C.c_double),
-                ("dz", C.c_double)]
+                ("dz", C.c_double), ("re", C.c_double)]
 
 
 _lib = None
+ORC_VERSION = 2   # the structure layouts above
 
 
 def _load():
@@ -68,6 +69,9 @@ def _load():
                                     C.c_double, dp, dp, dp, dp, dp, C.c_int]
         lib.orc_endpoint_vjp.argtypes = lib.orc_zhs_vjp.argtypes
         lib.orc_version.restype = C.c_int
+        lib.orc_gl_rule.argtypes = [dp, dp]
+        if lib.orc_version() != ORC_VERSION:
+            raise ImportError(f"{_LIB} is stale (version {lib.orc_version()}); rebuild the oracle")
         _lib = lib
     return _lib
 
@@ -95,9 +99,10 @@ class _Args:
             f = _f64(np.asarray(medium.table, dtype=np.float64))
             self.keep.append(f)
             self.md = _Medium(medium.code, float(medium.n0m1), float(medium.h), _dp(f), f.size,
-                              float(medium.z0), float(medium.dz))
+                              float(medium.z0), float(medium.dz), 0.0)
         else:
-            self.md = _Medium(medium.code, float(medium.n0m1), float(medium.h), None, 0, 0.0, 1.0)
+            self.md = _Medium(medium.code, float(medium.n0m1), float(medium.h), None, 0, 0.0, 1.0,
+                              float(getattr(medium, "earth_radius", 0.0)))
 
 
 _Tracks._fields_names = staticmethod(lambda: [f for f, _ in _Tracks._fields_[1:]])
@@ -120,6 +125,15 @@ def traces(formalism: str, tracks, array, medium, k: float = 1.0, n_threads: int
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return out
+
+
+def gl_rule():
+    """Nodes (ascending, on [0, 1]) and weights of the quadrature rule the
+    spherical-Earth path mean uses."""
+    lib = _load()
+    s, w = np.zeros(16), np.zeros(16)
+    n = lib.orc_gl_rule(_dp(s), _dp(w))
+    return s[:n].copy(), w[:n].copy()
 
 
 def propagate(tracks, array, medium):

@@ -47,7 +47,11 @@
  * 1 + n0m1 f(z) with f piecewise linear through equally spaced nodes, whose
  * path mean is the exact integral of f over the path divided by its height
  * difference, evaluated in a fixed operation order (tab_F) that is part of
- * the timing chain.
+ * the timing chain. Spherical Earth: n = 1 + n0m1 exp(-H/h) with H the height
+ * above a sphere of radius re touching z = 0 at the origin; its path mean has
+ * no closed form and is the 8-point Gauss-Legendre quadrature along the
+ * straight path, in the fixed order of spherical_index (also part of the
+ * timing chain).
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared -pthread -lm
  */
@@ -57,7 +61,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_VERSION 1
+#define ORC_VERSION 2
 #define ORC_C_LIGHT 299792458.0 /* m/s, exact by definition of the metre */
 
 typedef struct {
@@ -86,6 +90,8 @@ typedef struct {
   const double *f;
   int32_t n_f;
   double z0, dz;
+  double re;     /* 3, spherical Earth: n = 1 + n0m1 exp(-H/h), H the height above the
+                    sphere of radius re (m) centred at (0, 0, -re) */
 } orc_medium;
 
 int orc_version(void) { return ORC_VERSION; }
@@ -119,6 +125,88 @@ static double tab_F(const orc_medium *md, double z) {
   if (i == last) return acc + f[last] * (z - (md->z0 + (double)last * dz));
   double w = t - (double)i;
   return acc + dz * (w * f[i] + (0.5 * w * w) * (f[i + 1] - f[i]));
+}
+
+/* Spherical Earth, centre C = (0, 0, -re). For a point q, rho2 = |q - C|^2 -
+ * re^2 = (x^2 + y^2) + z (z + 2 re), and the height above the sphere is
+ * |q - C| - re = rho2 / (|q - C| + re): the same number without subtracting
+ * two radii. Returned: that height over the scale height h, with one
+ * division. */
+static double sphere_exponent(const orc_medium *md, double rho2) {
+  return rho2 / ((sqrt(rho2 + md->re * md->re) + md->re) * md->h);
+}
+
+static double sphere_rho2(const orc_medium *md, double x, double y, double z) {
+  return (x * x + y * y) + z * (z + (md->re + md->re));
+}
+
+/* The 8-point Gauss-Legendre rule moved from [-1, 1] to [0, 1]: nodes s_k =
+ * (1 + x_k) / 2 in ascending order and weights w_k = 1 / ((1 - x_k^2)
+ * P8'(x_k)^2) (half the classical ones, so that they sum to 1), x_k the roots
+ * of the Legendre polynomial P8. Each root is found on its own by Newton's
+ * method in long double, from the estimate -cos(pi (k + 3/4) / (8 + 1/2)),
+ * with P8 and P7 from Bonnet's recurrence (j+1) P_{j+1} = (2j+1) x P_j -
+ * j P_{j-1} and P8' = 8 (P7 - x P8) / (1 - x^2). */
+#define ORC_GL 8
+static double gl_node[ORC_GL], gl_weight[ORC_GL];
+static pthread_once_t gl_once = PTHREAD_ONCE_INIT;
+
+static void legendre8(long double x, long double *p8, long double *p7) {
+  long double prev = 1.0L, cur = x;
+  for (int j = 1; j < ORC_GL; ++j) {
+    long double next = ((2 * j + 1) * x * cur - j * prev) / (j + 1);
+    prev = cur;
+    cur = next;
+  }
+  *p8 = cur;
+  *p7 = prev;
+}
+
+static void gl_init(void) {
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int k = 0; k < ORC_GL; ++k) {
+    long double x = -cosl(pi * (k + 0.75L) / (ORC_GL + 0.5L)), p8, p7, d;
+    for (int it = 0; it < 100; ++it) {
+      legendre8(x, &p8, &p7);
+      d = ORC_GL * (p7 - x * p8) / (1.0L - x * x);
+      long double step = p8 / d;
+      x -= step;
+      if (fabsl(step) < 1e-20L) break;
+    }
+    legendre8(x, &p8, &p7);
+    d = ORC_GL * (p7 - x * p8) / (1.0L - x * x);
+    gl_node[k] = (double)((1.0L + x) * 0.5L);
+    gl_weight[k] = (double)(1.0L / ((1.0L - x * x) * d * d));
+  }
+}
+
+/* The rule itself (for its pins): nodes and weights, ORC_GL of each. */
+int orc_gl_rule(double *s, double *w) {
+  pthread_once(&gl_once, gl_init);
+  for (int k = 0; k < ORC_GL; ++k) {
+    s[k] = gl_node[k];
+    w[k] = gl_weight[k];
+  }
+  return ORC_GL;
+}
+
+/* Path mean of n from the emission point P to the antenna X over the
+ * spherical Earth: 1 + n0m1 sum_k w_k exp(-H(q_k) / h) at the nodes q_k = P +
+ * s_k (X - P), the terms added in ascending s_k. Along the line rho2 is a
+ * quadratic in s: rho2(P + s d) = rho2(P) + s (2 (P - C).d + s d.d). */
+static double spherical_index(const orc_medium *md, double px, double py, double pz, double ax,
+                              double ay, double az) {
+  pthread_once(&gl_once, gl_init);
+  double dx = ax - px, dy = ay - py, dz = az - pz;
+  double c0 = sphere_rho2(md, px, py, pz);
+  double c1 = 2.0 * ((px * dx + py * dy) + (pz + md->re) * dz);
+  double c2 = (dx * dx + dy * dy) + dz * dz;
+  double sum = 0.0;
+  for (int k = 0; k < ORC_GL; ++k) {
+    double s = gl_node[k];
+    sum = sum + gl_weight[k] * exp(-sphere_exponent(md, c0 + s * (c1 + s * c2)));
+  }
+  return 1.0 + md->n0m1 * sum;
 }
 
 /* Local refractive index n(z) at the emission point (§2: the propagator is
@@ -167,16 +255,21 @@ static path propagate(const orc_antennas *ar, const orc_medium *md, int64_t a,
   p.dy = ar->y[a] - py;
   p.dz = ar->z[a] - pz;
   p.r = sqrt((p.dx * p.dx + p.dy * p.dy) + p.dz * p.dz);
-  double neff = effective_index(md, pz, ar->z[a]);
+  double neff = md->kind == 3 ? spherical_index(md, px, py, pz, ar->x[a], ar->y[a], ar->z[a])
+                              : effective_index(md, pz, ar->z[a]);
   p.t = tp + (neff * p.r) * inv_c;
   p.u = (p.t - ar->t_start[a]) * inv_dt;
   return p;
 }
 
-/* A tabulated medium needs at least two nodes and a positive spacing. */
+/* A tabulated medium needs at least two nodes and a positive spacing; the
+ * exponential profiles a positive scale height; the sphere a radius of at
+ * least 1 km. */
 static int medium_ok(const orc_medium *md) {
-  if (md->kind != 2) return md->kind == 0 || md->kind == 1;
-  return md->f && md->n_f >= 2 && md->dz > 0.0;
+  if (md->kind == 2) return md->f && md->n_f >= 2 && md->dz > 0.0;
+  if (md->kind == 3) return md->h > 0.0 && md->re >= 1000.0 && isfinite(md->re);
+  if (md->kind == 1) return md->h > 0.0;
+  return md->kind == 0;
 }
 
 /* Bin of u, or -1 outside [0, n_bins) (NaN is outside). */
@@ -212,7 +305,10 @@ static void endpoint_pair(const orc_tracks *tr, int64_t i, const orc_antennas *a
     double rx = p.dx / p.r, ry = p.dy / p.r, rz = p.dz / p.r;
     double bx = tr->bx[i], by = tr->by[i], bz = tr->bz[i];
     double bdotr = (bx * rx + by * ry) + bz * rz;
-    double doppler = 1.0 - index_at(md, pz) * bdotr; /* signed */
+    double n_src = md->kind == 3
+                       ? 1.0 + md->n0m1 * exp(-sphere_exponent(md, sphere_rho2(md, px, py, pz)))
+                       : index_at(md, pz);
+    double doppler = 1.0 - n_src * bdotr; /* signed */
     if (doppler == 0.0) continue;
     /* r x (r x beta) = r (beta.r) - beta */
     double vx = rx * bdotr - bx, vy = ry * bdotr - by, vz = rz * bdotr - bz;
@@ -521,7 +617,7 @@ int orc_zhs_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_medium *
                 int n_threads) {
   if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
   if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
-  if (md->kind == 2) return -1; /* adjoints are defined for the closed-form media */
+  if (md->kind >= 2) return -1; /* adjoints are defined for the closed-form media */
   *g_n0m1 = 0.0;
   if (tr->n == 0) return 0;
   double *gn = (double *)calloc((size_t)tr->n, sizeof(double));
@@ -644,7 +740,7 @@ int orc_endpoint_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_med
                      double *g_n0m1, int n_threads) {
   if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
   if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
-  if (md->kind == 2) return -1; /* adjoints are defined for the closed-form media */
+  if (md->kind >= 2) return -1; /* adjoints are defined for the closed-form media */
   *g_n0m1 = 0.0;
   if (tr->n == 0) return 0;
   double *gn = (double *)calloc((size_t)tr->n, sizeof(double));

@@ -51,12 +51,17 @@ int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, 
     return fail(RT_E_INVALID, "formalism must be RT_ENDPOINT or RT_ZHS");
   if (precision != RT_FP64 && precision != RT_MIXED)
     return fail(RT_E_INVALID, "precision must be RT_FP64 or RT_MIXED");
-  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL && med->kind != RT_TABULATED)
-    return fail(RT_E_INVALID, "medium kind must be RT_UNIFORM, RT_EXPONENTIAL or RT_TABULATED");
+  if (med->kind != RT_UNIFORM && med->kind != RT_EXPONENTIAL && med->kind != RT_TABULATED &&
+      med->kind != RT_SPHERICAL)
+    return fail(RT_E_INVALID,
+                "medium kind must be RT_UNIFORM, RT_EXPONENTIAL, RT_TABULATED or RT_SPHERICAL");
   if (!(med->n0_minus_1 >= 0.0) || !is_finite(med->n0_minus_1))
     return fail(RT_E_INVALID, "n0_minus_1 must be finite and >= 0");
-  if (med->kind == RT_EXPONENTIAL && (!(med->scale_height > 0.0) || !is_finite(med->scale_height)))
+  if ((med->kind == RT_EXPONENTIAL || med->kind == RT_SPHERICAL) &&
+      (!(med->scale_height > 0.0) || !is_finite(med->scale_height)))
     return fail(RT_E_INVALID, "scale_height must be finite and > 0");
+  if (med->kind == RT_SPHERICAL && (!(med->earth_radius >= 1000.0) || !is_finite(med->earth_radius)))
+    return fail(RT_E_INVALID, "earth_radius must be finite and >= 1000 m");
   if (med->kind == RT_TABULATED) {
     if (!med->table) return fail(RT_E_INVALID, "a tabulated medium needs its table");
     if (med->n_table < 2 || med->n_table > (1 << 20))
@@ -102,6 +107,53 @@ void rt_fill_table(const rt_medium &med, rt::Consts &c) {
     c.tinv_dz = 1.0 / med.table_dz;
   }
 }
+// Nodes (ascending) and weights of the n-point Gauss-Legendre rule moved to
+// [0, 1], n even: the roots of the Legendre polynomial P_n by Newton's method
+// in long double from the estimate cos(pi (i - 1/4) / (n + 1/2)), P_n and
+// P_n' from the three-term recurrence, weights 2 / ((1 - x^2) P_n'(x)^2);
+// the rule is symmetric, so each root x > 0 gives s = (1 -+ x) / 2.
+static void gauss_legendre01(int n, double *s, double *w) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 1; i <= n / 2; ++i) {
+    long double x = cosl(pi * ((long double)i - 0.25L) / ((long double)n + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 64; ++it) {
+      long double p0 = 1.0L, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0L);
+      const long double step = p1 / dp;
+      x -= step;
+      if (fabsl(step) <= 1e-19L) break;
+    }
+    long double p0 = 1.0L, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0L);
+    const long double wt = 1.0L / ((1.0L - x * x) * dp * dp);   // half of 2 / (...)
+    s[i - 1] = (double)((1.0L - x) * 0.5L);
+    s[n - i] = (double)((1.0L + x) * 0.5L);
+    w[i - 1] = w[n - i] = (double)wt;
+  }
+}
+
+void rt_fill_sphere(const rt_medium &med, rt::Consts &c) {
+  c.re = c.re2 = c.re_twice = 0.0;
+  for (int k = 0; k < rt::kGl; ++k) c.gl_s[k] = c.gl_w[k] = 0.0;
+  if (med.kind == RT_SPHERICAL) {
+    c.re = med.earth_radius;
+    c.re2 = c.re * c.re;
+    c.re_twice = c.re + c.re;
+    gauss_legendre01(rt::kGl, c.gl_s, c.gl_w);
+  }
+}
+
 int rt_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
 
 extern "C" {
@@ -153,12 +205,13 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
   c.k = k;
   c.n_uniform = 1.0 + med->n0_minus_1;
   c.n0m1 = med->n0_minus_1;
-  c.h = med->kind == RT_EXPONENTIAL ? med->scale_height : 1.0;
+  c.h = med->kind == RT_EXPONENTIAL || med->kind == RT_SPHERICAL ? med->scale_height : 1.0;
   c.n0h = c.n0m1 * c.h;
   c.nbins_d = (double)det->n_bins;
   c.n_bins = det->n_bins;
   c.medium = med->kind;
   rt_fill_table(*med, c);
+  rt_fill_sphere(*med, c);
   *plan = p;
   return RT_OK;
 }
@@ -250,7 +303,7 @@ int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, 
                size_t workspace_bytes, void *stream) {
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ZHS) return fail(RT_E_INVALID, "rt_zhs_vjp needs an RT_ZHS plan");
-  if (plan->med.kind == RT_TABULATED)
+  if (plan->med.kind == RT_TABULATED || plan->med.kind == RT_SPHERICAL)
     return fail(RT_E_UNSUPPORTED, "the adjoints take the uniform and exponential media");
   return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
                   workspace_bytes, stream);
@@ -262,7 +315,7 @@ int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ENDPOINT)
     return fail(RT_E_INVALID, "rt_endpoint_vjp needs an RT_ENDPOINT plan");
-  if (plan->med.kind == RT_TABULATED)
+  if (plan->med.kind == RT_TABULATED || plan->med.kind == RT_SPHERICAL)
     return fail(RT_E_UNSUPPORTED, "the adjoints take the uniform and exponential media");
   return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
                   workspace_bytes, stream);

@@ -319,6 +319,7 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     c.n_bins = B;
     c.medium = in.med.kind;
     rt_fill_table(in.med, c);
+    rt_fill_sphere(in.med, c);
     if (d.n_blocks > 0) max_slot = std::max(max_slot, d.slot_len);
     b.total_pairs += in.tracks.n * in.det.n_antennas;
   }
@@ -424,7 +425,7 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
     if (sh.tracks.n >= ((int64_t)1 << 31))
       return rt_fail(RT_E_UNSUPPORTED, where + "at most 2^31 - 1 tracks per shower");
     if (sh.tracks.n > 0 && !sh.traces) return rt_fail(RT_E_INVALID, where + "traces is NULL");
-    if (sh.med.kind == RT_TABULATED)
+    if (sh.med.kind == RT_TABULATED || sh.med.kind == RT_SPHERICAL)
       return rt_fail(RT_E_UNSUPPORTED, where + "batches take the uniform and exponential media");
     if (options && options->per_shower) {
       const rt_tiling &t = options->per_shower[s];

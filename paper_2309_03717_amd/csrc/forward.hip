@@ -46,7 +46,7 @@ struct PrepArgs {
 template <int F, int P>
 __global__ void __launch_bounds__(256) prepare_kernel(PrepArgs g) {
   const double z_ref = g.an.z[0];
-  const double e_ref = g.c.medium != 0 ? path_factor(z_ref, g.c) : 0.0;
+  const double e_ref = g.c.medium == 1 || g.c.medium == 2 ? path_factor(z_ref, g.c) : 0.0;
   const int64_t n_pad = g.n_blocks * 64;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -102,8 +102,10 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int64_t waves = blockDim.x >> 6;
   const int64_t b_first = (int64_t)split * g.blocks_per_split + (threadIdx.x >> 6);
   const int64_t b_end = min(g.n_blocks, (int64_t)(split + 1) * g.blocks_per_split);
-  deposit_blocks<F, P, MED, AT, F == 0>(g.rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
-                                        hi, lo_d, hi_d, g.c);
+  // record prefetch where delivery bounds the loop: the Endpoint deposit,
+  // except over the spherical Earth, whose per-pair quadrature dominates
+  deposit_blocks<F, P, MED, AT, F == 0 && MED != 3>(g.rec, b_first, b_end, waves, mask, t, tile,
+                                                    row_len, lo, hi, lo_d, hi_d, g.c);
   __syncthreads();
 
   acc_t *dst = reinterpret_cast<acc_t *>(g.partial);
@@ -150,7 +152,10 @@ __global__ void __launch_bounds__(256) propagate_kernel(TrackPtrs tr, AntPtrs an
       double pz = e ? tr.z1[i] : tr.z0[i];
       double tp = e ? tr.t1[i] : tr.t0[i];
       double neff = c.n_uniform;
-      if (c.medium != 0) neff = path_index(pz, az, path_factor(pz, c), path_factor(az, c), c);
+      if (c.medium == 3)
+        neff = sph_path_index(px, py, pz, ax, ay, az, c);
+      else if (c.medium != 0)
+        neff = path_index(pz, az, path_factor(pz, c), path_factor(az, c), c);
       double t = arrival_time(px, py, pz, tp, ax, ay, az, neff, c);
       double u = (t - tau) * c.inv_dt;
       size_t o = ((size_t)e * tr.n + i) * an.m + a;
@@ -271,6 +276,7 @@ static DepositFn pick_at(int at) {
 
 template <int F, int P>
 static DepositFn pick_med(int med, int at) {
+  if (med == 3) return pick_at<F, P, 3>(at);
   if (med == 2) return pick_at<F, P, 2>(at);
   return med ? pick_at<F, P, 1>(at) : pick_at<F, P, 0>(at);
 }
@@ -320,7 +326,7 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
   g.n_atiles = tl.n_atiles;
   g.n_segs = tl.n_segs;
   g.seg_len = tl.seg_len;
-  const int med = p.med.kind;   // 0 uniform, 1 exponential, 2 tabulated
+  const int med = p.med.kind;   // 0 uniform, 1 exponential, 2 tabulated, 3 spherical
   DepositFn fn = pick_deposit(p.formalism, p.precision, med, tl.at);
   MergeFn mf = pick_merge(p.formalism, p.precision);
   if (tl.lds_bytes > 65536)

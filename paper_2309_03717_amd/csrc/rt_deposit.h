@@ -68,7 +68,8 @@ constexpr int record_loads() {
 // non-finite field gets NaN times so that no antenna window accepts it.
 // z_ref, e_ref: height of antenna 0 and its path factor. In non-uniform media
 // the "height factor" slots hold local_factor (n = 1 + n0m1 * it at the end
-// point): exp(-(z / h)) or, tabulated, f(z).
+// point): exp(-(z / h)), tabulated f(z), or over the spherical Earth
+// exp(-(H(P) / h)).
 template <int F, int P>
 __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool present,
                                             const Consts &c, double z_ref, double e_ref,
@@ -99,7 +100,12 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
   }
   v[R_E0] = v[R_E1] = 0.0;
   v[R_NE0] = v[R_NE1] = c.n_uniform;
-  if (c.medium != 0) {
+  if (c.medium == 3) {
+    // spherical Earth: the path index depends on the whole antenna position
+    // and is taken per pair by the deposit
+    v[R_E0] = sph_factor(v[R_X0], v[R_Y0], v[R_Z0], c);
+    v[R_E1] = sph_factor(v[R_X1], v[R_Y1], v[R_Z1], c);
+  } else if (c.medium != 0) {
     v[R_E0] = local_factor(v[R_Z0], c);
     v[R_E1] = local_factor(v[R_Z1], c);
     const double p0 = c.medium == 2 ? tab_F(v[R_Z0], c) : v[R_E0];
@@ -259,7 +265,10 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
         double ne0 = v[R_NE0], ne1 = v[R_NE1];
-        if (kOff && !t.at_ref[a]) {
+        if (MED == 3) {
+          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
+          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
+        } else if (kOff && !t.at_ref[a]) {
           const double p0 = MED == 2 ? tab_F(z0, c) : e0;
           const double p1 = MED == 2 ? tab_F(z1, c) : e1;
           ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
@@ -280,7 +289,10 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
         double ne0 = v[R_NE0], ne1 = v[R_NE1];
-        if (kOff && !t.at_ref[a]) {
+        if (MED == 3) {
+          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
+          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
+        } else if (kOff && !t.at_ref[a]) {
           const double p0 = MED == 2 ? tab_F(z0, c) : e0;
           const double p1 = MED == 2 ? tab_F(z1, c) : e1;
           ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
@@ -355,7 +367,7 @@ __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_firs
   bool off = false;
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
-  if (P == 0 || (MED != 0 && (F == 0 || off)))
+  if (P == 0 || (MED == 3 ? F == 0 : MED != 0 && (F == 0 || off)))
     deposit_blocks_n<F, P, MED, AT, true, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
                                               lo, hi, lo_d, hi_d, c);
   else
@@ -375,7 +387,7 @@ __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, in
     t.ay[a] = an.y[ai];
     t.az[a] = an.z[ai];
     t.tau[a] = an.t_start[ai];
-    t.ea[a] = MED != 0 ? path_factor_m<MED>(t.az[a], c) : 0.0;
+    t.ea[a] = MED == 1 || MED == 2 ? path_factor_m<MED>(t.az[a], c) : 0.0;
     t.at_ref[a] = t.az[a] == z_ref;
   }
 }

@@ -12,10 +12,17 @@
 //     n_eff = 1 + n0m1 * exp(-(((zP + zX) * 0.5) / h))   (|zP - zX| < 1e-3 m)
 //     n_eff = 1 + n0m1 * ((F(zP) - F(zX)) / (zP - zX))   (tabulated, F below;
 //             1 + n0m1 * f((zP + zX) * 0.5) when |zP - zX| < 1e-3 m)
+//     n_eff = 1 + n0m1 * S                               (spherical Earth,
+//             S = S + w_k * exp(-(r_k / ((sqrt(r_k + re*re) + re) * h)))
+//             summed over the nodes k ascending, r_k = A + s_k * (B + s_k * D),
+//             A = (px*px + py*py) + pz * (pz + 2 re),
+//             B = 2 * ((px*dx + py*dy) + (pz + re) * dz),
+//             D = (dx*dx + dy*dy) + dz*dz)
 //     t = T + (n_eff * R) * (1 / c);   u = (t - t_start) * (1 / dt)
 //     in the window iff 0 <= u < n_bins; bin = floor(u)
 // The exponential form is the mean of n(z) = 1 + n0m1 exp(-z/h) along the
-// straight path (§2: the propagator gives the emission path of each pair).
+// straight path (§2: the propagator gives the emission path of each pair);
+// over a spherical Earth the same mean is taken by Gauss-Legendre quadrature.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +34,7 @@ constexpr int kMaxTile = 8;     // antennas per workgroup tile (template bound)
 constexpr int64_t kDefaultPass = 1 << 20;   // tracks per deposit pass by default
 constexpr int kXcds = 8;        // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int64_t kZhsSplitBlocks = 2048;   // ZHS track split cap: 128K tracks
+constexpr int kGl = 8;          // Gauss-Legendre nodes of the spherical path mean
 
 struct Consts {
   double inv_c;       // 1 / c
@@ -36,12 +44,16 @@ struct Consts {
   double n0m1, h, n0h;  // n0h = n0m1 * h
   double nbins_d;     // (double) n_bins
   int32_t n_bins;
-  int32_t medium;     // 0 uniform, 1 exponential, 2 tabulated
+  int32_t medium;     // 0 uniform, 1 exponential, 2 tabulated, 3 spherical
   // tabulated profile: f at tz0 + i tdz (i < n_tab), and its cumulative
   // integral at the nodes (tabF, or null: summed on the fly)
   const double *tab, *tabF;
   int32_t n_tab;
   double tz0, tdz, tinv_dz;   // tinv_dz = 1 / tdz
+  // spherical Earth: radius, its square and twice it; quadrature nodes on
+  // [0, 1] (ascending) and weights
+  double re, re2, re_twice;
+  double gl_s[kGl], gl_w[kGl];
 };
 
 struct TrackPtrs {
@@ -151,6 +163,38 @@ __device__ __forceinline__ double sqrt_rn(double x) {
   g = fma(d, h, g);
   if (__builtin_expect(!(x > 0x1p-767 && x < __builtin_inf()), 0)) g = sqrt(x);
   return g;
+}
+
+// Spherical Earth of radius re centred at (0, 0, -re). For a point q, rho2 =
+// |q - C|^2 - re^2 = (x*x + y*y) + z * (z + 2 re), and its height above the
+// sphere is H = |q - C| - re = rho2 / (sqrt(rho2 + re^2) + re) (no
+// cancellation of two radii); sph_exponent is H / h with one division.
+__device__ __forceinline__ double sph_exponent(double rho2, const Consts &c) {
+  return rho2 / ((sqrt_rn(rho2 + c.re2) + c.re) * c.h);
+}
+
+// exp(-(H(q) / h)): n(q) = 1 + n0m1 * sph_factor(q).
+__device__ __forceinline__ double sph_factor(double x, double y, double z, const Consts &c) {
+  return exp(-sph_exponent((x * x + y * y) + z * (z + c.re_twice), c));
+}
+
+// Path mean of n over the straight path from P to the antenna X (spherical
+// Earth): 1 + n0m1 * (sum over the nodes of w_k * exp(-(H(q_k) / h))), the
+// nodes taken in ascending order. Along q = P + s d (d = X - P), rho2 is the
+// quadratic A + s (B + s D) with A = rho2(P), B = 2 (P - C).d, D = d.d.
+__device__ __forceinline__ double sph_path_index(double px, double py, double pz, double ax,
+                                                 double ay, double az, const Consts &c) {
+  const double dx = ax - px, dy = ay - py, dz = az - pz;
+  const double qa = (px * px + py * py) + pz * (pz + c.re_twice);
+  const double qb = 2.0 * ((px * dx + py * dy) + (pz + c.re) * dz);
+  const double qd = (dx * dx + dy * dy) + dz * dz;
+  double s = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < kGl; ++k) {
+    const double sk = c.gl_s[k];
+    s = s + c.gl_w[k] * exp(-sph_exponent(qa + sk * (qb + sk * qd), c));
+  }
+  return 1.0 + c.n0m1 * s;
 }
 
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an

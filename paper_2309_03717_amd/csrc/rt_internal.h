@@ -77,5 +77,9 @@ int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, 
 int rt_check_tracks(const rt_tracks *t, int64_t n_antennas);
 // Tabulated-profile fields of the constants from a medium (zero otherwise).
 void rt_fill_table(const rt_medium &med, rt::Consts &c);
+
+// Spherical-Earth fields of the constants (radius, quadrature rule; zero
+// otherwise).
+void rt_fill_sphere(const rt_medium &med, rt::Consts &c);
 // Current device, its compute units and LDS bytes per workgroup and per CU.
 int rt_device_info(int *dev, int *num_cus, size_t *lds_block, size_t *lds_cu);

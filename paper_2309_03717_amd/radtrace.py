@@ -28,8 +28,9 @@ _lib = C.CDLL(LIB_PATH)
 RT_OK, RT_E_INVALID, RT_E_UNSUPPORTED, RT_E_NO_DEVICE, RT_E_HIP, RT_E_WORKSPACE = range(6)
 RT_ENDPOINT, RT_ZHS = 0, 1
 RT_FP64, RT_MIXED = 0, 1
-RT_UNIFORM, RT_EXPONENTIAL, RT_TABULATED = 0, 1, 2
-MEDIUM_KIND = {"uniform": RT_UNIFORM, "exponential": RT_EXPONENTIAL, "tabulated": RT_TABULATED}
+RT_UNIFORM, RT_EXPONENTIAL, RT_TABULATED, RT_SPHERICAL = 0, 1, 2, 3
+MEDIUM_KIND = {"uniform": RT_UNIFORM, "exponential": RT_EXPONENTIAL, "tabulated": RT_TABULATED,
+               "spherical": RT_SPHERICAL}
 FORMALISM = {"endpoint": RT_ENDPOINT, "zhs": RT_ZHS}
 PRECISION = {"fp64": RT_FP64, "mixed": RT_MIXED}
 K_SI = 4.80320471518522e-18
@@ -38,7 +39,7 @@ K_SI = 4.80320471518522e-18
 class rt_medium(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n0_minus_1", C.c_double), ("scale_height", C.c_double),
                 ("table", C.c_void_p), ("n_table", C.c_int32), ("table_z0", C.c_double),
-                ("table_dz", C.c_double)]
+                ("table_dz", C.c_double), ("earth_radius", C.c_double)]
 
 
 class rt_detector(C.Structure):
@@ -77,6 +78,10 @@ class rt_batch_options(C.Structure):
 
 _P = C.c_void_p
 _lib.rt_abi_version.restype = C.c_int
+ABI_VERSION = 2   # the structure layouts below
+if _lib.rt_abi_version() != ABI_VERSION:
+    raise ImportError(f"{LIB_PATH} has ABI version {_lib.rt_abi_version()}, the binding expects "
+                      f"{ABI_VERSION}: rebuild the library")
 _lib.rt_status_string.restype = C.c_char_p
 _lib.rt_status_string.argtypes = [C.c_int]
 _lib.rt_last_error.restype = C.c_char_p
@@ -208,13 +213,13 @@ def rt_last_error() -> str:
 
 def rt_plan_create(det: DeviceDetector, medium_kind: int, n0_minus_1: float, scale_height: float,
                    formalism: int, precision: int, k: float, table: Optional[torch.Tensor] = None,
-                   table_z0: float = 0.0, table_dz: float = 1.0) -> int:
+                   table_z0: float = 0.0, table_dz: float = 1.0, earth_radius: float = 0.0) -> int:
     """table: device float64 tensor of the tabulated profile (kept alive by
-    the caller for the plan's lifetime)."""
+    the caller for the plan's lifetime); earth_radius: spherical medium only."""
     handle = _P()
     d = det.struct()
     m = rt_medium(medium_kind, n0_minus_1, scale_height, _ptr(table),
-                  0 if table is None else table.numel(), table_z0, table_dz)
+                  0 if table is None else table.numel(), table_z0, table_dz, earth_radius)
     _check(_lib.rt_plan_create(C.byref(handle), C.byref(d), C.byref(m), formalism, precision,
                                float(k)), "rt_plan_create")
     return handle.value
@@ -356,7 +361,8 @@ class Plan:
         self.handle = rt_plan_create(det, MEDIUM_KIND[medium.kind], float(medium.n0m1),
                                      float(medium.h), self.formalism, self.precision, k,
                                      self._table, float(getattr(medium, "z0", 0.0)),
-                                     float(getattr(medium, "dz", 1.0)))
+                                     float(getattr(medium, "dz", 1.0)),
+                                     float(getattr(medium, "earth_radius", 0.0)))
         self._ws = None
         self.dtype = torch.float64 if self.precision == RT_FP64 else torch.float32
 
@@ -443,7 +449,7 @@ def _device_table(medium, device) -> Optional[torch.Tensor]:
 def _medium_struct(medium, table: Optional[torch.Tensor] = None) -> rt_medium:
     return rt_medium(MEDIUM_KIND[medium.kind], float(medium.n0m1), float(medium.h), _ptr(table),
                      0 if table is None else table.numel(), float(getattr(medium, "z0", 0.0)),
-                     float(getattr(medium, "dz", 1.0)))
+                     float(getattr(medium, "dz", 1.0)), float(getattr(medium, "earth_radius", 0.0)))
 
 
 @dataclass

@@ -27,6 +27,7 @@ Z_AXIS = 10_000.0              # m, the axis point the reference plane front sta
 WINDOW_LEAD = 200e-9           # s, trace window opens this long before the reference arrival
 N0_AIR = 2.92e-4               # sea-level refractivity n - 1
 H_AIR = 8000.0                 # m, scale height of the exponential refractivity
+EARTH_RADIUS = 6.371e6         # m, mean Earth radius for the spherical medium
 SEED_BASE = 2309037170
 BLOCK = 1 << 16                # tracks per seeded block
 K_SI = 4.80320471518522e-18    # V*s, e / (4 pi eps0 c): SI prefactor of the fields
@@ -39,20 +40,25 @@ BETA_W_FIELDS = TRACK_FIELDS[8:]     # float64 (FP64 mode) or float32 (mixed mod
 # --------------------------------------------------------------------------- media
 @dataclass(frozen=True)
 class Medium:
-    """Refractive-index model n(z): ``uniform`` n = 1 + n0m1, ``exponential``
-    n = 1 + n0m1 * exp(-z / h), or ``tabulated`` n = 1 + n0m1 * f(z) with f
+    """Refractive-index model: ``uniform`` n = 1 + n0m1, ``exponential``
+    n = 1 + n0m1 * exp(-z / h), ``tabulated`` n = 1 + n0m1 * f(z) with f
     piecewise linear through ``table`` (values at z0 + i * dz, constant beyond
-    the first and last node)."""
+    the first and last node), or ``spherical`` n = 1 + n0m1 * exp(-H / h) with
+    H the height above a spherical Earth of radius ``earth_radius`` whose
+    surface touches z = 0 at the origin."""
     kind: str = "uniform"
     n0m1: float = N0_AIR
     h: float = H_AIR
     table: Optional[tuple] = None
     z0: float = 0.0
     dz: float = 1.0
+    earth_radius: float = 0.0
 
     def __post_init__(self):
-        if self.kind not in ("uniform", "exponential", "tabulated"):
+        if self.kind not in ("uniform", "exponential", "tabulated", "spherical"):
             raise ValueError(f"unknown medium kind {self.kind!r}")
+        if self.kind == "spherical" and not self.earth_radius >= 1000.0:
+            raise ValueError("a spherical medium needs earth_radius >= 1000 m")
         if self.kind == "tabulated":
             if self.table is None or len(self.table) < 2 or not self.dz > 0:
                 raise ValueError("a tabulated medium needs >= 2 nodes and dz > 0")
@@ -60,14 +66,15 @@ class Medium:
 
     @property
     def code(self) -> int:
-        return {"uniform": 0, "exponential": 1, "tabulated": 2}[self.kind]
+        return {"uniform": 0, "exponential": 1, "tabulated": 2, "spherical": 3}[self.kind]
 
 
 def _mean_index(medium: Medium, z_lo: float, z_hi: float) -> float:
     """Mean of n(z) over [z_lo, z_hi] by the trapezoid rule on 4097 points.
 
     Only used to place each antenna's trace window; it is deliberately not the
-    propagator's closed form."""
+    propagator's closed form (and over the spherical Earth it ignores the
+    curvature, which moves a vertical column's heights by well under 1 mm)."""
     if medium.kind == "uniform" or z_hi == z_lo:
         return 1.0 + medium.n0m1
     z = np.linspace(z_lo, z_hi, 4097)
@@ -304,6 +311,82 @@ def shower_tracks(seed: int, n: int, recipe: ShowerRecipe = ShowerRecipe(),
 SHOWER_SEED = SEED_BASE + 5
 
 
+@dataclass(frozen=True)
+class InclinedRecipe:
+    """An inclined shower over a wide array, where the curvature of the Earth
+    shows in the refractive index along the paths: the axis has zenith angle
+    ``zenith_deg`` (azimuth 0: travelling towards +x) and meets the ground at
+    the origin; emission points are uniform along the axis between
+    ``axis_lo`` and ``axis_hi`` metres before the ground, with Gaussian
+    offsets of ``sigma`` across it; directions lie within ``cap_deg`` of the
+    axis (uniform in solid angle); a plane particle front moves down the axis
+    at c from the axis point ``axis_hi`` before the ground at t = 0."""
+    zenith_deg: float = 75.0
+    axis_lo: float = 2_000.0     # m
+    axis_hi: float = 40_000.0
+    sigma: float = 200.0         # m
+    cap_deg: float = 2.0
+    len_lo: float = 0.1          # m
+    len_hi: float = 10.0
+    beta_lo: float = 0.9
+    beta_hi: float = 0.99999
+
+    def frame(self):
+        """Unit vectors: the axis direction of motion u and two across it."""
+        th = math.radians(self.zenith_deg)
+        u = np.array([math.sin(th), 0.0, -math.cos(th)])
+        e1 = np.array([math.cos(th), 0.0, math.sin(th)])
+        e2 = np.array([0.0, 1.0, 0.0])
+        return u, e1, e2
+
+    def front_time(self, x, y, z):
+        """When the plane front passes (x, y, z) (s)."""
+        u, _, _ = self.frame()
+        top = -self.axis_hi * u
+        return ((x - top[0]) * u[0] + (y - top[1]) * u[1] + (z - top[2]) * u[2]) / C_LIGHT
+
+
+def _draw_inclined_block(rng: np.random.Generator, n: int, r: InclinedRecipe) -> Tracks:
+    # fixed draw order: charge, axis distance, two offsets, cos(theta), phi,
+    # length, beta
+    q = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    sa = rng.uniform(r.axis_lo, r.axis_hi, n)
+    a1 = rng.normal(0.0, r.sigma, n)
+    a2 = rng.normal(0.0, r.sigma, n)
+    cos_t = rng.uniform(math.cos(math.radians(r.cap_deg)), 1.0, n)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    length = rng.uniform(r.len_lo, r.len_hi, n)
+    beta = rng.uniform(r.beta_lo, r.beta_hi, n)
+    u, e1, e2 = r.frame()
+    p0 = -sa[:, None] * u + a1[:, None] * e1 + a2[:, None] * e2
+    sin_t = np.sqrt(np.maximum(0.0, 1.0 - cos_t * cos_t))
+    d = (cos_t[:, None] * u + (sin_t * np.cos(phi))[:, None] * e1
+         + (sin_t * np.sin(phi))[:, None] * e2)
+    p1 = p0 + length[:, None] * d
+    t0 = r.front_time(p0[:, 0], p0[:, 1], p0[:, 2])
+    t1 = t0 + length / (beta * C_LIGHT)
+    return Tracks(p0[:, 0].copy(), p0[:, 1].copy(), p0[:, 2].copy(), t0, p1[:, 0].copy(),
+                  p1[:, 1].copy(), p1[:, 2].copy(), t1, beta * d[:, 0], beta * d[:, 1],
+                  beta * d[:, 2], q)
+
+
+INCLINED_SEED = SEED_BASE + 6
+
+
+def inclined_shower(n: int, recipe: InclinedRecipe = InclinedRecipe(), nx: int = 8,
+                    spacing: float = 2_000.0, dt: float = 0.5e-9, n_bins: int = 8192,
+                    seed: int = INCLINED_SEED):
+    """n tracks of the inclined shower and an nx x nx ground grid whose
+    windows open WINDOW_LEAD before the plane front passes each antenna
+    (vacuum speed: refraction delays the pulse by tens of ns, inside the
+    window). Returns (tracks, array)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0])))
+    tr = _draw_inclined_block(rng, max(n, 0), recipe)
+    x, y, z = grid_layout(nx, nx, spacing)
+    t_start = recipe.front_time(x, y, z) - WINDOW_LEAD
+    return tr, AntennaArray(x, y, z, t_start, float(dt), int(n_bins))
+
+
 # --------------------------------------------------------------------------- workloads
 @dataclass
 class Workload:
@@ -336,6 +419,7 @@ def layered_air(dz: float = 50.0, top: float = 20_000.0) -> Medium:
 
 UNIFORM_AIR = Medium("uniform", N0_AIR, H_AIR)
 EXPONENTIAL_AIR = Medium("exponential", N0_AIR, H_AIR)
+SPHERICAL_AIR = Medium("spherical", N0_AIR, H_AIR, earth_radius=EARTH_RADIUS)
 RECIPE_SMALL = TrackRecipe(1_000.0, 10_000.0, 50.0)
 RECIPE_WIDE = TrackRecipe(500.0, 15_000.0, 100.0)
 

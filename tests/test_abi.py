@@ -41,7 +41,7 @@ def test_python_binding_has_the_same_names(rt):
 
 
 def test_version_and_status_strings(rt):
-    assert rt.rt_abi_version() == 1
+    assert rt.rt_abi_version() == rt.ABI_VERSION == 2
     assert rt.rt_status_string(rt.RT_OK) == "ok"
     assert "workspace" in rt.rt_status_string(rt.RT_E_WORKSPACE)
     assert rt.rt_status_string(99) == "unknown status"
@@ -189,3 +189,57 @@ def test_plan_create_rejects_invalid_tables(rt, case):
     st = rt._lib.rt_plan_create(C.byref(handle), C.byref(det), C.byref(med), rt.RT_ENDPOINT,
                                 rt.RT_FP64, 1.0)
     assert st == rt.RT_E_INVALID, rt.rt_last_error()
+
+
+@pytest.mark.parametrize("case", ["zero_radius", "small_radius", "nan_radius", "inf_radius",
+                                  "zero_scale_height"])
+def test_plan_create_rejects_invalid_spheres(rt, case):
+    det, keep = _detector(rt)
+    med = rt.rt_medium(rt.RT_SPHERICAL, 2.92e-4, 8000.0, None, 0, 0.0, 1.0, 6.371e6)
+    if case == "zero_radius":
+        med.earth_radius = 0.0
+    elif case == "small_radius":
+        med.earth_radius = 999.0
+    elif case == "nan_radius":
+        med.earth_radius = float("nan")
+    elif case == "inf_radius":
+        med.earth_radius = float("inf")
+    elif case == "zero_scale_height":
+        med.scale_height = 0.0
+    handle = C.c_void_p()
+    st = rt._lib.rt_plan_create(C.byref(handle), C.byref(det), C.byref(med), rt.RT_ZHS,
+                                rt.RT_MIXED, 1.0)
+    assert st == rt.RT_E_INVALID, rt.rt_last_error()
+    assert "earth_radius" in rt.rt_last_error() or "scale_height" in rt.rt_last_error()
+
+
+def test_medium_struct_carries_the_earth_radius(rt):
+    from paper_2309_03717_amd.workloads import SPHERICAL_AIR, EXPONENTIAL_AIR
+    m = rt._medium_struct(SPHERICAL_AIR)
+    assert m.kind == rt.RT_SPHERICAL and m.earth_radius == 6.371e6 and m.scale_height == 8000.0
+    assert rt._medium_struct(EXPONENTIAL_AIR).earth_radius == 0.0
+    assert C.sizeof(rt.rt_medium) == 64
+
+
+@pytest.mark.parametrize("medium", ["uniform", "exponential", "layered", "spherical"])
+def test_plan_binding_passes_every_medium_field(rt, medium):
+    """The Python Plan marshals each medium completely: on a host without a
+    GPU the library validates the medium first and then reports the missing
+    device (an incomplete medium would be rejected as invalid)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2309_03717_amd import workloads as W
+    md = {"uniform": W.UNIFORM_AIR, "exponential": W.EXPONENTIAL_AIR,
+          "layered": W.layered_air(), "spherical": W.SPHERICAL_AIR}[medium]
+    arr = W.config(0).array
+    det = rt.DeviceDetector.from_array(arr, device="cpu")
+    with pytest.raises(rt.RadtraceError) as e:
+        rt.Plan(det, md, "zhs", "mixed")
+    assert e.value.status == rt.RT_E_NO_DEVICE, rt.rt_last_error()
+    # a radius the Python check would refuse, set past it to reach the library's
+    bad = W.Medium("spherical", W.N0_AIR, W.H_AIR, earth_radius=6.371e6)
+    object.__setattr__(bad, "earth_radius", 10.0)
+    with pytest.raises(rt.RadtraceError) as e:
+        rt.Plan(det, bad, "zhs", "mixed")
+    assert e.value.status == rt.RT_E_INVALID

@@ -307,6 +307,62 @@ def test_tabulated_medium_rejected_by_adjoint_and_batch(rt):
     assert e.value.status == rt.RT_E_UNSUPPORTED
 
 
+# ----------------------------------------------------------------- spherical Earth
+def spherical_case(which, n):
+    """(tracks, array) for the spherical-Earth tests: the star with antennas
+    at several heights and config-1 tracks, or the inclined shower over a
+    14-km grid, where the curvature moves arrival times by up to ~0.1 ns."""
+    if which == "star":
+        return W.config(1).tracks(n), tilted_star(W.SPHERICAL_AIR)
+    return W.inclined_shower(n)
+
+
+@pytest.mark.parametrize("which", ["star", "inclined"])
+def test_spherical_propagator_bit_exact(rt, orc, which):
+    import torch
+    md = W.SPHERICAL_AIR
+    tr, arr = spherical_case(which, 800)
+    det = rt.DeviceDetector.from_array(arr)
+    plan = rt.Plan(det, md, "endpoint", "fp64")
+    t, b = plan.propagate(rt.DeviceTracks.from_tracks(tr))
+    torch.cuda.synchronize()
+    t_ref, _, b_ref = orc.propagate(tr, arr, md)
+    assert (b_ref >= 0).mean() > 0.3
+    assert np.array_equal(b.cpu().numpy(), b_ref)
+    assert np.array_equal(t.cpu().numpy(), t_ref)
+
+
+@pytest.mark.parametrize("which", ["star", "inclined"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_spherical_medium_traces(rt, orc, formalism, precision, which):
+    """Exponential atmosphere over the spherical Earth (path mean by
+    quadrature per pair): traces against the oracle."""
+    md = W.SPHERICAL_AIR
+    tr, arr = spherical_case(which, 20_000)
+    got = gpu_traces(rt, formalism, precision, tr, arr, md)
+    ref = oracle_traces(orc, formalism, precision, tr, arr, md)
+    err = rel_l2(got, ref)
+    print(formalism, precision, which, "spherical: max rel L2", err.max())
+    assert np.abs(ref).max() > 0
+    assert err.max() <= (FP64_BOUND if precision == "fp64" else MIXED_BOUND)
+
+
+def test_spherical_medium_rejected_by_adjoint_and_batch(rt):
+    import torch
+    md = W.SPHERICAL_AIR
+    tr, arr = spherical_case("star", 100)
+    det = rt.DeviceDetector.from_array(arr)
+    plan = rt.Plan(det, md, "endpoint", "fp64")
+    g = torch.zeros((arr.m, arr.n_bins, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(rt.RadtraceError) as e:
+        plan.vjp(rt.DeviceTracks.from_tracks(tr), g)
+    assert e.value.status == rt.RT_E_UNSUPPORTED
+    with pytest.raises(rt.RadtraceError) as e:
+        rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
+    assert e.value.status == rt.RT_E_UNSUPPORTED
+
+
 # ----------------------------------------------------------------- degenerate cases
 def test_degenerate_tracks(rt, orc):
     """Zero-length tracks (the two Endpoint impulses cancel, the ZHS box has

@@ -573,3 +573,159 @@ def test_adjoints_reject_tabulated_media(orc):
     for fn in (orc.zhs_vjp, orc.endpoint_vjp):
         with pytest.raises(ValueError):
             fn(tr, w.array, _TAB, g)
+
+
+# ----------------------------------------------------------------- spherical Earth
+from paper_2309_03717_amd.workloads import EARTH_RADIUS, SPHERICAL_AIR  # noqa: E402
+
+
+def _sph_height(q, re):
+    """Height above the sphere written the plain way, |q - C| - re, in long
+    double (a different expression from the oracle's)."""
+    x, y, z = (np.longdouble(v) for v in q)
+    re = np.longdouble(re)
+    return float(np.sqrt(x * x + y * y + (z + re) * (z + re)) - re)
+
+
+def _neff_from_time(orc, md, p, x):
+    tr = one_track(p, np.asarray(p) + [0, 0, -1.0], (0, 0, -0.99), t0=2e-6)
+    ar = antennas([x], 0.0, 1e-9, 10)
+    t, _, _ = orc.propagate(tr, ar, md)
+    r = float(np.linalg.norm(np.asarray(x, float) - np.asarray(p, float)))
+    return (t[0, 0, 0] - 2e-6) * C_LIGHT / r
+
+
+def test_gauss_legendre_rule(orc):
+    """The oracle's quadrature is the 8-point Gauss-Legendre rule on [0, 1]:
+    it integrates s^j exactly for j = 0..15 (evaluated exactly on its double
+    nodes and weights: relative error within 2 ulp) and not s^16; and it agrees
+    with numpy's rule moved to [0, 1] (nodes (1 + x) / 2, weights w / 2) within
+    numpy's own accuracy."""
+    from fractions import Fraction
+    s, w = orc.gl_rule()
+    assert s.shape == (8,) and np.all(np.diff(s) > 0) and np.all(w > 0)
+    sf = [Fraction(float(v)) for v in s]
+    wf = [Fraction(float(v)) for v in w]
+    for j in range(17):
+        moment = sum(wk * sk ** j for sk, wk in zip(sf, wf))
+        rel = abs(float(moment * (j + 1) - 1))
+        if j < 16:
+            assert rel <= 2 * ULP, (j, rel)
+        else:
+            assert rel > 1e-10
+    x, wx = np.polynomial.legendre.leggauss(8)
+    assert np.allclose(s, (1.0 + x) / 2.0, rtol=1e-14, atol=0)
+    assert np.allclose(w, wx / 2.0, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("p,x", [
+    ((0.0, 0.0, 12_000.0), (0.0, 0.0, 0.0)),            # radial: H = z along the path
+    ((300.0, -150.0, 8_000.0), (1_200.0, 400.0, 0.0)),   # a near-vertical shower pair
+    ((60_000.0, 0.0, 9_000.0), (0.0, 0.0, 0.0)),         # inclined, 60 km away
+    ((-150_000.0, 20_000.0, 20_000.0), (0.0, 0.0, 5.0)),  # far and high
+    ((-50_000.0, 0.0, 0.0), (50_000.0, 0.0, 0.0)),       # a chord along the ground
+    ((0.0, 0.0, 50.0), (100.0, 0.0, 1_500.0)),           # antenna above the emission
+])
+def test_spherical_index_is_path_mean(orc, p, x):
+    """Spherical Earth: n_eff = (t - T) c / R equals the mean of
+    1 + n0m1 exp(-H/h) along the straight path by adaptive quadrature, with H
+    = |q - C| - re evaluated independently."""
+    md = SPHERICAL_AIR
+    neff = _neff_from_time(orc, md, p, x)
+    p_, d = np.asarray(p, float), np.asarray(x, float) - np.asarray(p, float)
+    f = lambda s: md.n0m1 * math.exp(-_sph_height(p_ + s * d, md.earth_radius) / md.h)
+    mean = integrate.quad(f, 0.0, 1.0, epsabs=0, epsrel=1e-13, limit=200)[0]
+    assert (neff - 1.0) == pytest.approx(mean, rel=1e-9)
+
+
+def test_spherical_chord_sees_the_ground_fall_away(orc):
+    """A 100-km chord along z = 0 rises above the curved ground (H up to
+    d^2 / (2 re) at its ends), so its mean index is below the flat 1 + n0m1:
+    about 1 - d^2 / (6 re h) of it with d = 50 km."""
+    md = SPHERICAL_AIR
+    neff = _neff_from_time(orc, md, (-50_000.0, 0.0, 0.0), (50_000.0, 0.0, 0.0))
+    approx = 1.0 - 50_000.0 ** 2 / (6 * EARTH_RADIUS * md.h)
+    assert (neff - 1.0) / md.n0m1 == pytest.approx(approx, rel=2e-3)
+    assert (neff - 1.0) / md.n0m1 < 0.995
+
+
+def test_spherical_radial_and_flat_limits_equal_exponential(orc):
+    """Along the vertical through the origin H = z, and for a huge radius the
+    ground is flat: both reduce to the exponential closed form, to the
+    quadrature's accuracy (bins may differ only at edges)."""
+    w = config(1)
+    tr = w.tracks(300)
+    flat = Medium("spherical", N0_AIR, 8000.0, earth_radius=1e15)
+    t_e, _, b_e = orc.propagate(tr, w.array, w.medium)
+    t_f, _, b_f = orc.propagate(tr, w.array, flat)
+    T = np.stack([tr.t0, tr.t1])[:, :, None]
+    assert np.all(np.abs((t_f - T) - (t_e - T)) <= 1e-12 * N0_AIR * (t_e - T) + 4 * ULP * t_e)
+    assert (b_f != b_e).mean() < 1e-3
+    for zp in (500.0, 7_000.0, 15_000.0):
+        n_s = _neff_from_time(orc, SPHERICAL_AIR, (0.0, 0.0, zp), (0.0, 0.0, 0.0))
+        n_e = _neff_from_time(orc, EXPONENTIAL_AIR, (0.0, 0.0, zp), (0.0, 0.0, 0.0))
+        assert (n_s - 1.0) == pytest.approx(n_e - 1.0, rel=1e-11)
+
+
+def test_spherical_without_refractivity_is_vacuum_exactly(orc):
+    """n0m1 = 0: every medium is vacuum; the spherical traces equal the
+    uniform n = 1 traces bit for bit."""
+    w = config(0)
+    tr = w.tracks(200)
+    vac_s = Medium("spherical", 0.0, 8000.0, earth_radius=EARTH_RADIUS)
+    vac_u = Medium("uniform", 0.0, 8000.0)
+    for f in ("endpoint", "zhs"):
+        assert np.array_equal(orc.traces(f, tr, w.array, vac_s), orc.traces(f, tr, w.array, vac_u))
+
+
+def test_spherical_rotation_about_the_vertical(orc):
+    """The sphere is symmetric about the vertical through the origin: turning
+    tracks and antennas by 90 degrees turns the fields with them."""
+    w = config(1)
+    tr = w.tracks(400)
+    rot = Tracks(-tr.y0, tr.x0, tr.z0, tr.t0, -tr.y1, tr.x1, tr.z1, tr.t1, -tr.by, tr.bx, tr.bz,
+                 tr.qw)
+    a = w.array
+    from paper_2309_03717_amd.workloads import AntennaArray
+    ar = AntennaArray(-a.y, a.x.copy(), a.z.copy(), a.t_start, a.dt, a.n_bins)
+    for f in ("endpoint", "zhs"):
+        e0 = orc.traces(f, tr, a, SPHERICAL_AIR)
+        e1 = orc.traces(f, rot, ar, SPHERICAL_AIR)
+        turned = np.stack([-e0[..., 1], e0[..., 0], e0[..., 2]], axis=-1)
+        assert np.abs(e0).max() > 0
+        assert np.linalg.norm(e1 - turned) <= 1e-9 * np.linalg.norm(e0)
+
+
+def test_spherical_endpoint_uses_the_height_above_the_sphere(orc):
+    """Endpoint impulse of one far track end: D = 1 - n(P) beta.r with n(P)
+    from the height above the sphere (not z), against a direct evaluation."""
+    md = SPHERICAL_AIR
+    p0 = np.array([-40_000.0, 3_000.0, 6_000.0])
+    beta = np.array([0.70, -0.05, -0.70])
+    tr = one_track(p0, p0 + 2.0 * beta / np.linalg.norm(beta), beta, t0=0.0)
+    x = np.array([0.0, 0.0, 0.0])
+    t, _, _ = orc.propagate(tr, antennas([x], 0.0, 1e-9, 10), md)
+    dt = 0.2e-9
+    ar = antennas([x], t[0, 0, 0] - 100.5 * dt, dt, 4096)   # the start lands mid-bin 100
+    e = orc.traces("endpoint", tr, ar, md)
+    d = x - p0
+    r = np.linalg.norm(d)
+    rhat = d / r
+    n_src = 1.0 + md.n0m1 * math.exp(-_sph_height(p0, md.earth_radius) / md.h)
+    doppler = 1.0 - n_src * float(beta @ rhat)
+    v = rhat * float(beta @ rhat) - beta
+    expect = v / (doppler * r * dt)
+    assert np.allclose(e[0, 100], expect, rtol=1e-12, atol=0)
+    # with n taken at z instead the value differs clearly
+    n_flat = 1.0 + md.n0m1 * math.exp(-p0[2] / md.h)
+    wrong = v / ((1.0 - n_flat * float(beta @ rhat)) * r * dt)
+    assert not np.allclose(e[0, 100], wrong, rtol=1e-9, atol=0)
+
+
+def test_adjoints_reject_spherical_media(orc):
+    w = config(3)
+    tr = w.tracks(4)
+    g = np.zeros((w.array.m, w.array.n_bins, 3))
+    for fn in (orc.zhs_vjp, orc.endpoint_vjp):
+        with pytest.raises(ValueError):
+            fn(tr, w.array, SPHERICAL_AIR, g)

@@ -90,3 +90,27 @@ def test_shower_stream_is_reproducible_time_ordered_and_regenerable():
     assert np.median(r) == pytest.approx(30.0 * np.log(2), rel=0.05)
     L = np.sqrt((a.x1 - a.x0) ** 2 + (a.y1 - a.y0) ** 2 + (a.z1 - a.z0) ** 2)
     assert L.min() >= 0.1 - 1e-9 and L.max() <= 2.0 + 1e-9
+
+
+def test_inclined_shower_geometry():
+    """The inclined stream: seeded, emission points near the axis and above
+    ground, directions within the cap of the axis, start times on the plane
+    front, and windows that open 200 ns before it passes each antenna."""
+    r = W.InclinedRecipe()
+    tr, ar = W.inclined_shower(5000)
+    tr2, _ = W.inclined_shower(5000)
+    assert np.array_equal(tr.x0, tr2.x0) and np.array_equal(tr.t1, tr2.t1)
+    u, e1, e2 = r.frame()
+    assert abs(u @ e1) < 1e-15 and abs(u @ e2) < 1e-15 and abs(np.linalg.norm(u) - 1) < 1e-15
+    p0 = np.stack([tr.x0, tr.y0, tr.z0], axis=1)
+    along = -(p0 @ u)
+    assert along.min() > r.axis_lo - 5 * r.sigma and along.max() < r.axis_hi + 5 * r.sigma
+    assert tr.z0.min() > 0.0
+    beta = np.stack([tr.bx, tr.by, tr.bz], axis=1)
+    bn = np.linalg.norm(beta, axis=1)
+    assert np.all((bn >= r.beta_lo) & (bn <= r.beta_hi))
+    assert np.all(beta @ u / bn >= math.cos(math.radians(r.cap_deg)) - 1e-12)
+    assert np.allclose(tr.t0, r.front_time(tr.x0, tr.y0, tr.z0), rtol=1e-12, atol=1e-18)
+    assert ar.m == 64 and ar.n_bins == 8192
+    assert np.allclose(ar.t_start, r.front_time(ar.x, ar.y, ar.z) - W.WINDOW_LEAD, rtol=0,
+                       atol=1e-18)
