@@ -372,6 +372,45 @@ def bench_adjoint(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_oracle(args):
+    """The FP64 oracle alone on the host (no GPU): the grid workload's first
+    args.cpu_sample tracks x all 4096 antennas, both formalisms, at one thread
+    and at every host thread (at most 16), the latter also with the antenna
+    bunch sizes {1, 4, 16, 64} (the paper's unit of work per thread) beside
+    the default ceil(M / threads). Reported for context: the oracle is the
+    reference, not a tuned CPU code."""
+    import oracle
+    from paper_2309_03717_amd import workloads as W
+    oracle._load()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    w = W.config(2)
+    tr = w.tracks(args.cpu_sample).to_mixed().widened()
+    pairs = tr.n * w.array.m
+    runs = []
+    for threads, bunch in [(1, 0), (cores, 0), (cores, 1), (cores, 4), (cores, 16), (cores, 64)]:
+        secs = {}
+        for f in ("endpoint", "zhs"):
+            t0 = time.perf_counter()
+            oracle.traces(f, tr, w.array, w.medium, k=1.0, n_threads=threads, bunch=bunch)
+            secs[f] = time.perf_counter() - t0
+        rate = 2 * pairs / (secs["endpoint"] + secs["zhs"])
+        runs.append({"threads": threads, "bunch": bunch or -(-w.array.m // threads),
+                     "pairs_per_s": rate, "seconds": {k: round(v, 3) for k, v in secs.items()}})
+        log(f"oracle {threads} threads, bunch {runs[-1]['bunch']}: {rate / 1e6:.1f} M pairs/s")
+    best = max(r["pairs_per_s"] for r in runs)
+    print(json.dumps({"metric": "oracle antenna-track pairs/sec (Endpoint, ZHS), host CPU",
+                      "value": best, "unit": "pairs/s", "n_gpus": 0, "steps": 1, "warmup": 0,
+                      "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"{w.name}[{tr.n}]", "n_antennas": w.array.m,
+                                 "host_threads": cores},
+                      "speedup_all_threads": round(runs[1]["pairs_per_s"] / runs[0]["pairs_per_s"], 2),
+                      "runs": runs}), flush=True)
+
+
 def bench_copy(args):
     """Calibration for hardware byte counters: a plain device-to-device copy
     of a known size (args.copy_mib MiB read and written per launch)."""
@@ -409,11 +448,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
     ap.add_argument("--workload", default="grid4096",
-                    choices=["grid4096", "batched", "adjoint", "shower", "copy"],
+                    choices=["grid4096", "batched", "adjoint", "shower", "copy", "oracle"],
                     help="grid4096: 1e8 tracks x 4096 antennas (default); batched: 256 showers; "
                          "adjoint: forward + VJP on 1e6 tracks x 64 antennas; "
                          "shower: shower-like vs random tracks on the grid; "
-                         "copy: byte-counter calibration")
+                         "copy: byte-counter calibration; oracle: the CPU oracle alone "
+                         "at 1 and all host threads and several antenna bunch sizes")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
     ap.add_argument("--showers", type=int, default=256, help="batched: number of showers")
     ap.add_argument("--medium", default="exponential",
@@ -435,6 +475,9 @@ def main():
         return
     if args.workload == "copy":
         bench_copy(args)
+        return
+    if args.workload == "oracle":
+        bench_oracle(args)
         return
     if args.workload == "adjoint":
         bench_adjoint(args)
