@@ -348,6 +348,28 @@ def test_spherical_medium_traces(rt, orc, formalism, precision, which):
     assert err.max() <= (FP64_BOUND if precision == "fp64" else MIXED_BOUND)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_spherical_tilings(rt, orc, formalism, precision):
+    """The spherical deposits under every tiling of the invariance test
+    (tiles of up to 4 antennas, bin segments, splits, small workgroups,
+    short passes): against the oracle, and against each other up to
+    summation order."""
+    md = W.SPHERICAL_AIR
+    tr, arr = spherical_case("star", 3000)
+    ref = oracle_traces(orc, formalism, precision, tr, arr, md)
+    bound = FP64_BOUND if precision == "fp64" else MIXED_BOUND
+    base = None
+    for tl in TILINGS:
+        g = gpu_traces(rt, formalism, precision, tr, arr, md, tiling=tl)
+        assert rel_l2(g, ref).max() <= bound, tl
+        if base is None:
+            base = g
+        else:
+            np.testing.assert_allclose(g, base, rtol=0, atol=(1e-11 if precision == "fp64" else 1e-6)
+                                       * np.abs(base).max(), err_msg=str(tl))
+
+
 def test_spherical_medium_rejected_by_adjoint_and_batch(rt):
     import torch
     md = W.SPHERICAL_AIR
