@@ -369,7 +369,37 @@ def bench_adjoint(args):
                       "n_tracks": n, "n_antennas": w.array.m, "n_bins": w.array.n_bins,
                       "precision": "mixed"},
            "per_formalism": per}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_adjoint(w, min(args.cpu_sample, n), grad)
     print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_adjoint(workload, n_sample, grad):
+    """The FP64 oracle's forward traces plus its vector-Jacobian product, both
+    formalisms, on the first n_sample tracks (the same float-rounded inputs and
+    upstream gradient), in the bench's unit: forward + adjoint pairs/s."""
+    import oracle
+    oracle._load()
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    tr = workload.tracks(n_sample).to_mixed().widened()
+    g = grad.double().cpu().numpy()
+    secs = {}
+    for f, vjp in (("zhs", oracle.zhs_vjp), ("endpoint", oracle.endpoint_vjp)):
+        t0 = time.perf_counter()
+        oracle.traces(f, tr, workload.array, workload.medium, n_threads=cores)
+        vjp(tr, workload.array, workload.medium, g, n_threads=cores)
+        secs[f] = time.perf_counter() - t0
+        log(f"cpu baseline {f} forward + vjp: {secs[f]:.2f} s on {cores} threads")
+    pairs = tr.n * workload.array.m
+    return {"value": 2 * 2 * pairs / (secs["zhs"] + secs["endpoint"]), "unit": "pairs/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"first {tr.n} tracks x all {workload.array.m} antennas, forward traces + "
+                      f"VJP of both formalisms, FP64 oracle on the same float32-rounded inputs",
+            "seconds": {k: round(v, 3) for k, v in secs.items()}}
 
 
 def bench_oracle(args):
