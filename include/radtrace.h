@@ -166,7 +166,8 @@ int rt_plan_destroy(rt_plan *plan);
  * keeps the automatic choice.
  *  antennas_per_block: antennas whose traces one workgroup keeps in LDS (1-8)
  *  track_splits: track ranges per pass, merged in fixed order afterwards
- *  block_threads: workgroup size, a multiple of 64 in [64, 1024]
+ *  block_threads: workgroup size, a multiple of 64 in [64, 1024] (automatic:
+ *                 1024, four waves per SIMD beside one trace tile per CU)
  *  bins_per_segment: bins per LDS trace segment, a multiple of 64 (or
  *                    n_bins); segments split long traces across workgroups
  *  tracks_per_pass: a call deposits its tracks in consecutive passes of at

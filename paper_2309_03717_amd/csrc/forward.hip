@@ -12,10 +12,11 @@
 // order into the caller's traces, so no float atomic ever touches global
 // memory and a fixed tiling gives the same merge order on every call.
 //
-// Track records are loaded one wave block ahead (register double-buffering)
-// so that the L2 latency of the next record overlaps the arithmetic of the
-// current one; with one 4096-bin FP64 trace per workgroup every record is read
-// once per antenna, which makes this loop sensitive to load latency.
+// With one 4096-bin FP64 trace per workgroup every record is read once per
+// antenna, which makes this loop sensitive to load latency. Workgroups of 1024
+// threads (four waves per SIMD, one workgroup per CU) cover most of it; the
+// Endpoint deposit, bound by record delivery, also loads each record one wave
+// block ahead (register double-buffering).
 //
 // Precision. Accumulation in LDS and in the split partials is double in both
 // modes: gfx950 executes LDS double-precision atomic adds (ds_add_f64) at close
