@@ -41,9 +41,10 @@ enum : int {
 // single-precision fields in pairs, (amplitude, bx) and (by, bz), and keep the
 // height factors e0, e1 in double precision in slots 12-13 (the Endpoint
 // source index 1 + (n0 - 1) e sits next to the Cherenkov pole, where a
-// rounded index would dominate the error). A wave reads 12 of the 16 slots,
-// plus the height factors where the exponential Endpoint needs the source
-// index or a tile antenna sits off the reference height.
+// rounded index would dominate the error). A wave reads 12 of the 16 slots
+// (10 in the uniform medium), plus the height factors where the exponential
+// Endpoint needs the source index or a tile antenna sits off the reference
+// height.
 enum : int { M_AB = 10, M_YZ = 11, M_E0 = 12, M_E1 = 13 };
 
 __device__ __forceinline__ double pack2(float lo, float hi) {
@@ -57,11 +58,16 @@ __device__ __forceinline__ float hi32(double d) {
   return __uint_as_float((unsigned)((unsigned long long)__double_as_longlong(d) >> 32));
 }
 
-// Record slots a wave loads: all of an FP64 record; of a mixed record the
-// first 12, and the height factors when H.
-template <int P, bool H>
-constexpr int record_loads() {
-  return P == 0 ? kRec : (H ? M_E1 + 1 : M_YZ + 1);
+// Slots a wave loads from a record: all of an FP64 record; of a mixed record
+// the geometry, times and packed single-precision fields, the path indices
+// except in the uniform medium (where the index is the constant 1 + n0m1),
+// and the height factors when H.
+template <int P, int MED, bool H>
+constexpr bool slot_loaded(int f) {
+  if (P == 0) return true;
+  if (f == R_NE0 || f == R_NE1) return MED != 0;
+  if (f <= M_YZ) return true;
+  return H && f <= M_E1;
 }
 
 // Builds the record of one track (fields as above). A track with any
@@ -264,7 +270,8 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
-        double ne0 = v[R_NE0], ne1 = v[R_NE1];
+        double ne0 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE0];
+        double ne1 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE1];
         if (MED == 3) {
           ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
           ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
@@ -288,7 +295,8 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
-        double ne0 = v[R_NE0], ne1 = v[R_NE1];
+        double ne0 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE0];
+        double ne1 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE1];
         if (MED == 3) {
           ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
           ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
@@ -323,25 +331,25 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
                                                  const Tile<AT> &t, acc_t *tile, int row_len,
                                                  int lo, int hi, double lo_d, double hi_d,
                                                  const Consts &c) {
-  constexpr int kLoad = record_loads<P, H>();
   const int lane = threadIdx.x & 63;
   if (!PF) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
       double rv[kRec];
       const double *r = rec + blk * (kRec * 64) + lane;
 #pragma unroll
-      for (int f = 0; f < kRec; ++f) rv[f] = f < kLoad ? r[f * 64] : 0.0;
+      for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
       deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
     }
     return;
   }
   double nx[kRec];
 #pragma unroll
-  for (int f = kLoad; f < kRec; ++f) nx[f] = 0.0;
+  for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
   if (b_first < b_end) {
     const double *r = rec + b_first * (kRec * 64) + lane;
 #pragma unroll
-    for (int f = 0; f < kLoad; ++f) nx[f] = r[f * 64];
+    for (int f = 0; f < kRec; ++f)
+      if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
   }
   for (int64_t blk = b_first; blk < b_end; blk += waves) {
     double rv[kRec];
@@ -350,7 +358,8 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
     if (blk + waves < b_end) {
       const double *r = rec + (blk + waves) * (kRec * 64) + lane;
 #pragma unroll
-      for (int f = 0; f < kLoad; ++f) nx[f] = r[f * 64];
+      for (int f = 0; f < kRec; ++f)
+        if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
     }
     deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
   }
