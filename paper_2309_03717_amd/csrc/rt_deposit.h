@@ -42,9 +42,9 @@ enum : int {
 // height factors e0, e1 in double precision in slots 12-13 (the Endpoint
 // source index 1 + (n0 - 1) e sits next to the Cherenkov pole, where a
 // rounded index would dominate the error). A wave reads 12 of the 16 slots
-// (10 in the uniform medium), plus the height factors where the exponential
-// Endpoint needs the source index or a tile antenna sits off the reference
-// height.
+// (10 without the path indices: uniform medium, spherical Earth), plus the
+// height factors where the Endpoint needs the source index or a tile antenna
+// sits off the reference height.
 enum : int { M_AB = 10, M_YZ = 11, M_E0 = 12, M_E1 = 13 };
 
 __device__ __forceinline__ double pack2(float lo, float hi) {
@@ -58,14 +58,15 @@ __device__ __forceinline__ float hi32(double d) {
   return __uint_as_float((unsigned)((unsigned long long)__double_as_longlong(d) >> 32));
 }
 
-// Slots a wave loads from a record: all of an FP64 record; of a mixed record
-// the geometry, times and packed single-precision fields, the path indices
-// except in the uniform medium (where the index is the constant 1 + n0m1),
-// and the height factors when H.
+// Slots a wave loads from a record: the geometry, times, amplitude and
+// velocity; the path indices to the reference height only where the deposit
+// reads them (not in the uniform medium, whose index is the constant 1 + n0m1,
+// nor over the spherical Earth, which takes it per pair); the height factors
+// only when H.
 template <int P, int MED, bool H>
 constexpr bool slot_loaded(int f) {
-  if (P == 0) return true;
-  if (f == R_NE0 || f == R_NE1) return MED != 0;
+  if (f == R_NE0 || f == R_NE1) return MED == 1 || MED == 2;
+  if (P == 0) return (f == R_E0 || f == R_E1) ? H : true;
   if (f <= M_YZ) return true;
   return H && f <= M_E1;
 }
@@ -235,8 +236,8 @@ struct Tile {
 
 // All deposits of one track record (this lane's track) into the tile
 // antennas selected by mask.
-// H: the height factors are present (always in FP64 records; in mixed
-// records when deposit_blocks loaded them).
+// H: the height factors were loaded (deposit_blocks loads them where they are
+// used).
 template <int F, int P, int MED, int AT, bool H>
 __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, const Tile<AT> &t,
                                                acc_t *tile, int row_len, int lo, int hi,
@@ -250,7 +251,7 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
     bx = v[R_BX];
     by = v[R_BY];
     bz = v[R_BZ];
-    if (MED != 0) {
+    if (MED != 0 && H) {
       e0 = v[R_E0];
       e1 = v[R_E1];
     }
@@ -270,8 +271,8 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
-        double ne0 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE0];
-        double ne1 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE1];
+        double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
+        double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
         if (MED == 3) {
           ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
           ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
@@ -295,8 +296,8 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 #pragma unroll
     for (int a = 0; a < AT; ++a) {
       if ((mask >> a) & 1) {
-        double ne0 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE0];
-        double ne1 = P == 1 && MED == 0 ? c.n_uniform : v[R_NE1];
+        double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
+        double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
         if (MED == 3) {
           ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
           ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
@@ -365,9 +366,9 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
   }
 }
 
-// As deposit_blocks_n, reading the height factors of mixed records only where
-// they are used: the exponential Endpoint (source index) and tiles with an
-// antenna off the reference height.
+// As deposit_blocks_n, reading the height factors only where they are used:
+// the Endpoint source index in non-uniform media, and tiles with an antenna off
+// the reference height (whose path index is taken per pair from them).
 template <int F, int P, int MED, int AT, bool PF>
 __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
                                                int64_t waves, uint64_t mask, const Tile<AT> &t,
@@ -376,7 +377,7 @@ __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_firs
   bool off = false;
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
-  if (P == 0 || (MED == 3 ? F == 0 : MED != 0 && (F == 0 || off)))
+  if (MED == 3 ? F == 0 : MED != 0 && (F == 0 || off))
     deposit_blocks_n<F, P, MED, AT, true, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
                                               lo, hi, lo_d, hi_d, c);
   else
