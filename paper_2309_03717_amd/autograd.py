@@ -49,7 +49,11 @@ def radio_traces(formalism: str, qw, p0, p1, n0m1, *, t0, t1, beta, det: rt.Devi
                  medium_kind: str, scale_height: float = 8000.0, precision: str = "mixed",
                  k: float = 1.0):
     """Traces [M, n_bins, 3] of the given tracks in the given formalism
-    ("zhs" or "endpoint"), differentiable in qw, p0, p1 and n0m1."""
+    ("zhs" or "endpoint"), differentiable in qw, p0, p1 and n0m1. The adjoints
+    are defined for the uniform and exponential media."""
+    if medium_kind not in ("uniform", "exponential"):
+        raise ValueError(f"differentiable traces take the uniform and exponential media, "
+                         f"not {medium_kind!r}")
     return RadioTraces.apply(qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium_kind,
                              scale_height, precision, k)
 
