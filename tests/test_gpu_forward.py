@@ -115,6 +115,24 @@ def test_fp64_star_array_exponential(rt, orc, formalism):
     assert err.max() <= FP64_BOUND
 
 
+@pytest.mark.parametrize("cfg", [0, 3])
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_mixed_error_whole_small_workloads(rt, orc, formalism, cfg):
+    """The mixed-precision error of the whole 16-antenna uniform workload
+    (1e4 tracks) and of the forward traces of the differentiable workload
+    (1e6 tracks x 64 antennas), against the oracle on the same float-rounded
+    inputs."""
+    w = W.config(cfg)
+    tr = w.tracks()
+    gpu = gpu_traces(rt, formalism, "mixed", tr, w.array, w.medium)
+    ref = oracle_traces(orc, formalism, "mixed", tr, w.array, w.medium)
+    err = rel_l2(gpu, ref)
+    print(f"{formalism} mixed config{cfg} ({tr.n} tracks): max rel L2 {err.max():.3e} "
+          f"median {np.median(err):.3e}")
+    assert np.abs(ref).max() > 0
+    assert err.max() <= MIXED_BOUND
+
+
 @pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
 def test_mixed_star_array_exponential(rt, orc, formalism):
     """Mixed precision: same bins (FP64 timing), FP32 amplitudes; the oracle
