@@ -478,39 +478,116 @@ static double value_at(const double *g, int32_t n_bins, double u) {
   return g[3 * (int64_t)floor(u)];
 }
 
-/* d t / d P for the propagator: (n_eff dR/dP + R dn_eff/dP) / c, and
- * d t / d n0m1 = R (dn_eff / dn0m1) / c. */
+/* Tabulated profile: slope of f at z (the cell z falls in, as tab_f takes it;
+ * zero beyond the first and last node, where f is constant). */
+static double tab_slope(const orc_medium *md, double z) {
+  double t = (z - md->z0) * (1.0 / md->dz);
+  int64_t last = md->n_f - 1;
+  if (!(t > 0.0) || t >= (double)last) return 0.0;
+  int64_t i = (int64_t)floor(t);
+  return (md->f[i + 1] - md->f[i]) / md->dz;
+}
+
+/* Gradient of the path index n_eff(P, X) with respect to the emission point
+ * P (out_grad) and its derivative with respect to n0m1 (out_dn0):
+ *   exponential: n = 1 + n0m1 h (e_X - e_P) / (z_P - z_X);
+ *   tabulated:   n = 1 + n0m1 (F(z_P) - F(z_X)) / (z_P - z_X), dF/dz = f;
+ *   both with n = 1 + n0m1 (local factor at the mid height) below 1 mm;
+ *   spherical:   n = 1 + n0m1 S, S = sum_k w_k exp(-H(q_k) / h), q_k = P +
+ *                s_k (X - P), and dH(q)/dq = (q - C) / |q - C|, dq_k/dP = 1 - s_k. */
+static void index_gradient(const orc_medium *md, double px, double py, double pz, double ax,
+                           double ay, double az, double out_grad[3], double *out_dn0) {
+  out_grad[0] = out_grad[1] = out_grad[2] = 0.0;
+  if (md->kind == 0) {
+    *out_dn0 = 1.0;
+    return;
+  }
+  if (md->kind == 3) {
+    pthread_once(&gl_once, gl_init);
+    double sum = 0.0, g[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < ORC_GL; ++k) {
+      double s = gl_node[k];
+      double qz = pz + s * (az - pz);
+      double q[3] = {px + s * (ax - px), py + s * (ay - py), qz + md->re};   /* q - C */
+      double rho2 = sphere_rho2(md, q[0], q[1], qz);
+      double len = sqrt(rho2 + md->re * md->re);                            /* |q - C| */
+      double e = exp(-((rho2 / (len + md->re)) / md->h));
+      sum += gl_weight[k] * e;
+      for (int j = 0; j < 3; ++j) g[j] += gl_weight[k] * e * (1.0 - s) * q[j] / len;
+    }
+    for (int j = 0; j < 3; ++j) out_grad[j] = -md->n0m1 * g[j] / md->h;
+    *out_dn0 = sum;
+    return;
+  }
+  double del = pz - az;
+  if (fabs(del) >= 1e-3) {
+    if (md->kind == 2) {
+      double fbar = (tab_F(md, pz) - tab_F(md, az)) / del;
+      out_grad[2] = md->n0m1 * (tab_f(md, pz) - fbar) / del;
+      *out_dn0 = fbar;
+    } else {
+      double h = md->h, ep = exp(-pz / h), ea = exp(-az / h);
+      double f = (ea - ep) / del;
+      /* d f / d zp = (ep / h) / del - (ea - ep) / del^2 */
+      out_grad[2] = md->n0m1 * h * ((ep / h) / del - (ea - ep) / (del * del));
+      *out_dn0 = h * f;
+    }
+  } else {
+    double mid = (pz + az) * 0.5;
+    if (md->kind == 2) {
+      out_grad[2] = md->n0m1 * tab_slope(md, mid) * 0.5;
+      *out_dn0 = tab_f(md, mid);
+    } else {
+      double e = exp(-mid / md->h);
+      out_grad[2] = -md->n0m1 * e / (2.0 * md->h);
+      *out_dn0 = e;
+    }
+  }
+}
+
+/* The local (source) index n(P) of the Endpoint Doppler factor, with its
+ * gradient in P and its derivative in n0m1. */
+static double source_index(const orc_medium *md, double px, double py, double pz,
+                           double out_grad[3], double *out_dn0) {
+  out_grad[0] = out_grad[1] = out_grad[2] = 0.0;
+  if (md->kind == 0) {
+    *out_dn0 = 1.0;
+    return 1.0 + md->n0m1;
+  }
+  if (md->kind == 3) {
+    double q[3] = {px, py, pz + md->re};   /* P - C */
+    double rho2 = sphere_rho2(md, px, py, pz);
+    double len = sqrt(rho2 + md->re * md->re);
+    double e = exp(-((rho2 / (len + md->re)) / md->h));
+    for (int j = 0; j < 3; ++j) out_grad[j] = -md->n0m1 * (e / md->h) * q[j] / len;
+    *out_dn0 = e;
+    return 1.0 + md->n0m1 * exp(-sphere_exponent(md, sphere_rho2(md, px, py, pz)));
+  }
+  if (md->kind == 2) {
+    out_grad[2] = md->n0m1 * tab_slope(md, pz);
+    *out_dn0 = tab_f(md, pz);
+    return 1.0 + md->n0m1 * tab_f(md, pz);
+  }
+  double e = exp(-(pz / md->h));
+  out_grad[2] = -md->n0m1 * e / md->h;
+  *out_dn0 = e;
+  return 1.0 + md->n0m1 * e;
+}
+
+/* d t / d P and d t / d n0m1 of the arrival t = T + n_eff R / c at antenna a:
+ * dR/dP = -(X - P) / R. */
 static void time_derivatives(const orc_antennas *ar, const orc_medium *md, int64_t a,
                              double px, double py, double pz, double out_dp[3], double *out_dn) {
   double dx = ar->x[a] - px, dy = ar->y[a] - py, dz = ar->z[a] - pz;
   double r = sqrt((dx * dx + dy * dy) + dz * dz);
-  double za = ar->z[a];
-  double neff, dneff_dz, dneff_dn0;
-  if (md->kind == 0) {
-    neff = 1.0 + md->n0m1;
-    dneff_dz = 0.0;
-    dneff_dn0 = 1.0;
-  } else {
-    double h = md->h, del = pz - za;
-    if (fabs(del) >= 1e-3) {
-      double ep = exp(-pz / h), ea = exp(-za / h);
-      double f = (ea - ep) / del;
-      neff = 1.0 + md->n0m1 * h * f;
-      /* d f / d zp = (ep / h) / del - (ea - ep) / del^2 */
-      dneff_dz = md->n0m1 * h * ((ep / h) / del - (ea - ep) / (del * del));
-      dneff_dn0 = h * f;
-    } else {
-      double e = exp(-((pz + za) * 0.5) / h);
-      neff = 1.0 + md->n0m1 * e;
-      dneff_dz = -md->n0m1 * e / (2.0 * h);
-      dneff_dn0 = e;
-    }
-  }
-  /* dR/dP = -(X - P) / R */
-  out_dp[0] = (neff * (-dx / r)) / ORC_C_LIGHT;
-  out_dp[1] = (neff * (-dy / r)) / ORC_C_LIGHT;
-  out_dp[2] = (neff * (-dz / r) + r * dneff_dz) / ORC_C_LIGHT;
-  *out_dn = r * dneff_dn0 / ORC_C_LIGHT;
+  double neff = md->kind == 3 ? spherical_index(md, px, py, pz, ar->x[a], ar->y[a], ar->z[a])
+                              : effective_index(md, pz, ar->z[a]);
+  double gn[3], dn0;
+  index_gradient(md, px, py, pz, ar->x[a], ar->y[a], ar->z[a], gn, &dn0);
+  out_dp[0] = (neff * (-dx / r) + r * gn[0]) / ORC_C_LIGHT;
+  out_dp[1] = (neff * (-dy / r) + r * gn[1]) / ORC_C_LIGHT;
+  out_dp[2] = (neff * (-dz / r) + r * gn[2]) / ORC_C_LIGHT;
+  *out_dn = r * dn0 / ORC_C_LIGHT;
 }
 
 typedef struct {
@@ -617,7 +694,6 @@ int orc_zhs_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_medium *
                 int n_threads) {
   if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
   if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
-  if (md->kind >= 2) return -1; /* adjoints are defined for the closed-form media */
   *g_n0m1 = 0.0;
   if (tr->n == 0) return 0;
   double *gn = (double *)calloc((size_t)tr->n, sizeof(double));
@@ -697,7 +773,8 @@ static void *ep_vjp_worker(void *arg) {
         double R = p.r;
         double r[3] = {p.dx / R, p.dy / R, p.dz / R};
         double b = (beta[0] * r[0] + beta[1] * r[1]) + beta[2] * r[2];
-        double n_src = index_at(md, pz);
+        double gsrc[3], dsrc_dn0;
+        double n_src = source_index(md, px, py, pz, gsrc, &dsrc_dn0);
         double D = 1.0 - n_src * b;
         if (D == 0.0) continue;
         double V[3] = {r[0] * b - beta[0], r[1] * b - beta[1], r[2] * b - beta[2]};
@@ -714,14 +791,9 @@ static void *ep_vjp_worker(void *arg) {
           double df = A * (gdV / (D * R) + n_src * gV * db / (D * D * R) - gV * r[j] / (D * R * R));
           gp[end][j] -= df;
         }
-        double df_dn = A * gV * b / (D * D * R);
-        if (md->kind == 0) {
-          gn += df_dn;
-        } else {
-          double e = exp(-(pz / md->h));
-          gn += df_dn * e;
-          gp[end][2] += df_dn * md->n0m1 * e * (-1.0 / md->h);
-        }
+        double df_dn = A * gV * b / (D * D * R);   /* through n_src */
+        gn += df_dn * dsrc_dn0;
+        for (int j = 0; j < 3; ++j) gp[end][j] += df_dn * gsrc[j];
       }
     }
     job->g_qw[i] = gq;
@@ -740,7 +812,6 @@ int orc_endpoint_vjp(const orc_tracks *tr, const orc_antennas *ar, const orc_med
                      double *g_n0m1, int n_threads) {
   if (!tr || !ar || !md || !grad || !g_qw || !g_p0 || !g_p1 || !g_n0m1) return -1;
   if (!(ar->dt > 0.0) || tr->n < 0 || ar->m < 0) return -1;
-  if (md->kind >= 2) return -1; /* adjoints are defined for the closed-form media */
   *g_n0m1 = 0.0;
   if (tr->n == 0) return 0;
   double *gn = (double *)calloc((size_t)tr->n, sizeof(double));

@@ -333,14 +333,28 @@ def test_zhs_vjp_weight_is_exact_linear_share(orc):
         assert grads["qw"][i] == pytest.approx(li / tr.qw[i], rel=1e-10, abs=1e-300)
 
 
-def test_zhs_vjp_matches_central_differences(orc):
+def _adjoint_medium(name):
+    from paper_2309_03717_amd.workloads import SPHERICAL_AIR, layered_air
+    return {"exponential": config(3).medium, "layered": layered_air(),
+            "spherical": SPHERICAL_AIR}[name]
+
+
+def _with_n0(md, v):
+    import dataclasses
+    return dataclasses.replace(md, n0m1=v)
+
+
+@pytest.mark.parametrize("medium", ["exponential", "layered", "spherical"])
+def test_zhs_vjp_matches_central_differences(orc, medium):
     """Positions and n0 - 1 by central differences on the forward oracle
     (Richardson-extrapolated from steps h and 2h: h = 1e-5 m, 1e-6 relative),
     skipping tracks whose shift moves a box edge across a bin edge (the loss
     has a kink there). Narrow near-Cherenkov boxes make the loss strongly
-    curved in the edge positions, hence the small steps."""
+    curved in the edge positions, hence the small steps. In the exponential,
+    tabulated and spherical-Earth media (the last with horizontal components
+    of the path-index gradient)."""
     w = config(3)
-    md = w.medium
+    md = _adjoint_medium(medium)
     rng = np.random.default_rng(9)
     tr = w.tracks(400)
     ar = w.array
@@ -389,13 +403,13 @@ def test_zhs_vjp_matches_central_differences(orc):
     for i in range(tr.n):
         ok = True
         for s in (-2 * hn, 2 * hn):
-            _, us, _ = orc.propagate(tr.take([i]), ar, Medium(md.kind, md.n0m1 + s, md.h))
+            _, us, _ = orc.propagate(tr.take([i]), ar, _with_n0(md, md.n0m1 + s))
             ok &= bool((np.floor(us[:, 0]) == np.floor(u0[:, i])).all())
         if ok:
             keep.append(i)
     sub = tr.take(keep)
     assert sub.n >= 6
-    fd = richardson(lambda v: _loss(orc, sub, ar, Medium(md.kind, v, md.h), g), md.n0m1, hn)
+    fd = richardson(lambda v: _loss(orc, sub, ar, _with_n0(md, v), g), md.n0m1, hn)
     an = orc.zhs_vjp(sub, ar, md, g)["n0m1"]
     assert an == pytest.approx(fd, rel=1e-5)
 
@@ -421,14 +435,15 @@ def test_endpoint_vjp_weight_is_exact_linear_share(orc, cfg):
     assert nonzero >= 10
 
 
-@pytest.mark.parametrize("cfg", [0, 3])
-def test_endpoint_vjp_matches_central_differences(orc, cfg):
+@pytest.mark.parametrize("cfg,medium", [(0, None), (3, None), (3, "layered"), (3, "spherical")])
+def test_endpoint_vjp_matches_central_differences(orc, cfg, medium):
     """Positions and n0 - 1 against Richardson-extrapolated central
     differences of the forward oracle (steps h and 2h; h = 1e-3 m and 1e-6
     relative), skipping shifts that move an impulse across a bin edge (the
-    loss jumps there; the adjoint holds bins fixed)."""
+    loss jumps there; the adjoint holds bins fixed); uniform, exponential,
+    tabulated and spherical-Earth media (path index and source index)."""
     w = config(cfg)
-    md, ar = w.medium, w.array
+    md, ar = (w.medium if medium is None else _adjoint_medium(medium)), w.array
     tr = w.tracks(400)
     _, u, b = orc.propagate(tr, ar, md)
     reach = np.flatnonzero(((b >= 0).any(axis=0)).any(axis=1))[:10]
@@ -461,11 +476,11 @@ def test_endpoint_vjp_matches_central_differences(orc, cfg):
     assert checked > 30
     hn = 1e-6 * md.n0m1
     keep = [i for i in range(tr.n)
-            if all((np.floor(orc.propagate(tr.take([i]), ar, Medium(md.kind, md.n0m1 + s, md.h))[1])
+            if all((np.floor(orc.propagate(tr.take([i]), ar, _with_n0(md, md.n0m1 + s))[1])
                     == np.floor(orc.propagate(tr.take([i]), ar, md)[1])).all() for s in (-2 * hn, 2 * hn))]
     sub = tr.take(keep)
     assert sub.n >= 5
-    fd = richardson(lambda v: _ep_loss(orc, sub, ar, Medium(md.kind, v, md.h), g), md.n0m1, hn)
+    fd = richardson(lambda v: _ep_loss(orc, sub, ar, _with_n0(md, v), g), md.n0m1, hn)
     an = orc.endpoint_vjp(sub, ar, md, g)["n0m1"]
     assert an == pytest.approx(fd, rel=1e-5)
 
@@ -565,14 +580,6 @@ def test_tabulated_exponential_samples_approach_closed_form(orc):
     # (n_eff - 1) R / c differs by at most 1e-6 relative
     assert np.all(np.abs((t_t - T) - (t_e - T)) <= 2e-6 * N0_AIR * (t_e - T) + 1e-18)
 
-
-def test_adjoints_reject_tabulated_media(orc):
-    w = config(3)
-    tr = w.tracks(4)
-    g = np.zeros((w.array.m, w.array.n_bins, 3))
-    for fn in (orc.zhs_vjp, orc.endpoint_vjp):
-        with pytest.raises(ValueError):
-            fn(tr, w.array, _TAB, g)
 
 
 # ----------------------------------------------------------------- spherical Earth
@@ -722,10 +729,47 @@ def test_spherical_endpoint_uses_the_height_above_the_sphere(orc):
     assert not np.allclose(e[0, 100], wrong, rtol=1e-9, atol=0)
 
 
-def test_adjoints_reject_spherical_media(orc):
-    w = config(3)
-    tr = w.tracks(4)
-    g = np.zeros((w.array.m, w.array.n_bins, 3))
-    for fn in (orc.zhs_vjp, orc.endpoint_vjp):
-        with pytest.raises(ValueError):
-            fn(tr, w.array, SPHERICAL_AIR, g)
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_spherical_adjoints_on_far_tracks(orc, formalism):
+    """Inclined shower over the spherical Earth (emission points 2-40 km out
+    along a 75-degree axis): the horizontal components of the path-index and
+    source-index gradients matter there. Central differences of the forward
+    oracle in x, y and z of both ends (Richardson, h = 1e-4 m), skipping
+    shifts that move an arrival across a bin edge."""
+    from paper_2309_03717_amd.workloads import SPHERICAL_AIR, inclined_shower
+    md = SPHERICAL_AIR
+    tr, ar = inclined_shower(300)
+    _, u, b = orc.propagate(tr, ar, md)
+    reach = np.flatnonzero(((b >= 0).any(axis=0)).any(axis=1))
+    far = reach[np.argsort(-np.abs(tr.x0[reach]))][:8]
+    tr = tr.take(far)
+    g = np.random.default_rng(31).normal(size=(ar.m, ar.n_bins, 3))
+    vjp = orc.endpoint_vjp if formalism == "endpoint" else orc.zhs_vjp
+    grads = vjp(tr, ar, md, g)
+    loss = lambda t: float(np.sum(g * orc.traces(formalism, t, ar, md)))
+
+    def richardson(f, x0, h):
+        c = lambda s: (f(x0 + s) - f(x0 - s)) / (2 * s)
+        return (4.0 * c(h) - c(2 * h)) / 3.0
+
+    h = 1e-4
+    checked = 0
+    for i in range(tr.n):
+        one = tr.take([i])
+        _, u0, _ = orc.propagate(one, ar, md)
+        scale = max(np.abs(grads["p0"][:, i]).max(), np.abs(grads["p1"][:, i]).max())
+        for end in (0, 1):
+            for c, comp in enumerate("xyz"):
+                key = f"{comp}{end}"
+                base = float(one.arrays()[key][0])
+                moved = lambda v: Tracks(**{**one.arrays(), key: np.array([v])})
+                if any((np.floor(orc.propagate(moved(base + s), ar, md)[1]) != np.floor(u0)).any()
+                       for s in (-2 * h, 2 * h)):
+                    continue
+                fd = richardson(lambda v: loss(moved(v)), base, h)
+                an = grads["p0" if end == 0 else "p1"][c, i]
+                # the loss sums 64 antennas x 8192 bins: its rounding noise
+                # over h is ~1e-6 of the track's largest gradient component
+                assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-6 * scale, (i, key, an, fd)
+                checked += 1
+    assert checked >= 20
