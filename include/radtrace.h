@@ -93,8 +93,8 @@ typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
  * with the nodes s_k and weights w_k of the rule on [0, 1] (ascending s_k,
  * sum w_k = 1; accurate to double rounding for these profiles), and h(q) =
  * rho2 / (sqrt(rho2 + R^2) + R), rho2 = (qx^2 + qy^2) + qz (qz + 2R), which is
- * |q - C| - R without cancellation. The adjoints and batches accept the
- * uniform and exponential media. */
+ * |q - C| - R without cancellation. The adjoints accept every medium; batches
+ * the uniform and exponential media. */
 typedef enum {
   RT_UNIFORM = 0,
   RT_EXPONENTIAL = 1,

@@ -2,11 +2,14 @@
 library's deposit (ZHS or Endpoint) and whose backward is the matching
 hand-written adjoint (rt_zhs_vjp, rt_endpoint_vjp). Differentiable inputs:
 per-track weights qw [n], start points p0 [3, n], end points p1 [3, n] and
-the refractivity n0 - 1 (0-d tensor); the emission times, the velocities and
-the antenna array are held fixed (and, for the Endpoint formalism, the bins
-the impulses land in).
+the refractivity n0 - 1 (0-d tensor); the emission times, the velocities, the
+antenna array and the shape of the medium (scale height, table, Earth radius)
+are held fixed (and, for the Endpoint formalism, the bins the impulses land
+in). Every medium is differentiable.
 """
 from __future__ import annotations
+
+import dataclasses
 
 import torch
 
@@ -16,9 +19,8 @@ from .workloads import Medium
 
 class RadioTraces(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium_kind, scale_height,
-                precision, k):
-        medium = Medium(medium_kind, float(n0m1.detach().cpu()), float(scale_height))
+    def forward(ctx, qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium, precision, k):
+        medium = dataclasses.replace(medium, n0m1=float(n0m1.detach().cpu()))
         plan = rt.Plan(det, medium, formalism, precision, k)
         in_dtype = torch.float64 if precision == "fp64" else torch.float32
         tracks = rt.DeviceTracks(
@@ -38,7 +40,7 @@ class RadioTraces(torch.autograd.Function):
         gq, gp0, gp1, gn = ctx.plan.vjp(ctx.tracks, grad)
         dq, d0, d1, dn = ctx.dtypes
         return (gq.to(dq), gp0.to(d0), gp1.to(d1), gn.reshape(()).to(dn),
-                None, None, None, None, None, None, None, None, None)
+                None, None, None, None, None, None, None, None)
 
 
 # kept for callers of the ZHS-only name
@@ -46,16 +48,15 @@ ZHSTraces = RadioTraces
 
 
 def radio_traces(formalism: str, qw, p0, p1, n0m1, *, t0, t1, beta, det: rt.DeviceDetector,
-                 medium_kind: str, scale_height: float = 8000.0, precision: str = "mixed",
-                 k: float = 1.0):
+                 medium_kind: str = "exponential", scale_height: float = 8000.0,
+                 medium: Medium | None = None, precision: str = "mixed", k: float = 1.0):
     """Traces [M, n_bins, 3] of the given tracks in the given formalism
-    ("zhs" or "endpoint"), differentiable in qw, p0, p1 and n0m1. The adjoints
-    are defined for the uniform and exponential media."""
-    if medium_kind not in ("uniform", "exponential"):
-        raise ValueError(f"differentiable traces take the uniform and exponential media, "
-                         f"not {medium_kind!r}")
-    return RadioTraces.apply(qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium_kind,
-                             scale_height, precision, k)
+    ("zhs" or "endpoint"), differentiable in qw, p0, p1 and n0m1. The medium is
+    ``medium`` (any kind; its own n0m1 is replaced by the n0m1 tensor) or, if
+    that is None, the uniform or exponential profile named by medium_kind."""
+    if medium is None:
+        medium = Medium(medium_kind, float(n0m1.detach().cpu()), float(scale_height))
+    return RadioTraces.apply(qw, p0, p1, n0m1, t0, t1, beta, det, formalism, medium, precision, k)
 
 
 def zhs_traces(qw, p0, p1, n0m1, **kw):

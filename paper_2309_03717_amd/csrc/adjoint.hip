@@ -13,6 +13,11 @@
 // refractivity n0 - 1 (through the path indices of the edges) are accumulated
 // per track over all antennas; beta and the emission times are held fixed.
 //
+// Every medium: in the flat ones the path index depends on the heights only
+// (its derivative is cached per antenna height); over the spherical Earth its
+// gradient in the emission point has horizontal components and is taken per
+// pair from the quadrature.
+//
 // Kernels: phi_kernel (one workgroup per antenna: prefix sums of G in double),
 // vjp_kernel (one thread per track, loop over antennas, per-track gradients
 // in registers, per-workgroup partial of the n0 - 1 gradient in fixed order)
@@ -88,34 +93,128 @@ struct VjpArgs {
   double *n0_part;      // [gridDim.x]
 };
 
-// d t / d z_P of the path index for an end at height zp with height factor
-// ep (and of n_eff itself), and d n_eff / d (n0 - 1); antenna at height za
-// with height factor ea.
-__device__ __forceinline__ void index_derivatives(double zp, double za, double ep, double ea,
+// Tabulated profile: slope of f at z (the cell tab_f interpolates in; zero
+// beyond the end nodes, where f is constant).
+__device__ __forceinline__ double tab_slope(double z, const Consts &c) {
+  const double t = (z - c.tz0) * c.tinv_dz;
+  if (!(t > 0.0) || t >= (double)(c.n_tab - 1)) return 0.0;
+  const int k = (int)floor(t);
+  return (c.tab[k + 1] - c.tab[k]) * c.tinv_dz;
+}
+
+// The per-height path factor the flat media's path index takes: exp(-z/h)
+// (exponential), the integral F (tabulated); 0 otherwise. MED: the medium
+// kind (0 uniform, 1 exponential, 2 tabulated, 3 spherical) at compile time.
+template <int MED>
+__device__ __forceinline__ double path_factor_flat(double z, const Consts &c) {
+  return MED == 1 ? height_factor(z, c) : MED == 2 ? tab_F(z, c) : 0.0;
+}
+
+// Path index of an end at height zp towards an antenna at height za in the
+// flat media (0 uniform, 1 exponential, 2 tabulated), with its derivative in
+// zp (dn_dz) and in n0 - 1 (dn_dn0). pp, pa: the path factors of the two
+// heights (exponential: exp(-z/h); tabulated: the integral F). The index is
+// the one the forward timing uses, so the bins are the forward's.
+template <int MED>
+__device__ __forceinline__ void index_derivatives(double zp, double za, double pp, double pa,
                                                   const Consts &c, double &neff, double &dn_dz,
                                                   double &dn_dn0) {
-  if (c.medium == 0) {
+  if (MED == 0) {
     neff = c.n_uniform;
     dn_dz = 0.0;
     dn_dn0 = 1.0;
     return;
   }
-  neff = path_index(zp, za, ep, ea, c);
-  double dz = zp - za;
+  neff = path_index_m<MED>(zp, za, pp, pa, c);
+  const double dz = zp - za;
   if (fabs(dz) >= 1e-3) {
-    double f = (ea - ep) / dz;
-    dn_dn0 = c.h * f;
-    // d f / d zp = (ep / h) / dz - f / dz
-    dn_dz = c.n0h * ((ep / c.h) / dz - f / dz);
-  } else {
-    double e = exp(-(((zp + za) * 0.5) / c.h));
-    dn_dn0 = e;
-    dn_dz = -c.n0m1 * e / (2.0 * c.h);
+    if (MED == 2) {   // n = 1 + n0m1 (F(zp) - F(za)) / dz, F' = f
+      const double fbar = (pp - pa) / dz;
+      dn_dn0 = fbar;
+      dn_dz = c.n0m1 * (tab_f(zp, c) - fbar) / dz;
+    } else {               // n = 1 + n0m1 h (ea - ep) / dz
+      const double f = (pa - pp) / dz;
+      dn_dn0 = c.h * f;
+      // d f / d zp = (ep / h) / dz - f / dz
+      dn_dz = c.n0h * ((pp / c.h) / dz - f / dz);
+    }
+  } else {                 // the local index at the mid height
+    const double mid = (zp + za) * 0.5;
+    if (MED == 2) {
+      dn_dn0 = tab_f(mid, c);
+      dn_dz = c.n0m1 * tab_slope(mid, c) * 0.5;
+    } else {
+      const double e = exp(-(mid / c.h));
+      dn_dn0 = e;
+      dn_dz = -c.n0m1 * e / (2.0 * c.h);
+    }
   }
 }
 
-template <int P>
-__global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
+// Spherical Earth: the gradient of the path index with respect to the
+// emission point P (all three components) and its derivative in n0 - 1, from
+// the quadrature: n = 1 + n0m1 S, S = sum_k w_k exp(-H(q_k) / h),
+// q_k = P + s_k (X - P), dH/dq = (q - C) / |q - C|, dq_k / dP = 1 - s_k.
+__device__ __forceinline__ void sph_index_gradient(double px, double py, double pz, double ax,
+                                                   double ay, double az, const Consts &c,
+                                                   double grad[3], double &dn_dn0) {
+  double sum = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < kGl; ++k) {
+    const double sk = c.gl_s[k];
+    const double qx = px + sk * (ax - px), qy = py + sk * (ay - py), qz = pz + sk * (az - pz);
+    const double rho2 = (qx * qx + qy * qy) + qz * (qz + c.re_twice);
+    const double len = sqrt(rho2 + c.re2);   // |q - C|
+    const double we = c.gl_w[k] * exp(-sph_exponent(rho2, c));
+    sum += we;
+    const double f = we * (1.0 - sk) / len;
+    g0 += f * qx;
+    g1 += f * qy;
+    g2 += f * (qz + c.re);
+  }
+  const double sc = -c.n0m1 / c.h;
+  grad[0] = sc * g0;
+  grad[1] = sc * g1;
+  grad[2] = sc * g2;
+  dn_dn0 = sum;
+}
+
+// The local (source) index of the Endpoint Doppler factor at P, its gradient
+// in P and its derivative in n0 - 1 (the same value as the forward's
+// 1 + n0m1 * local factor).
+template <int MED>
+__device__ __forceinline__ double source_index(double px, double py, double pz, const Consts &c,
+                                               double grad[3], double &dn_dn0) {
+  grad[0] = grad[1] = grad[2] = 0.0;
+  if (MED == 0) {
+    dn_dn0 = 1.0;
+    return c.n_uniform;
+  }
+  double e;
+  if (MED == 3) {
+    const double rho2 = (px * px + py * py) + pz * (pz + c.re_twice);
+    const double len = sqrt(rho2 + c.re2);
+    e = exp(-sph_exponent(rho2, c));
+    const double sc = -c.n0m1 * (e / c.h) / len;
+    grad[0] = sc * px;
+    grad[1] = sc * py;
+    grad[2] = sc * (pz + c.re);
+  } else if (MED == 2) {
+    e = tab_f(pz, c);
+    grad[2] = c.n0m1 * tab_slope(pz, c);
+  } else {
+    e = height_factor(pz, c);
+    grad[2] = -c.n0m1 * e / c.h;
+  }
+  dn_dn0 = e;
+  return fma(c.n0m1, e, 1.0);
+}
+
+// MED: the medium kind at compile time, so that each kernel keeps only its
+// own registers.
+template <int P, int MED>
+__global__ void __launch_bounds__(kVjpBlock) __attribute__((amdgpu_waves_per_eu(3)))
+vjp_kernel(VjpArgs v) {
   using In = typename std::conditional<P == 0, double, float>::type;
   const Consts &c = v.c;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -130,20 +229,25 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
               isfinite(x1) && isfinite(y1) && isfinite(z1) && isfinite(t1) && isfinite(b[0]) &&
               isfinite(b[1]) && isfinite(b[2]);
     double gq = 0.0, gp0[3] = {0.0, 0.0, 0.0}, gp1[3] = {0.0, 0.0, 0.0};
-    const double e0 = c.medium == 1 ? height_factor(z0, c) : 0.0;
-    const double e1 = c.medium == 1 ? height_factor(z1, c) : 0.0;
+    const double e0 = path_factor_flat<MED>(z0, c), e1 = path_factor_flat<MED>(z1, c);
     const double mx = (x0 + x1) * 0.5, my = (y0 + y1) * 0.5, mz = (z0 + z1) * 0.5;
     const double kdt = c.k * (t1 - t0);   // I = kdt * qw * beta_perp / R_m
-    // path indices and their derivatives depend on the antenna height only:
-    // recomputed when it changes (a uniform test: every lane sees the same
-    // antenna)
-    double z_prev = __builtin_nan(""), ne0 = 0, dnz0 = 0, dnn0 = 0, ne1 = 0, dnz1 = 0, dnn1 = 0;
+    // in the flat media the path indices and their derivatives depend on the
+    // antenna height only: recomputed when it changes (a uniform test: every
+    // lane sees the same antenna); over the spherical Earth, per pair
+    double z_prev = __builtin_nan(""), ne0 = 0, dnn0 = 0, ne1 = 0, dnn1 = 0;
+    double gn0[3] = {0.0, 0.0, 0.0}, gn1[3] = {0.0, 0.0, 0.0};
     for (int64_t a = 0; ok && a < v.an.m; ++a) {
       const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
-      if (!(az == z_prev)) {
-        const double ea = c.medium == 1 ? height_factor(az, c) : 0.0;
-        index_derivatives(z0, az, e0, ea, c, ne0, dnz0, dnn0);
-        index_derivatives(z1, az, e1, ea, c, ne1, dnz1, dnn1);
+      if (MED == 3) {
+        ne0 = sph_path_index(x0, y0, z0, ax, ay, az, c);
+        ne1 = sph_path_index(x1, y1, z1, ax, ay, az, c);
+        sph_index_gradient(x0, y0, z0, ax, ay, az, c, gn0, dnn0);
+        sph_index_gradient(x1, y1, z1, ax, ay, az, c, gn1, dnn1);
+      } else if (!(az == z_prev)) {
+        const double ea = path_factor_flat<MED>(az, c);
+        index_derivatives<MED>(z0, az, e0, ea, c, ne0, gn0[2], dnn0);
+        index_derivatives<MED>(z1, az, e1, ea, c, ne1, gn1[2], dnn1);
         z_prev = az;
       }
       double d0x, d0y, d0z, r0, r02, d1x, d1y, d1z, r1, r12;
@@ -196,14 +300,14 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
       // box edges: u = (T + n_eff R / c - tau) / dt
       const double dl_ds = (start_lo ? dl_dlo : dl_dhi) * c.inv_dt * c.inv_c;
       const double dl_de = (start_lo ? dl_dhi : dl_dlo) * c.inv_dt * c.inv_c;
-      // d (n_eff R) / d P = -n_eff d / R + R dn_eff/dz e_z
+      // d (n_eff R) / d P = -n_eff d / R + R grad n_eff
       const double n0r = ne0 / r0, n1r = ne1 / r1;
-      gp0[0] += dl_ds * (-n0r * d0x);
-      gp0[1] += dl_ds * (-n0r * d0y);
-      gp0[2] += dl_ds * (-n0r * d0z + r0 * dnz0);
-      gp1[0] += dl_de * (-n1r * d1x);
-      gp1[1] += dl_de * (-n1r * d1y);
-      gp1[2] += dl_de * (-n1r * d1z + r1 * dnz1);
+      gp0[0] += dl_ds * (-n0r * d0x + r0 * gn0[0]);
+      gp0[1] += dl_ds * (-n0r * d0y + r0 * gn0[1]);
+      gp0[2] += dl_ds * (-n0r * d0z + r0 * gn0[2]);
+      gp1[0] += dl_de * (-n1r * d1x + r1 * gn1[0]);
+      gp1[1] += dl_de * (-n1r * d1y + r1 * gn1[1]);
+      gp1[2] += dl_de * (-n1r * d1z + r1 * gn1[2]);
       gn_local += dl_ds * r0 * dnn0 + dl_de * r1 * dnn1;
     }
     v.g_qw[i] = gq;
@@ -231,7 +335,7 @@ __global__ void __launch_bounds__(kVjpBlock) vjp_kernel(VjpArgs v) {
 //   dq/dd_j = beta_j / R^2 - 2 (beta.d) d_j / R^4,  dnum/dd_j = d_j / R - n_src beta_j,
 //   df/dn_src = c (g.W) (beta.d) / num^2,
 // and dP = -dd; n_src = 1 + (n0 - 1) e(z_P) adds the height derivative of e.
-template <int P>
+template <int P, int MED>
 __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
   using In = typename std::conditional<P == 0, double, float>::type;
   const Consts &c = v.c;
@@ -247,19 +351,23 @@ __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
     for (int e = 0; e < 2; ++e)
       for (int k = 0; k < 4; ++k) ok = ok && isfinite(pos[e][k]);
     double gq = 0.0, gp[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
-    double hf[2] = {0.0, 0.0}, ns[2] = {c.n_uniform, c.n_uniform};
-    if (c.medium == 1)
-      for (int e = 0; e < 2; ++e) {
-        hf[e] = height_factor(pos[e][2], c);
-        ns[e] = fma(c.n0m1, hf[e], 1.0);
-      }
+    // source index n(P) of each end with its gradient and n0 - 1 derivative;
+    // the path factors of the flat media for the (bin-deciding) path index
+    double ns[2], gsrc[2][3], dsrc[2], pf[2];
+    for (int e = 0; e < 2; ++e) {
+      ns[e] = source_index<MED>(pos[e][0], pos[e][1], pos[e][2], c, gsrc[e], dsrc[e]);
+      pf[e] = path_factor_flat<MED>(pos[e][2], c);
+    }
     const double kdt = c.k * c.inv_dt;
     double z_prev = __builtin_nan(""), nes[2] = {c.n_uniform, c.n_uniform};
     for (int64_t a = 0; ok && a < v.an.m; ++a) {
       const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
-      if (c.medium == 1 && !(az == z_prev)) {   // uniform test: one antenna per step
-        const double ea = height_factor(az, c);
-        for (int e = 0; e < 2; ++e) nes[e] = path_index(pos[e][2], az, hf[e], ea, c);
+      if (MED == 3) {
+        for (int e = 0; e < 2; ++e)
+          nes[e] = sph_path_index(pos[e][0], pos[e][1], pos[e][2], ax, ay, az, c);
+      } else if ((MED == 1 || MED == 2) && !(az == z_prev)) {   // uniform test
+        const double pa = path_factor_flat<MED>(az, c);
+        for (int e = 0; e < 2; ++e) nes[e] = path_index_m<MED>(pos[e][2], az, pf[e], pa, c);
         z_prev = az;
       }
       const In *ga = (const In *)v.grad + (size_t)a * c.n_bins * 3;
@@ -290,12 +398,8 @@ __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
           gp[e][k] -= a1 * (g[k] * q + gd * dq) - a2 * dnum;
         }
         const double dfn = a2 * bd;   // d f / d n_src
-        if (c.medium == 1) {
-          gn_local += dfn * hf[e];
-          gp[e][2] -= dfn * c.n0m1 * hf[e] / c.h;
-        } else {
-          gn_local += dfn;
-        }
+        gn_local += dfn * dsrc[e];
+        for (int k = 0; k < 3; ++k) gp[e][k] += dfn * gsrc[e][k];
       }
     }
     v.g_qw[i] = gq;
@@ -329,15 +433,47 @@ __global__ void __launch_bounds__(256) n0_sum_kernel(const double *part, int64_t
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// ZHS: [Phi tables][per-workgroup n0 partials]; Endpoint: the partials only.
+// ZHS: [Phi tables][per-workgroup n0 partials][F table of a tabulated
+// medium]; Endpoint: the partials and the F table.
 static size_t phi_bytes(const rt_plan &p) {
   if (p.formalism != RT_ZHS) return 0;
   return align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double));
 }
 
-size_t vjp_workspace_bytes(const rt_plan &p, int64_t n) {
+using VjpKernel = void (*)(VjpArgs);
+
+template <int F, int P>
+static VjpKernel vjp_kernel_med(int med) {
+  if (F == RT_ZHS) {
+    switch (med) {
+      case 0: return vjp_kernel<P, 0>;
+      case 1: return vjp_kernel<P, 1>;
+      case 2: return vjp_kernel<P, 2>;
+      default: return vjp_kernel<P, 3>;
+    }
+  }
+  switch (med) {
+    case 0: return ep_vjp_kernel<P, 0>;
+    case 1: return ep_vjp_kernel<P, 1>;
+    case 2: return ep_vjp_kernel<P, 2>;
+    default: return ep_vjp_kernel<P, 3>;
+  }
+}
+
+// kind = formalism * 8 + precision * 4 + medium kind
+static VjpKernel vjp_kernel_for(int kind) {
+  const int med = kind & 3, prec = (kind >> 2) & 1, f = kind >> 3;
+  if (f == RT_ZHS) return prec ? vjp_kernel_med<RT_ZHS, 1>(med) : vjp_kernel_med<RT_ZHS, 0>(med);
+  return prec ? vjp_kernel_med<RT_ENDPOINT, 1>(med) : vjp_kernel_med<RT_ENDPOINT, 0>(med);
+}
+
+static size_t part_bytes(int64_t n) {
   const int64_t blocks = (n + kVjpBlock - 1) / kVjpBlock;
-  return phi_bytes(p) + align256((size_t)std::max<int64_t>(blocks, 1) * sizeof(double));
+  return align256((size_t)std::max<int64_t>(blocks, 1) * sizeof(double));
+}
+
+size_t vjp_workspace_bytes(const rt_plan &p, int64_t n) {
+  return phi_bytes(p) + part_bytes(n) + table_bytes(p);
 }
 
 hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, double *g_qw,
@@ -346,6 +482,12 @@ hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, do
   char *ws = reinterpret_cast<char *>(workspace);
   double *phi = reinterpret_cast<double *>(ws);
   double *part = reinterpret_cast<double *>(ws + phi_bytes(p));
+  Consts c = p.c;
+  if (p.med.kind == RT_TABULATED) {
+    double *cells = reinterpret_cast<double *>(ws + phi_bytes(p) + part_bytes(t.n));
+    launch_tab_cells(p, cells, stream);
+    c.tabF = cells;
+  }
   const unsigned m = (unsigned)p.det.n_antennas;
   if (p.formalism == RT_ZHS) {
     if (p.precision == RT_FP64)
@@ -356,7 +498,7 @@ hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, do
   VjpArgs v;
   v.tr = track_ptrs(t);
   v.an = ant_ptrs(p.det);
-  v.c = p.c;
+  v.c = c;
   v.grad = grad;
   v.phi = phi;
   v.g_qw = g_qw;
@@ -364,17 +506,8 @@ hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, do
   v.g_p1 = g_p1;
   v.n0_part = part;
   const int64_t blocks = (t.n + kVjpBlock - 1) / kVjpBlock;
-  if (p.formalism == RT_ZHS) {
-    if (p.precision == RT_FP64)
-      vjp_kernel<0><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
-    else
-      vjp_kernel<1><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
-  } else {
-    if (p.precision == RT_FP64)
-      ep_vjp_kernel<0><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
-    else
-      ep_vjp_kernel<1><<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
-  }
+  const int kind = p.formalism * 8 + p.precision * 4 + p.med.kind;
+  vjp_kernel_for(kind)<<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
   n0_sum_kernel<<<1, 256, 0, stream>>>(part, blocks, g_n0);
   return hipGetLastError();
 }

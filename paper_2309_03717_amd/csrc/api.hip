@@ -303,8 +303,6 @@ int rt_zhs_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_traces, 
                size_t workspace_bytes, void *stream) {
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ZHS) return fail(RT_E_INVALID, "rt_zhs_vjp needs an RT_ZHS plan");
-  if (plan->med.kind == RT_TABULATED || plan->med.kind == RT_SPHERICAL)
-    return fail(RT_E_UNSUPPORTED, "the adjoints take the uniform and exponential media");
   return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
                   workspace_bytes, stream);
 }
@@ -315,8 +313,6 @@ int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
   if (!plan) return fail(RT_E_INVALID, "plan is NULL");
   if (plan->formalism != RT_ENDPOINT)
     return fail(RT_E_INVALID, "rt_endpoint_vjp needs an RT_ENDPOINT plan");
-  if (plan->med.kind == RT_TABULATED || plan->med.kind == RT_SPHERICAL)
-    return fail(RT_E_UNSUPPORTED, "the adjoints take the uniform and exponential media");
   return vjp_call(plan, tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1, workspace,
                   workspace_bytes, stream);
 }

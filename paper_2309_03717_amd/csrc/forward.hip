@@ -179,7 +179,7 @@ size_t prep_bytes(const rt_plan &, int64_t n) {
   return align256((size_t)wave_blocks(n) * kRec * 64 * sizeof(double));
 }
 
-static size_t table_bytes(const rt_plan &p) {
+size_t table_bytes(const rt_plan &p) {
   return p.med.kind == RT_TABULATED ? align256((size_t)p.med.n_table * sizeof(double)) : 0;
 }
 
@@ -193,6 +193,10 @@ __global__ void tab_cells_kernel(const double *f, int n, double dz, double *cell
     acc += (0.5 * dz) * (f[j - 1] + f[j]);
     cells[j] = acc;
   }
+}
+
+void launch_tab_cells(const rt_plan &p, double *cells, hipStream_t stream) {
+  tab_cells_kernel<<<1, 64, 0, stream>>>(p.c.tab, p.c.n_tab, p.c.tdz, cells);
 }
 
 Tiling choose_tiling(const rt_plan &p, int64_t n) {
@@ -306,7 +310,7 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
   Consts c = p.c;
   if (p.med.kind == RT_TABULATED) {
     double *cells = reinterpret_cast<double *>(ws + workspace_bytes(p, t.n) - table_bytes(p));
-    tab_cells_kernel<<<1, 64, 0, stream>>>(c.tab, c.n_tab, c.tdz, cells);
+    launch_tab_cells(p, cells, stream);
     c.tabF = cells;
   }
   PrepArgs pa;

@@ -58,6 +58,12 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
                           hipStream_t stream);
 // ZHS vector-Jacobian product (adjoint.hip).
 size_t vjp_workspace_bytes(const rt_plan &p, int64_t n);
+
+// Tabulated medium: bytes of the cumulative table F at the nodes (0 for the
+// other media), and the one-thread kernel that writes it (the summation
+// order every lookup relies on).
+size_t table_bytes(const rt_plan &p);
+void launch_tab_cells(const rt_plan &p, double *cells, hipStream_t stream);
 hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, double *g_qw,
                       double *g_p0, double *g_p1, double *g_n0, void *workspace,
                       hipStream_t stream);

@@ -243,11 +243,3 @@ def test_plan_binding_passes_every_medium_field(rt, medium):
     with pytest.raises(rt.RadtraceError) as e:
         rt.Plan(det, bad, "zhs", "mixed")
     assert e.value.status == rt.RT_E_INVALID
-
-
-def test_differentiable_traces_reject_media_without_adjoint():
-    from paper_2309_03717_amd import autograd
-    for kind in ("tabulated", "spherical"):
-        with pytest.raises(ValueError, match="uniform and exponential"):
-            autograd.radio_traces("zhs", None, None, None, None, t0=None, t1=None, beta=None,
-                                  det=None, medium_kind=kind)

@@ -285,3 +285,64 @@ def test_endpoint_autograd_workflow(rt, orc):
     assert loss.item() > 0
     for k, v in errs.items():
         assert v <= EP_BOUND, (k, v)
+
+
+# ----------------------------------------------------------------- heavier media
+def heavier_case(which, n):
+    """(tracks, array, medium) for the adjoints in the tabulated and
+    spherical media: the 8 x 8 grid with antennas at eight heights (so the
+    per-height derivative cache changes), or the inclined shower over the
+    14-km grid (horizontal gradient components of the spherical index)."""
+    w = W.config(3)
+    if which == "inclined":
+        tr, arr = W.inclined_shower(n)
+        return tr, arr, W.SPHERICAL_AIR
+    md = W.layered_air() if which == "layered" else W.SPHERICAL_AIR
+    a = w.array
+    z = (np.arange(a.m) % 8) * 10.0
+    return w.tracks(n), W.make_array(a.x, a.y, z, md, a.dt, a.n_bins), md
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("which", ["layered", "spherical", "inclined"])
+def test_vjp_heavier_media_match_oracle(rt, orc, which, precision):
+    tr, arr, md = heavier_case(which, 6000 if which == "inclined" else 20_000)
+    grad = np.random.default_rng(41).normal(size=(arr.m, arr.n_bins, 3))
+    if precision == "mixed":
+        grad = grad.astype(np.float32)
+    tr_ref = tr.to_mixed().widened() if precision == "mixed" else tr
+    for f, gpu_fn, orc_fn, bound in (("zhs", gpu_vjp, orc.zhs_vjp, 1e-9),
+                                     ("endpoint", gpu_ep_vjp, orc.endpoint_vjp, EP_BOUND)):
+        gq, gp0, gp1, gn = gpu_fn(rt, tr, arr, md, grad, precision)
+        ref = orc_fn(tr_ref, arr, md, grad.astype(np.float64), n_threads=8)
+        errs = {"qw": rel(gq, ref["qw"]), "p0": rel(gp0, ref["p0"]), "p1": rel(gp1, ref["p1"]),
+                "n0m1": rel(gn[0], ref["n0m1"])}
+        print(f, which, precision, {k: f"{v:.2e}" for k, v in errs.items()})
+        assert np.abs(ref["qw"]).max() > 0
+        for k, v in errs.items():
+            assert v <= bound, (f, k, v)
+
+
+def test_autograd_with_a_spherical_medium(rt, orc):
+    """The autograd Function takes a whole medium (here the spherical Earth):
+    its gradients equal the oracle's adjoint of the same loss."""
+    import torch
+    from paper_2309_03717_amd import autograd
+    tr, arr, md = heavier_case("inclined", 2000)
+    det = rt.DeviceDetector.from_array(arr)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+    qw = dev(tr.qw).requires_grad_()
+    p0 = dev(np.stack([tr.x0, tr.y0, tr.z0])).requires_grad_()
+    p1 = dev(np.stack([tr.x1, tr.y1, tr.z1])).requires_grad_()
+    n0 = torch.tensor(md.n0m1, dtype=torch.float64, device="cuda", requires_grad=True)
+    beta = dev(np.stack([tr.bx, tr.by, tr.bz]))
+    g = np.random.default_rng(43).normal(size=(arr.m, arr.n_bins, 3))
+    out = autograd.zhs_traces(qw, p0, p1, n0, t0=dev(tr.t0), t1=dev(tr.t1), beta=beta, det=det,
+                              medium=md, precision="fp64")
+    (out * dev(g)).sum().backward()
+    ref = orc.zhs_vjp(tr, arr, md, g, n_threads=8)
+    errs = {"qw": rel(qw.grad.cpu().numpy(), ref["qw"]), "p0": rel(p0.grad.cpu().numpy(), ref["p0"]),
+            "p1": rel(p1.grad.cpu().numpy(), ref["p1"]), "n0m1": rel(n0.grad.item(), ref["n0m1"])}
+    print("autograd spherical", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-9, (k, v)

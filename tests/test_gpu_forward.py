@@ -309,17 +309,11 @@ def test_tabulated_medium_traces(rt, orc, formalism, precision):
     assert err.max() <= (FP64_BOUND if precision == "fp64" else MIXED_BOUND)
 
 
-def test_tabulated_medium_rejected_by_adjoint_and_batch(rt):
-    import torch
+def test_tabulated_medium_rejected_by_batch(rt):
     md = W.layered_air()
     arr = tilted_star(md)
     tr = W.config(1).tracks(100)
     det = rt.DeviceDetector.from_array(arr)
-    plan = rt.Plan(det, md, "zhs", "fp64")
-    g = torch.zeros((arr.m, arr.n_bins, 3), dtype=torch.float64, device="cuda")
-    with pytest.raises(rt.RadtraceError) as e:
-        plan.vjp(rt.DeviceTracks.from_tracks(tr), g)
-    assert e.value.status == rt.RT_E_UNSUPPORTED
     with pytest.raises(rt.RadtraceError) as e:
         rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
     assert e.value.status == rt.RT_E_UNSUPPORTED
@@ -388,16 +382,10 @@ def test_spherical_tilings(rt, orc, formalism, precision):
                                        * np.abs(base).max(), err_msg=str(tl))
 
 
-def test_spherical_medium_rejected_by_adjoint_and_batch(rt):
-    import torch
+def test_spherical_medium_rejected_by_batch(rt):
     md = W.SPHERICAL_AIR
     tr, arr = spherical_case("star", 100)
     det = rt.DeviceDetector.from_array(arr)
-    plan = rt.Plan(det, md, "endpoint", "fp64")
-    g = torch.zeros((arr.m, arr.n_bins, 3), dtype=torch.float64, device="cuda")
-    with pytest.raises(rt.RadtraceError) as e:
-        plan.vjp(rt.DeviceTracks.from_tracks(tr), g)
-    assert e.value.status == rt.RT_E_UNSUPPORTED
     with pytest.raises(rt.RadtraceError) as e:
         rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
     assert e.value.status == rt.RT_E_UNSUPPORTED
