@@ -404,11 +404,12 @@ def cpu_baseline_adjoint(workload, n_sample, grad):
 
 def bench_oracle(args):
     """The FP64 oracle alone on the host (no GPU): the grid workload's first
-    args.cpu_sample tracks x all 4096 antennas, both formalisms, at one thread
-    and at every host thread (at most 16), the latter also with the antenna
+    args.cpu_sample tracks x all 4096 antennas, both formalisms, at 1, 2, 4,
+    8, 16 and all host threads (at most 16), the latter also with the antenna
     bunch sizes {1, 4, 16, 64} (the paper's unit of work per thread) beside
-    the default ceil(M / threads). Reported for context: the oracle is the
-    reference, not a tuned CPU code."""
+    the default ceil(M / threads); then the whole 16-antenna, star and
+    differentiable workloads at all host threads. Reported for context: the
+    oracle is the reference, not a tuned CPU code."""
     import oracle
     from paper_2309_03717_amd import workloads as W
     oracle._load()
@@ -421,7 +422,9 @@ def bench_oracle(args):
     tr = w.tracks(args.cpu_sample).to_mixed().widened()
     pairs = tr.n * w.array.m
     runs = []
-    for threads, bunch in [(1, 0), (cores, 0), (cores, 1), (cores, 4), (cores, 16), (cores, 64)]:
+    sweep = sorted({1, 2, 4, 8, 16} & set(range(1, cores + 1)) | {cores})
+    plan = [(t, 0) for t in sweep] + [(cores, b) for b in (1, 4, 16, 64)]
+    for threads, bunch in plan:
         secs = {}
         for f in ("endpoint", "zhs"):
             t0 = time.perf_counter()
@@ -431,14 +434,30 @@ def bench_oracle(args):
         runs.append({"threads": threads, "bunch": bunch or -(-w.array.m // threads),
                      "pairs_per_s": rate, "seconds": {k: round(v, 3) for k, v in secs.items()}})
         log(f"oracle {threads} threads, bunch {runs[-1]['bunch']}: {rate / 1e6:.1f} M pairs/s")
+    # the whole small workloads at every host thread (default bunches)
+    whole = {}
+    for k in (0, 1, 3):
+        wk = W.config(k)
+        tk = wk.tracks(mixed=True).widened()
+        secs = {}
+        for f in ("endpoint", "zhs"):
+            t0 = time.perf_counter()
+            oracle.traces(f, tk, wk.array, wk.medium, k=1.0, n_threads=cores)
+            secs[f] = time.perf_counter() - t0
+        whole[wk.name] = {"pairs": tk.n * wk.array.m,
+                          "pairs_per_s": 2 * tk.n * wk.array.m / (secs["endpoint"] + secs["zhs"]),
+                          "seconds": {f: round(v, 3) for f, v in secs.items()}}
+        log(f"oracle {wk.name}: {whole[wk.name]['pairs_per_s'] / 1e6:.1f} M pairs/s")
     best = max(r["pairs_per_s"] for r in runs)
+    one = next(r for r in runs if r["threads"] == 1 and r["bunch"] == w.array.m)
+    allt = next(r for r in runs if r["threads"] == cores and r["bunch"] == -(-w.array.m // cores))
     print(json.dumps({"metric": "oracle antenna-track pairs/sec (Endpoint, ZHS), host CPU",
                       "value": best, "unit": "pairs/s", "n_gpus": 0, "steps": 1, "warmup": 0,
                       "higher_is_better": True, "dtype": "f64", "data": "synthetic",
                       "config": {"workload": f"{w.name}[{tr.n}]", "n_antennas": w.array.m,
                                  "host_threads": cores},
-                      "speedup_all_threads": round(runs[1]["pairs_per_s"] / runs[0]["pairs_per_s"], 2),
-                      "runs": runs}), flush=True)
+                      "speedup_all_threads": round(allt["pairs_per_s"] / one["pairs_per_s"], 2),
+                      "runs": runs, "whole_workloads": whole}), flush=True)
 
 
 def bench_copy(args):
@@ -611,6 +630,8 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": None if traffic is None else round(traffic),
                 "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_rate_GBps": None if traffic is None else
+                round(traffic / (per[dom]["kernel_ms_avg"] / 1e3) / 1e9, 1),
                 "kernel": f"deposit_kernel<{dom},mixed,{medium.kind}>",
                 "kernel_ms_avg": round(per[dom]["kernel_ms_avg"], 3),
                 "ops_per_pair": per[dom]["ops_per_pair"],
