@@ -5,6 +5,7 @@
 #include <new>
 #include <string>
 
+#include "rt_deposit.h"   // kMergeThreads
 #include "rt_internal.h"
 
 static thread_local std::string g_last_error;
@@ -42,6 +43,8 @@ int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, 
                    double k) {
   if (!det || !med) return fail(RT_E_INVALID, "detector or medium is NULL");
   if (det->n_antennas < 1) return fail(RT_E_INVALID, "detector needs at least one antenna");
+  if (det->n_antennas > INT32_MAX)
+    return fail(RT_E_UNSUPPORTED, "at most 2^31 - 1 antennas per detector");
   if (!det->x || !det->y || !det->z || !det->t_start)
     return fail(RT_E_INVALID, "an antenna array pointer is NULL");
   if (!(det->dt > 0.0) || !is_finite(det->dt)) return fail(RT_E_INVALID, "dt must be finite and > 0");
@@ -276,6 +279,20 @@ int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *wo
   if (!traces) return fail(RT_E_INVALID, "traces is NULL");
   if (tracks->n >= ((int64_t)1 << 31))
     return fail(RT_E_UNSUPPORTED, "at most 2^31 - 1 tracks per call; stream larger inputs in chunks");
+  {
+    // every launch must fit the hardware grid (fewer than 2^32 threads, int
+    // workgroup indices): the deposit of a pass has tiles x segments x splits
+    // workgroups, the merge antennas x segments
+    const rt::Tiling tl = rt::choose_tiling(*plan, tracks->n);
+    const int64_t deposit = (int64_t)tl.n_atiles * tl.n_segs * tl.splits;
+    const int64_t merge = plan->det.n_antennas * tl.n_segs;
+    const int64_t limit = (int64_t)UINT32_MAX;
+    if (deposit * tl.block > limit || merge * rt::kMergeThreads > limit)
+      return fail(RT_E_UNSUPPORTED,
+                  "the array needs " + std::to_string(deposit) + " deposit workgroups of " +
+                      std::to_string(tl.block) + " threads per pass: split the antennas over "
+                      "several plans (or set fewer track splits)");
+  }
   size_t need = rt::workspace_bytes(*plan, tracks->n);
   if (!workspace || workspace_bytes < need)
     return fail(RT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes, got " +
@@ -327,6 +344,8 @@ static int vjp_call(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
     return fail(RT_E_INVALID, "a per-track gradient pointer is NULL");
   if (tracks->n >= ((int64_t)1 << 31) - 1024)
     return fail(RT_E_UNSUPPORTED, "at most 2^31 - 1025 tracks per call");
+  if (plan->det.n_antennas * 256 > (int64_t)UINT32_MAX)   // one 256-thread phi workgroup each
+    return fail(RT_E_UNSUPPORTED, "the adjoints take at most 16,777,215 antennas per plan");
   size_t need = rt::vjp_workspace_bytes(*plan, tracks->n);
   if (!workspace || workspace_bytes < need)
     return fail(RT_E_WORKSPACE, "workspace needs " + std::to_string(need) + " bytes");

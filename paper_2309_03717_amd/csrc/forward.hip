@@ -73,8 +73,7 @@ struct DepositArgs {
 };
 
 // F: 0 Endpoint, 1 ZHS.  P: 0 FP64, 1 mixed.  MED: 0 uniform, 1 exponential,
-// 2 tabulated.
-// AT: antennas per tile.
+// 2 tabulated, 3 spherical Earth.  AT: antennas per tile.
 template <int F, int P, int MED, int AT>
 __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];

@@ -243,3 +243,13 @@ def test_plan_binding_passes_every_medium_field(rt, medium):
     with pytest.raises(rt.RadtraceError) as e:
         rt.Plan(det, bad, "zhs", "mixed")
     assert e.value.status == rt.RT_E_INVALID
+
+
+def test_plan_create_rejects_more_than_int32_antennas(rt):
+    det, keep = _detector(rt)
+    det.n_antennas = 2 ** 31
+    med = rt.rt_medium(rt.RT_UNIFORM, 2.92e-4, 8000.0)
+    handle = C.c_void_p()
+    st = rt._lib.rt_plan_create(C.byref(handle), C.byref(det), C.byref(med), rt.RT_ZHS,
+                                rt.RT_MIXED, 1.0)
+    assert st == rt.RT_E_UNSUPPORTED and "antennas" in rt.rt_last_error()

@@ -246,6 +246,26 @@ def test_empty_and_out_of_window_and_nonfinite(rt, orc):
         assert rel_l2(gpu, ref).max() <= FP64_BOUND
 
 
+def test_oversized_launch_grid_is_rejected(rt):
+    """Five million antennas with 2^20 tracks need more deposit workgroups
+    per pass than one launch can hold: the call returns RT_E_UNSUPPORTED
+    before any launch (and before sizing the workspace)."""
+    import ctypes as C
+    import torch
+    m = 5_000_000
+    z = torch.zeros(m, dtype=torch.float64, device="cuda")
+    det = rt.DeviceDetector(z, z, z, z, 1e-10, 64)
+    plan = rt.Plan(det, W.UNIFORM_AIR, "zhs", "mixed")
+    tr = W.config(1).tracks(1 << 20).to_mixed()
+    dtr = rt.DeviceTracks.from_tracks(tr)
+    small = torch.zeros(1024, dtype=torch.uint8, device="cuda")
+    st = rt._lib.rt_accumulate(plan.handle, C.byref(dtr.struct(rt.RT_MIXED)), small.data_ptr(),
+                               small.data_ptr(), small.numel(),
+                               torch.cuda.current_stream().cuda_stream)
+    assert st == rt.RT_E_UNSUPPORTED, rt.rt_last_error()
+    assert "split the antennas" in rt.rt_last_error()
+
+
 def test_workspace_too_small_is_rejected(rt):
     import torch
     w = W.config(0)
