@@ -375,7 +375,9 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     for (int64_t a = 0; a < b.sh[s].an.m; ++a)
       for (int g = 0; g < b.sh[s].n_segs; ++g) b.merges.push_back(MergeTask{s, (int32_t)a, g, 0});
   }
-  if (b.merges.size() > (size_t)INT32_MAX) return "too many merge tasks";
+  // one merge workgroup of kMergeThreads per (shower, antenna, segment): the
+  // launch must stay below 2^32 threads
+  if (b.merges.size() * kMergeThreads > (size_t)UINT32_MAX) return "too many merge tasks";
   return "";
 }
 
