@@ -349,7 +349,8 @@ def rt_batch_set_timing_events(batch: int, start_event, stop_event) -> None:
 # ------------------------------------------------------------------ convenience
 class Plan:
     """A radio process for one detector, medium, formalism and precision
-    (§4, Listing 2), with its own workspace."""
+    (§4, Listing 2), with its own workspace per stream (calls on one stream
+    run in order and share it; calls on different streams get their own)."""
 
     def __init__(self, det: DeviceDetector, medium, formalism: str = "endpoint",
                  precision: str = "fp64", k: float = 1.0):
@@ -363,7 +364,7 @@ class Plan:
                                      self._table, float(getattr(medium, "z0", 0.0)),
                                      float(getattr(medium, "dz", 1.0)),
                                      float(getattr(medium, "earth_radius", 0.0)))
-        self._ws = None
+        self._ws = {}   # stream handle -> workspace
         self.dtype = torch.float64 if self.precision == RT_FP64 else torch.float32
 
     def __del__(self):
@@ -380,11 +381,16 @@ class Plan:
     def tiling(self, n_tracks: int):
         return rt_plan_get_tiling(self.handle, n_tracks)
 
-    def workspace(self, n_tracks: int) -> torch.Tensor:
+    def workspace(self, n_tracks: int, stream=None) -> torch.Tensor:
+        """The workspace of calls on ``stream`` (default: the current one),
+        grown to what n_tracks tracks need."""
         need = rt_plan_workspace_bytes(self.handle, n_tracks)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.det.x.device)
-        return self._ws
+        key = _stream(stream)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.det.x.device)
+            self._ws[key] = ws
+        return ws
 
     def new_traces(self) -> torch.Tensor:
         return torch.zeros((self.det.m, self.det.n_bins, 3), dtype=self.dtype,
@@ -394,8 +400,8 @@ class Plan:
         if traces.dtype != self.dtype or not traces.is_contiguous() or \
                 tuple(traces.shape) != (self.det.m, self.det.n_bins, 3):
             raise ValueError("traces must be a contiguous [M, n_bins, 3] tensor of the plan dtype")
-        rt_accumulate(self.handle, tracks.struct(self.precision), traces, self.workspace(tracks.n),
-                      stream)
+        rt_accumulate(self.handle, tracks.struct(self.precision), traces,
+                      self.workspace(tracks.n, stream), stream)
         return traces
 
     def traces(self, tracks: DeviceTracks, stream=None) -> torch.Tensor:

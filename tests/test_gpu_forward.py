@@ -246,6 +246,34 @@ def test_empty_and_out_of_window_and_nonfinite(rt, orc):
         assert rel_l2(gpu, ref).max() <= FP64_BOUND
 
 
+def test_one_plan_on_two_streams(rt):
+    """Calls of one plan on two streams may overlap: each stream gets its own
+    workspace, so the results equal those of the same calls in sequence."""
+    import torch
+    w = W.config(1)
+    det = rt.DeviceDetector.from_array(w.array)
+    plan = rt.Plan(det, w.medium, "zhs", "mixed")
+    a = rt.DeviceTracks.from_tracks(w.tracks(40_000, mixed=True))
+    b = rt.DeviceTracks.from_tracks(w.tracks(40_000, start=40_000, mixed=True))
+    ref_a, ref_b = plan.traces(a), plan.traces(b)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    out_a, out_b = plan.new_traces(), plan.new_traces()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            out_a.zero_()
+            plan.accumulate(a, out_a, stream=s1)
+        with torch.cuda.stream(s2):
+            out_b.zero_()
+            plan.accumulate(b, out_b, stream=s2)
+    torch.cuda.synchronize()
+    for got, ref in ((out_a, ref_a), (out_b, ref_b)):
+        g, r = got.double().cpu().numpy(), ref.double().cpu().numpy()
+        assert np.abs(r).max() > 0
+        np.testing.assert_allclose(g, r, rtol=0, atol=1e-6 * np.abs(r).max())
+
+
 def test_oversized_launch_grid_is_rejected(rt):
     """Five million antennas with 2^20 tracks need more deposit workgroups
     per pass than one launch can hold: the call returns RT_E_UNSUPPORTED
