@@ -93,8 +93,8 @@ typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
  * with the nodes s_k and weights w_k of the rule on [0, 1] (ascending s_k,
  * sum w_k = 1; accurate to double rounding for these profiles), and h(q) =
  * rho2 / (sqrt(rho2 + R^2) + R), rho2 = (qx^2 + qy^2) + qz (qz + 2R), which is
- * |q - C| - R without cancellation. The adjoints accept every medium; batches
- * the uniform and exponential media. */
+ * |q - C| - R without cancellation. Plans, adjoints and batches accept every
+ * medium. */
 typedef enum {
   RT_UNIFORM = 0,
   RT_EXPONENTIAL = 1,
@@ -272,9 +272,11 @@ int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
  * Many independent showers in one launch. Each shower is one call of §2's
  * loop (its own detector, medium, formalism and tracks; the tracks of one
  * shower never reach another shower's antennas); a batch runs all of them
- * with one persistent deposit kernel whose workgroups take work items
+ * with persistent deposit kernels whose workgroups take work items
  * (antenna tile x bin segment x track split of some shower) from a shared
- * counter, longest first, followed by one merge kernel. Per-shower results
+ * counter, longest first (one kernel for the uniform and exponential media,
+ * a second for the tabulated and spherical ones when the batch has any),
+ * followed by one merge kernel. Per-shower results
  * are those of rt_accumulate on that shower alone up to floating-point
  * summation order; bins never change. */
 typedef struct {
@@ -328,7 +330,8 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
 int rt_batch_destroy(rt_batch *batch);
 
 /* Device workspace (bytes) rt_batch_launch needs (per-track records of all
- * showers and one partial-trace slot per work item). */
+ * showers, one partial-trace slot per work item and the cumulative integral
+ * of every tabulated shower's profile at its nodes). */
 int rt_batch_workspace_bytes(const rt_batch *batch, size_t *bytes);
 
 /* Statistics of the plan (out: host; any pointer may be NULL): work items,

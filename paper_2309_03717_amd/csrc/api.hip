@@ -97,7 +97,8 @@ int rt_device_info(int *dev, int *num_cus, size_t *lds_block, size_t *lds_cu) {
 
 int rt_fail(int status, const std::string &msg) { return fail(status, msg); }
 
-void rt_fill_table(const rt_medium &med, rt::Consts &c) {
+// Tabulated-profile fields of the constants (zero otherwise).
+static void fill_table(const rt_medium &med, rt::Consts &c) {
   c.tab = c.tabF = nullptr;
   c.n_tab = 0;
   c.tz0 = 0.0;
@@ -146,7 +147,9 @@ static void gauss_legendre01(int n, double *s, double *w) {
   }
 }
 
-void rt_fill_sphere(const rt_medium &med, rt::Consts &c) {
+// Spherical-Earth fields of the constants (radius, quadrature rule; zero
+// otherwise).
+static void fill_sphere(const rt_medium &med, rt::Consts &c) {
   c.re = c.re2 = c.re_twice = 0.0;
   for (int k = 0; k < rt::kGl; ++k) c.gl_s[k] = c.gl_w[k] = 0.0;
   if (med.kind == RT_SPHERICAL) {
@@ -155,6 +158,21 @@ void rt_fill_sphere(const rt_medium &med, rt::Consts &c) {
     c.re_twice = c.re + c.re;
     gauss_legendre01(rt::kGl, c.gl_s, c.gl_w);
   }
+}
+
+void rt_fill_consts(const rt_detector &det, const rt_medium &med, double k, rt::Consts &c) {
+  c.inv_c = 1.0 / 299792458.0;
+  c.inv_dt = 1.0 / det.dt;
+  c.k = k;
+  c.n_uniform = 1.0 + med.n0_minus_1;
+  c.n0m1 = med.n0_minus_1;
+  c.h = med.kind == RT_EXPONENTIAL || med.kind == RT_SPHERICAL ? med.scale_height : 1.0;
+  c.n0h = c.n0m1 * c.h;
+  c.nbins_d = (double)det.n_bins;
+  c.n_bins = det.n_bins;
+  c.medium = med.kind;
+  fill_table(med, c);
+  fill_sphere(med, c);
 }
 
 int rt_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
@@ -202,19 +220,7 @@ int rt_plan_create(rt_plan **plan, const rt_detector *det, const rt_medium *med,
   p->at_user = p->splits_user = p->block_user = p->seg_user = 0;
   p->pass_user = 0;
   p->ev_start = p->ev_stop = nullptr;
-  rt::Consts &c = p->c;
-  c.inv_c = 1.0 / 299792458.0;
-  c.inv_dt = 1.0 / det->dt;
-  c.k = k;
-  c.n_uniform = 1.0 + med->n0_minus_1;
-  c.n0m1 = med->n0_minus_1;
-  c.h = med->kind == RT_EXPONENTIAL || med->kind == RT_SPHERICAL ? med->scale_height : 1.0;
-  c.n0h = c.n0m1 * c.h;
-  c.nbins_d = (double)det->n_bins;
-  c.n_bins = det->n_bins;
-  c.medium = med->kind;
-  rt_fill_table(*med, c);
-  rt_fill_sphere(*med, c);
+  rt_fill_consts(*det, *med, k, p->c);
   *plan = p;
   return RT_OK;
 }

@@ -33,6 +33,8 @@ struct ShowerDesc {
   int64_t blocks_per_split;
   int64_t part0;             // first double of this shower's partial slots
   int64_t slot_len;          // doubles per slot: at * seg_len * 3
+  int64_t tab_off;           // tabulated medium: first double of its F table in the
+                             // workspace's table region (-1 otherwise)
 };
 
 struct WorkItem {
@@ -45,18 +47,34 @@ struct MergeTask {
 
 struct BatchArgs {
   const ShowerDesc *sh;
-  const WorkItem *items;
+  const WorkItem *items;       // [n_light) uniform / exponential, then the others
   const MergeTask *merges;
   const int64_t *cum_blocks;   // [n_showers + 1] first wave block of each shower
-  int32_t n_showers, n_items;
-  int *counter;
+  int32_t n_showers, n_items, n_light;
+  int *counter;                // [2]: next light item, next other item
   double *rec;
   double *partial;
+  double *tables;              // F tables of the tabulated showers
   int64_t total_blocks;
 };
 
 __global__ void batch_reset_kernel(int *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+  if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0;
+}
+
+// The constants of a shower as the kernels use them: a tabulated medium
+// reads its F table from the workspace.
+__device__ __forceinline__ Consts shower_consts(const ShowerDesc &s, const BatchArgs &b) {
+  Consts c = s.c;
+  if (c.medium == 2) c.tabF = b.tables + s.tab_off;
+  return c;
+}
+
+// F at the nodes of every tabulated shower's profile, one workgroup per
+// shower, the sums of a single plan's table.
+__global__ void batch_tables_kernel(BatchArgs b) {
+  const ShowerDesc &s = b.sh[blockIdx.x];
+  if (threadIdx.x == 0 && s.c.medium == 2) fill_tab_cells(s.c, b.tables + s.tab_off);
 }
 
 // Records of every shower, one thread per padded track.
@@ -73,9 +91,9 @@ __global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
     }
     const ShowerDesc &s = b.sh[lo];
     const int64_t i = g - s.rec_block0 * 64;
-    const Consts c = s.c;
+    const Consts c = shower_consts(s, b);
     const double z_ref = s.an.z[0];
-    const double e_ref = c.medium != 0 ? path_factor(z_ref, c) : 0.0;
+    const double e_ref = c.medium == 1 || c.medium == 2 ? path_factor(z_ref, c) : 0.0;
     double v[kRec];
     if (s.formalism == RT_ENDPOINT)
       make_record<0, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
@@ -97,8 +115,8 @@ __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int
   load_tile<AT, MED>(an, a_begin, n_ant, c, t);
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
-  deposit_blocks<F, P, MED, AT, true>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo, hi,
-                                      (double)lo, (double)hi, c);
+  deposit_blocks<F, P, MED, AT, MED != 3>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
+                                          hi, (double)lo, (double)hi, c);
 }
 
 template <int F, int P, int MED>
@@ -115,24 +133,28 @@ __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b
 }
 
 // Persistent workgroups: take items until the counter passes the last one.
-// Every workgroup leaves the loop once the counter has handed out n_items
-// indices, so the grid always drains. The runtime switch over formalism,
+// Every workgroup leaves the loop once the counter has handed out its item
+// range, so the grid always drains. The runtime switch over formalism,
 // medium and tile width keeps the union of their live registers, hence at
 // most 512 threads per workgroup (about 200 VGPRs, two waves per SIMD).
-template <int P>
+// HEAVY = 0 takes the items of the uniform and exponential media (counter 0),
+// HEAVY = 1 those of the tabulated and spherical ones (counter 1), so that the
+// common case keeps its registers.
+template <int P, int HEAVY>
 __global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   acc_t *tile = reinterpret_cast<acc_t *>(smem);
   __shared__ int cur;
+  const int first = HEAVY ? b.n_light : 0, last = HEAVY ? b.n_items : b.n_light;
   for (;;) {
     __syncthreads();   // everyone has read cur and flushed the previous tile
-    if (threadIdx.x == 0) cur = atomicAdd(b.counter, 1);
+    if (threadIdx.x == 0) cur = first + atomicAdd(b.counter + HEAVY, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(cur);
-    if (it >= b.n_items) break;
+    if (it >= last) break;
     const WorkItem w = b.items[it];
     const ShowerDesc &sd = b.sh[w.shower];
-    const Consts c = sd.c;
+    const Consts c = shower_consts(sd, b);
     const AntPtrs an = sd.an;
     const int at = sd.at, seg_len = sd.seg_len;
     const int64_t a_begin = (int64_t)w.atile * at;
@@ -145,15 +167,16 @@ __global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
     const double *rec = b.rec + sd.rec_block0 * (kRec * 64);
     const int64_t b_first = (int64_t)w.split * sd.blocks_per_split + (threadIdx.x >> 6);
     const int64_t b_end = min(sd.n_blocks, (int64_t)(w.split + 1) * sd.blocks_per_split);
-    const int kind = sd.formalism * 2 + c.medium;
+    constexpr int M0 = HEAVY ? 2 : 0, M1 = HEAVY ? 3 : 1;   // this kernel's two media
+    const int kind = sd.formalism * 2 + (c.medium == M1);
     if (kind == 0)
-      run_item_at<0, P, 0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+      run_item_at<0, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
     else if (kind == 1)
-      run_item_at<0, P, 1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+      run_item_at<0, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
     else if (kind == 2)
-      run_item_at<1, P, 0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+      run_item_at<1, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
     else
-      run_item_at<1, P, 1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+      run_item_at<1, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
     __syncthreads();
     const int64_t slot = ((int64_t)w.atile * sd.n_segs + w.seg) * sd.splits + w.split;
     acc_t *dst = b.partial + sd.part0 + slot * sd.slot_len;
@@ -198,7 +221,9 @@ struct rt_batch {
   std::vector<rt::WorkItem> items;
   std::vector<rt::MergeTask> merges;
   std::vector<int64_t> cum;
+  int32_t n_light = 0;         // items of the uniform and exponential media, listed first
   int64_t total_blocks = 0, total_partial = 0, total_pairs = 0;
+  int64_t total_tab = 0;       // doubles of the tabulated showers' F tables
   rt::ShowerDesc *d_sh = nullptr;
   rt::WorkItem *d_items = nullptr;
   rt::MergeTask *d_merges = nullptr;
@@ -219,8 +244,13 @@ static size_t record_bytes(const rt_batch &b) {
   return align256((size_t)b.total_blocks * kRec * 64 * sizeof(double));
 }
 
+static size_t partial_bytes(const rt_batch &b) {
+  return align256((size_t)b.total_partial * sizeof(acc_t));
+}
+
+// records, partial slots, then the F tables of the tabulated showers
 size_t batch_workspace_bytes(const rt_batch &b) {
-  return record_bytes(b) + align256((size_t)b.total_partial * sizeof(acc_t));
+  return record_bytes(b) + partial_bytes(b) + align256((size_t)b.total_tab * sizeof(double));
 }
 
 static BatchArgs batch_args(const rt_batch &b, void *workspace) {
@@ -231,34 +261,50 @@ static BatchArgs batch_args(const rt_batch &b, void *workspace) {
   a.cum_blocks = b.d_cum;
   a.n_showers = (int32_t)b.sh.size();
   a.n_items = (int32_t)b.items.size();
+  a.n_light = b.n_light;
   a.counter = b.d_counter;
   char *ws = reinterpret_cast<char *>(workspace);
   a.rec = reinterpret_cast<double *>(ws);
   a.partial = reinterpret_cast<double *>(ws + record_bytes(b));
+  a.tables = reinterpret_cast<double *>(ws + record_bytes(b) + partial_bytes(b));
   a.total_blocks = b.total_blocks;
   return a;
 }
 
-static void *deposit_fn(int precision) {
-  return precision == RT_FP64 ? (void *)batch_deposit_kernel<0> : (void *)batch_deposit_kernel<1>;
+static void *deposit_fn(int precision, int heavy) {
+  if (precision == RT_FP64)
+    return heavy ? (void *)batch_deposit_kernel<0, 1> : (void *)batch_deposit_kernel<0, 0>;
+  return heavy ? (void *)batch_deposit_kernel<1, 1> : (void *)batch_deposit_kernel<1, 0>;
 }
 
-// reset counter, records, persistent deposit, merge
+static bool is_heavy(int medium) { return medium == RT_TABULATED || medium == RT_SPHERICAL; }
+
+// reset counters, F tables, records, the persistent deposits (uniform and
+// exponential showers, then the others), merge
 static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t stream,
                                 hipEvent_t ev0, hipEvent_t ev1) {
   if (b.items.empty()) return hipSuccess;
   BatchArgs a = batch_args(b, workspace);
   batch_reset_kernel<<<1, 64, 0, stream>>>(b.d_counter);
+  if (b.total_tab > 0) batch_tables_kernel<<<(unsigned)b.sh.size(), 64, 0, stream>>>(a);
   const unsigned pblocks = (unsigned)std::min<int64_t>((b.total_blocks * 64 + 255) / 256, 1 << 16);
   if (b.precision == RT_FP64)
     batch_prepare_kernel<0><<<pblocks, 256, 0, stream>>>(a);
   else
     batch_prepare_kernel<1><<<pblocks, 256, 0, stream>>>(a);
   if (ev0) (void)hipEventRecord(ev0, stream);
-  if (b.precision == RT_FP64)
-    batch_deposit_kernel<0><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
-  else
-    batch_deposit_kernel<1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+  if (b.n_light > 0) {
+    if (b.precision == RT_FP64)
+      batch_deposit_kernel<0, 0><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+    else
+      batch_deposit_kernel<1, 0><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+  }
+  if ((size_t)b.n_light < b.items.size()) {
+    if (b.precision == RT_FP64)
+      batch_deposit_kernel<0, 1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+    else
+      batch_deposit_kernel<1, 1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+  }
   if (ev1) (void)hipEventRecord(ev1, stream);
   if (b.precision == RT_FP64)
     batch_merge_kernel<0><<<(unsigned)b.merges.size(), kMergeThreads, 0, stream>>>(a);
@@ -307,19 +353,13 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     d.n_atiles = (int)((in.det.n_antennas + at - 1) / at);
     d.n_blocks = (in.tracks.n + 63) / 64;
     d.slot_len = (int64_t)at * seg * 3;
-    Consts &c = d.c;
-    c.inv_c = 1.0 / 299792458.0;
-    c.inv_dt = 1.0 / in.det.dt;
-    c.k = k;
-    c.n_uniform = 1.0 + in.med.n0_minus_1;
-    c.n0m1 = in.med.n0_minus_1;
-    c.h = in.med.kind == RT_EXPONENTIAL ? in.med.scale_height : 1.0;
-    c.n0h = c.n0m1 * c.h;
-    c.nbins_d = (double)B;
-    c.n_bins = B;
-    c.medium = in.med.kind;
-    rt_fill_table(in.med, c);
-    rt_fill_sphere(in.med, c);
+    rt_fill_consts(in.det, in.med, k, d.c);
+    const Consts &c = d.c;
+    d.tab_off = -1;
+    if (c.medium == RT_TABULATED) {   // 256-byte aligned table of n_tab doubles
+      d.tab_off = b.total_tab;
+      b.total_tab += ((int64_t)c.n_tab + 31) / 32 * 32;
+    }
     if (d.n_blocks > 0) max_slot = std::max(max_slot, d.slot_len);
     b.total_pairs += in.tracks.n * in.det.n_antennas;
   }
@@ -328,15 +368,17 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
                                                                512 / b.block));
   b.grid = num_cus * per_cu;
   // Track splits: items of similar cost (track x antenna evaluations, which
-  // every bin segment repeats), about items_per_cu of them per compute unit.
-  double total_cost = 0.0;
+  // every bin segment repeats), about items_per_cu of them per compute unit,
+  // counted apart for the two deposit kernels (their pairs cost differently).
+  double group_cost[2] = {0.0, 0.0};
   for (const ShowerDesc &d : b.sh)
-    total_cost += (double)d.n_blocks * 64 * d.at * d.n_atiles * d.n_segs;
-  const double target = std::max(1.0, total_cost / ((double)b.grid * items_per_cu));
+    group_cost[is_heavy(d.c.medium)] += (double)d.n_blocks * 64 * d.at * d.n_atiles * d.n_segs;
   b.cum.assign(n + 1, 0);
   for (int s = 0; s < n; ++s) {
     ShowerDesc &d = b.sh[s];
     const rt_tiling *user = (opt && opt->per_shower) ? &opt->per_shower[s] : nullptr;
+    const double target =
+        std::max(1.0, group_cost[is_heavy(d.c.medium)] / ((double)b.grid * items_per_cu));
     int64_t splits = user && user->track_splits > 0
                          ? user->track_splits
                          : (int64_t)std::ceil((double)d.n_blocks * 64 * d.at / target);
@@ -349,8 +391,9 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     b.total_partial += (int64_t)d.n_atiles * d.n_segs * d.splits * d.slot_len;
   }
   b.total_blocks = b.cum[n];
-  // Work items, longest first; equal costs keep shower order, so the items
-  // of one shower run side by side and share its records in the caches.
+  // Work items, the uniform and exponential media first, each group longest
+  // first; equal costs keep shower order, so the items of one shower run side
+  // by side and share its records in the caches.
   std::vector<std::pair<int64_t, WorkItem>> all;
   for (int s = 0; s < n; ++s) {
     const ShowerDesc &d = b.sh[s];
@@ -364,12 +407,18 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
         }
   }
   if (all.size() > (size_t)INT32_MAX - 1024) return "too many work items";
+  auto heavy = [&b](const WorkItem &w) { return is_heavy(b.sh[w.shower].c.medium); };
   std::stable_sort(all.begin(), all.end(),
-                   [](const std::pair<int64_t, WorkItem> &x, const std::pair<int64_t, WorkItem> &y) {
-                     return x.first > y.first;
+                   [&heavy](const std::pair<int64_t, WorkItem> &x,
+                            const std::pair<int64_t, WorkItem> &y) {
+                     const bool hx = heavy(x.second), hy = heavy(y.second);
+                     return hx != hy ? hy : x.first > y.first;
                    });
   b.items.reserve(all.size());
-  for (auto &x : all) b.items.push_back(x.second);
+  for (auto &x : all) {
+    b.items.push_back(x.second);
+    if (!heavy(x.second)) ++b.n_light;
+  }
   for (int s = 0; s < n; ++s) {
     if (b.sh[s].n_blocks == 0) continue;
     for (int64_t a = 0; a < b.sh[s].an.m; ++a)
@@ -427,8 +476,6 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
     if (sh.tracks.n >= ((int64_t)1 << 31))
       return rt_fail(RT_E_UNSUPPORTED, where + "at most 2^31 - 1 tracks per shower");
     if (sh.tracks.n > 0 && !sh.traces) return rt_fail(RT_E_INVALID, where + "traces is NULL");
-    if (sh.med.kind == RT_TABULATED || sh.med.kind == RT_SPHERICAL)
-      return rt_fail(RT_E_UNSUPPORTED, where + "batches take the uniform and exponential media");
     if (options && options->per_shower) {
       const rt_tiling &t = options->per_shower[s];
       if (t.antennas_per_block < 0 || t.antennas_per_block > 3 || t.track_splits < 0 ||
@@ -456,10 +503,10 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
   if (e == hipSuccess) e = rt::upload(&b->d_items, b->items);
   if (e == hipSuccess) e = rt::upload(&b->d_merges, b->merges);
   if (e == hipSuccess) e = rt::upload(&b->d_cum, b->cum);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, sizeof(int));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(rt::deposit_fn(precision), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)b->lds_bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(int));
+  for (int heavy = 0; heavy < 2 && e == hipSuccess; ++heavy)
+    e = hipFuncSetAttribute(rt::deposit_fn(precision, heavy),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes);
   if (e == hipSuccess && !b->direct) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     rt::release(b);

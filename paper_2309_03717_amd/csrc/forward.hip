@@ -184,18 +184,12 @@ size_t table_bytes(const rt_plan &p) {
 
 // F at the nodes of a tabulated profile: trapezoids summed from the first
 // node up, one thread (the order every lookup relies on).
-__global__ void tab_cells_kernel(const double *f, int n, double dz, double *cells) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double acc = 0.0;
-  cells[0] = 0.0;
-  for (int j = 1; j < n; ++j) {
-    acc += (0.5 * dz) * (f[j - 1] + f[j]);
-    cells[j] = acc;
-  }
+__global__ void tab_cells_kernel(Consts c, double *cells) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) fill_tab_cells(c, cells);
 }
 
 void launch_tab_cells(const rt_plan &p, double *cells, hipStream_t stream) {
-  tab_cells_kernel<<<1, 64, 0, stream>>>(p.c.tab, p.c.n_tab, p.c.tdz, cells);
+  tab_cells_kernel<<<1, 64, 0, stream>>>(p.c, cells);
 }
 
 Tiling choose_tiling(const rt_plan &p, int64_t n) {

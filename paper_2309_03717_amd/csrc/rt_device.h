@@ -91,6 +91,16 @@ __device__ __forceinline__ double tab_cells(int i, const Consts &c) {
   return acc;
 }
 
+// The same sums at every node, written to cells[0 .. n_tab), by one thread.
+__device__ __forceinline__ void fill_tab_cells(const Consts &c, double *cells) {
+  double acc = 0.0;
+  cells[0] = 0.0;
+  for (int j = 1; j < c.n_tab; ++j) {
+    acc += (0.5 * c.tdz) * (c.tab[j - 1] + c.tab[j]);
+    cells[j] = acc;
+  }
+}
+
 // Tabulated profile: F(z) = integral of f from tz0 to z (exact for the
 // piecewise-linear f; slope f at the ends beyond the nodes).
 __device__ __forceinline__ double tab_F(double z, const Consts &c) {

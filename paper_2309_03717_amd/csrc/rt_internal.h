@@ -81,11 +81,9 @@ int rt_hip_fail(hipError_t e, const char *what);
 int rt_check_setup(const rt_detector *det, const rt_medium *med, int formalism, int precision,
                    double k);
 int rt_check_tracks(const rt_tracks *t, int64_t n_antennas);
-// Tabulated-profile fields of the constants from a medium (zero otherwise).
-void rt_fill_table(const rt_medium &med, rt::Consts &c);
-
-// Spherical-Earth fields of the constants (radius, quadrature rule; zero
-// otherwise).
-void rt_fill_sphere(const rt_medium &med, rt::Consts &c);
+// The kernels' constants of one (detector, medium, prefactor) set-up: time
+// binning, refractivity and the fields of every medium kind (zero where the
+// kind does not use them). Single plans and batches both take them from here.
+void rt_fill_consts(const rt_detector &det, const rt_medium &med, double k, rt::Consts &c);
 // Current device, its compute units and LDS bytes per workgroup and per CU.
 int rt_device_info(int *dev, int *num_cus, size_t *lds_block, size_t *lds_cu);

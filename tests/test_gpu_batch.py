@@ -86,6 +86,87 @@ def test_batch_matches_oracle_per_shower(rt, orc, precision):
     print(precision, "worst per-antenna rel L2", worst, b.info)
 
 
+class Shower:
+    """A hand-built shower of a batch: array, medium, formalism, tracks."""
+
+    def __init__(self, index, formalism, medium, array, tracks):
+        self.index, self.formalism, self.medium, self.array = index, formalism, medium, array
+        self._tracks = tracks
+
+    def tracks(self, mixed=False):
+        return self._tracks.to_mixed() if mixed else self._tracks
+
+
+def tilted_star(medium):
+    """The 160-antenna star with antenna heights 0 .. 190 m."""
+    x, y, _ = W.star_layout(8, 20, 25.0)
+    z = (np.arange(x.size) % 20) * 10.0
+    return W.make_array(x, y, z, medium, 0.1e-9, 4096)
+
+
+def heavy_mix():
+    """Showers of every medium in one batch: the tabulated profile and the
+    spherical Earth (the star at several heights; the inclined shower over a
+    14-km grid with 8192 bins, hence several bin segments) between ordinary
+    uniform and exponential showers."""
+    layered, sph = W.layered_air(), W.SPHERICAL_AIR
+    light = small_showers(3, 1500)
+    star_t = tilted_star(layered)
+    star_s = tilted_star(sph)
+    inc_tr, inc_arr = W.inclined_shower(600)
+    c1 = W.config(1)
+    return [
+        light[0],
+        Shower(101, "zhs", layered, star_t, c1.tracks(1300)),
+        Shower(102, "endpoint", sph, star_s, c1.tracks(900, start=2000)),
+        light[1],
+        Shower(103, "zhs", sph, inc_arr, inc_tr),
+        Shower(104, "endpoint", layered, star_t, c1.tracks(1100, start=5000)),
+        light[2],
+        Shower(105, "endpoint", sph, inc_arr, inc_tr),
+    ]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_heavy_media_batch_matches_oracle(rt, orc, precision):
+    """A batch holding tabulated and spherical showers among uniform and
+    exponential ones: every shower against the oracle."""
+    showers = heavy_mix()
+    kinds = {s.medium.kind for s in showers}
+    assert {"tabulated", "spherical"} <= kinds and len(kinds) >= 3, kinds
+    tracks = [host_tracks(s, precision) for s in showers]
+    b = rt.Batch(device_showers(rt, showers, precision, tracks), precision)
+    got = fetch(b.launch())
+    bound = FP64_BOUND if precision == "fp64" else MIXED_BOUND
+    for sh, tr, g in zip(showers, tracks, got):
+        ref = oracle_of(orc, sh, tr, precision)
+        assert np.abs(ref).max() > 0, sh.index
+        e = rel_l2(g, ref).max()
+        print(precision, sh.index, sh.formalism, sh.medium.kind, "max rel L2", e)
+        assert e <= bound, (sh.index, sh.formalism, sh.medium.kind, e)
+
+
+HEAVY_OPTIONS = [dict(), dict(items_per_cu=64, max_antennas_per_tile=1),
+                 dict(block_threads=128, direct_launch=1)]
+
+
+@pytest.mark.parametrize("opt", HEAVY_OPTIONS, ids=[str(o) for o in HEAVY_OPTIONS])
+def test_heavy_media_batch_equals_single_plans(rt, opt):
+    """The same showers through single plans: equal up to summation order,
+    whatever the launch shape; graph replays (the F tables rebuilt each time)
+    add the same traces again."""
+    showers = heavy_mix()
+    dev = device_showers(rt, showers, "fp64")
+    b = rt.Batch(dev, "fp64", options=rt.BatchOptions(**opt))
+    got = fetch(b.launch())
+    again = fetch(b.launch())
+    for (det, md, f, dtr), g, g2 in zip(dev, got, again):
+        ref = fetch([rt.Plan(det, md, f, "fp64").traces(dtr)])[0]
+        scale = max(np.abs(ref).max(), 1e-300)
+        assert np.abs(g - ref).max() <= 1e-12 * scale, (md.kind, f)
+        assert np.abs(g2 - 2 * ref).max() <= 2e-12 * scale, (md.kind, f)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_equals_single_plans(rt, precision):
     showers = small_showers(8, 3000)

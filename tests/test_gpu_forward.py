@@ -357,16 +357,6 @@ def test_tabulated_medium_traces(rt, orc, formalism, precision):
     assert err.max() <= (FP64_BOUND if precision == "fp64" else MIXED_BOUND)
 
 
-def test_tabulated_medium_rejected_by_batch(rt):
-    md = W.layered_air()
-    arr = tilted_star(md)
-    tr = W.config(1).tracks(100)
-    det = rt.DeviceDetector.from_array(arr)
-    with pytest.raises(rt.RadtraceError) as e:
-        rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
-    assert e.value.status == rt.RT_E_UNSUPPORTED
-
-
 # ----------------------------------------------------------------- spherical Earth
 def spherical_case(which, n):
     """(tracks, array) for the spherical-Earth tests: the star with antennas
@@ -428,15 +418,6 @@ def test_spherical_tilings(rt, orc, formalism, precision):
         else:
             np.testing.assert_allclose(g, base, rtol=0, atol=(1e-11 if precision == "fp64" else 1e-6)
                                        * np.abs(base).max(), err_msg=str(tl))
-
-
-def test_spherical_medium_rejected_by_batch(rt):
-    md = W.SPHERICAL_AIR
-    tr, arr = spherical_case("star", 100)
-    det = rt.DeviceDetector.from_array(arr)
-    with pytest.raises(rt.RadtraceError) as e:
-        rt.Batch([(det, md, "zhs", rt.DeviceTracks.from_tracks(tr))], "fp64")
-    assert e.value.status == rt.RT_E_UNSUPPORTED
 
 
 # ----------------------------------------------------------------- degenerate cases
