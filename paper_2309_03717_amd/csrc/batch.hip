@@ -99,9 +99,7 @@ __global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
       make_record<0, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
     else
       make_record<1, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
-    double *out = b.rec + (blk * kRec) * 64 + (g & 63);
-#pragma unroll
-    for (int f = 0; f < kRec; ++f) out[f * 64] = v[f];
+    store_record<P>(b.rec + (blk * kRec) * 64, (int)(g & 63), v);
   }
 }
 

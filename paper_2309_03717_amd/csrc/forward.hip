@@ -53,9 +53,7 @@ __global__ void __launch_bounds__(256) prepare_kernel(PrepArgs g) {
        i += (int64_t)gridDim.x * blockDim.x) {
     double v[kRec];
     make_record<F, P>(g.tr, i, i < g.tr.n, g.c, z_ref, e_ref, v);
-    double *out = g.rec + ((i >> 6) * kRec) * 64 + (i & 63);
-#pragma unroll
-    for (int f = 0; f < kRec; ++f) out[f * 64] = v[f];
+    store_record<P>(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v);
   }
 }
 

@@ -25,10 +25,16 @@ struct Prec<1> {  // RT_MIXED
 
 // ------------------------------------------------------------------ track record
 
-// Per-track record, kRec doubles per track, blocked by waves of 64 tracks:
-// field f of track 64 b + l is rec[(b * kRec + f) * 64 + l], so a wave reads
-// each field as one contiguous 512-byte run from a single base address.
+// Per-track record, kRec doubles per track, blocked by waves of 64 tracks.
+// FP64 records are stored in field pairs (2g, 2g + 1): field f of track
+// 64 b + l is rec[(b * kRec + (f & ~1)) * 64 + 2 l + (f & 1)], so one 16-byte
+// load per lane brings a pair and a wave reads it as one contiguous 1-KB run.
+// Mixed records keep one field per run: rec[(b * kRec + f) * 64 + l], one
+// 8-byte load per lane and field (measured faster for their deposits, the
+// paired layout faster for the FP64 ones).
 constexpr int kRec = 16;
+template <int P>
+constexpr bool paired_records() { return P == 0; }
 enum : int {
   R_X0, R_Y0, R_Z0, R_T0,  // start point and time
   R_X1, R_Y1, R_Z1, R_T1,  // end point and time
@@ -69,6 +75,47 @@ constexpr bool slot_loaded(int f) {
   if (P == 0) return (f == R_E0 || f == R_E1) ? H : true;
   if (f <= M_YZ) return true;
   return H && f <= M_E1;
+}
+
+// The two fields of every pair are loaded together or not at all.
+template <int P, int MED, bool H>
+constexpr bool pairs_agree() {
+  for (int g = 0; g < kRec; g += 2)
+    if (slot_loaded<P, MED, H>(g) != slot_loaded<P, MED, H>(g + 1)) return false;
+  return true;
+}
+
+// Writes the record v of lane l into its wave block.
+template <int P>
+__device__ __forceinline__ void store_record(double *blk, int l, const double *v) {
+  if constexpr (paired_records<P>()) {
+#pragma unroll
+    for (int g = 0; g < kRec; g += 2)
+      *reinterpret_cast<double2 *>(blk + g * 64 + 2 * l) = make_double2(v[g], v[g + 1]);
+  } else {
+    double *out = blk + l;
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) out[f * 64] = v[f];
+  }
+}
+
+// Reads the slots of lane l's paired record that a deposit uses
+// (slot_loaded), one pair per load; the other slots read as 0. (Mixed records
+// are read field by field where they are used.)
+template <int P, int MED, bool H>
+__device__ __forceinline__ void load_record_pairs(const double *blk, int l, double *v) {
+  static_assert(paired_records<P>() && pairs_agree<P, MED, H>(),
+                "paired records, loaded a whole pair at a time");
+#pragma unroll
+  for (int g = 0; g < kRec; g += 2) {
+    if (slot_loaded<P, MED, H>(g)) {
+      const double2 d = *reinterpret_cast<const double2 *>(blk + g * 64 + 2 * l);
+      v[g] = d.x;
+      v[g + 1] = d.y;
+    } else {
+      v[g] = v[g + 1] = 0.0;
+    }
+  }
 }
 
 // Builds the record of one track (fields as above). A track with any
@@ -336,9 +383,13 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
   if (!PF) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
       double rv[kRec];
-      const double *r = rec + blk * (kRec * 64) + lane;
+      if constexpr (paired_records<P>()) {
+        load_record_pairs<P, MED, H>(rec + blk * (kRec * 64), lane, rv);
+      } else {
+        const double *r = rec + blk * (kRec * 64) + lane;
 #pragma unroll
-      for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
+        for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
+      }
       deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
     }
     return;
@@ -347,20 +398,28 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
 #pragma unroll
   for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
   if (b_first < b_end) {
-    const double *r = rec + b_first * (kRec * 64) + lane;
+    if constexpr (paired_records<P>()) {
+      load_record_pairs<P, MED, H>(rec + b_first * (kRec * 64), lane, nx);
+    } else {
+      const double *r = rec + b_first * (kRec * 64) + lane;
 #pragma unroll
-    for (int f = 0; f < kRec; ++f)
-      if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
+      for (int f = 0; f < kRec; ++f)
+        if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
+    }
   }
   for (int64_t blk = b_first; blk < b_end; blk += waves) {
     double rv[kRec];
 #pragma unroll
     for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
     if (blk + waves < b_end) {
-      const double *r = rec + (blk + waves) * (kRec * 64) + lane;
+      if constexpr (paired_records<P>()) {
+        load_record_pairs<P, MED, H>(rec + (blk + waves) * (kRec * 64), lane, nx);
+      } else {
+        const double *r = rec + (blk + waves) * (kRec * 64) + lane;
 #pragma unroll
-      for (int f = 0; f < kRec; ++f)
-        if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
+        for (int f = 0; f < kRec; ++f)
+          if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
+      }
     }
     deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
   }
