@@ -18,7 +18,9 @@
 // gradient in the emission point has horizontal components and is taken per
 // pair from the quadrature.
 //
-// Kernels: phi_kernel (one workgroup per antenna: prefix sums of G in double),
+// Kernels: phi_kernel (one workgroup per antenna: prefix sums of G in double,
+// written with G itself as one record per bin edge, so that a box edge reads
+// its Phi and G from one place),
 // vjp_kernel (one thread per track, loop over antennas, per-track gradients
 // in registers, per-workgroup partial of the n0 - 1 gradient in fixed order)
 // and n0_sum_kernel (fixed-order sum of the partials).
@@ -30,12 +32,16 @@ namespace rt {
 
 constexpr int kVjpBlock = 256;
 
-// Phi[a][c][j] = sum_{i < j} G[a][i][c], j = 0..B (double).
+// Edge records of one antenna, j = 0..B, kEdge doubles each (16-byte aligned):
+// Phi_c[j] = sum_{i < j} G[i][c] in slots 0-2 and G[j][c] (0 for j = B) in
+// slots 3-5, both in double.
+constexpr int kEdge = 6;
+
 template <typename TG>
 __global__ void __launch_bounds__(256) phi_kernel(const TG *grad, double *phi, int n_bins) {
   const int64_t a = blockIdx.x;
   const TG *g = grad + (size_t)a * n_bins * 3;
-  double *out = phi + (size_t)a * 3 * (n_bins + 1);
+  double *out = phi + (size_t)a * kEdge * (n_bins + 1);
   __shared__ double carry[256][3];
   const int per = (n_bins + blockDim.x - 1) / blockDim.x;
   const int b0 = min((int)threadIdx.x * per, n_bins), b1 = min(b0 + per, n_bins);
@@ -51,35 +57,45 @@ __global__ void __launch_bounds__(256) phi_kernel(const TG *grad, double *phi, i
       carry[t][threadIdx.x] = acc;
       acc += x;
     }
-    out[threadIdx.x * (n_bins + 1) + n_bins] = acc;   // Phi[B]: the total
+    out[(size_t)n_bins * kEdge + threadIdx.x] = acc;   // Phi[B]: the total
+    out[(size_t)n_bins * kEdge + 3 + threadIdx.x] = 0.0;
   }
   __syncthreads();
   for (int c = 0; c < 3; ++c) run[c] = carry[threadIdx.x][c];
   for (int b = b0; b < b1; ++b)
     for (int c = 0; c < 3; ++c) {
-      out[c * (n_bins + 1) + b] = run[c];
-      run[c] += (double)g[3 * b + c];
+      const double gv = (double)g[3 * b + c];
+      out[(size_t)b * kEdge + c] = run[c];
+      out[(size_t)b * kEdge + 3 + c] = gv;
+      run[c] += gv;
     }
 }
 
-template <typename TG>
-struct GradView {
-  const TG *g;       // [B][3] of one antenna
-  const double *phi; // [3][B + 1] of one antenna
-  int n_bins;
-  double nb;
+// G and its integral at a box edge u (in bins) of one antenna:
+// value[c] = G_c at u (zero outside [0, B)), cumulative[c] = Phi_c(u), the
+// integral of G_c from 0 to u, all from the edge record of bin floor(u)
+// (three 16-byte loads).
+struct EdgeValues {
+  double value[3], cumulative[3];
 
-  // G_c at u (zero outside [0, B))
-  __device__ __forceinline__ double value(int c, double u) const {
-    if (!(u >= 0.0 && u < nb)) return 0.0;
-    return (double)g[3 * (int)u + c];
-  }
-  // Phi_c(u) = integral of G_c from 0 to u
-  __device__ __forceinline__ double cumulative(int c, double u) const {
-    if (!(u > 0.0)) return 0.0;
-    if (u >= nb) return phi[c * (n_bins + 1) + n_bins];
-    int j = (int)u;
-    return phi[c * (n_bins + 1) + j] + (u - (double)j) * (double)g[3 * j + c];
+  __device__ __forceinline__ EdgeValues(const double *edges, int n_bins, double nb, double u) {
+    const bool inside = u >= 0.0 && u < nb;
+    const bool above = u >= nb;
+    for (int c = 0; c < 3; ++c) value[c] = cumulative[c] = 0.0;
+    if (!(inside || above)) return;   // below the window (or NaN)
+    const int j = inside ? (int)u : n_bins;
+    const double2 *r = reinterpret_cast<const double2 *>(edges + (size_t)j * kEdge);
+    const double2 p01 = r[0], p2g0 = r[1], g12 = r[2];
+    const double phi[3] = {p01.x, p01.y, p2g0.x}, g[3] = {p2g0.y, g12.x, g12.y};
+    const double w = u - (double)j;
+    for (int c = 0; c < 3; ++c) {
+      if (inside) {
+        value[c] = g[c];
+        cumulative[c] = u > 0.0 ? phi[c] + w * g[c] : 0.0;
+      } else {
+        cumulative[c] = phi[c];   // the total
+      }
+    }
   }
 };
 
@@ -88,7 +104,7 @@ struct VjpArgs {
   AntPtrs an;
   Consts c;
   const void *grad;     // [M][B][3], float (mixed) or double
-  const double *phi;    // [M][3][B+1]
+  const double *phi;    // ZHS: [M][B+1][kEdge] edge records
   double *g_qw, *g_p0, *g_p1;   // [n], [3][n], [3][n]
   double *n0_part;      // [gridDim.x]
 };
@@ -265,19 +281,19 @@ vjp_kernel(VjpArgs v) {
       const double bd = (b[0] * d[0] + b[1] * d[1]) + b[2] * d[2];
       double iu[3];   // integral per unit weight
       for (int k = 0; k < 3; ++k) iu[k] = kdt * (b[k] - bd * ir2 * d[k]) * ir;
-      GradView<In> gv{(const In *)v.grad + (size_t)a * c.n_bins * 3,
-                      v.phi + (size_t)a * 3 * (c.n_bins + 1), c.n_bins, c.nbins_d};
+      const double *edges = v.phi + (size_t)a * kEdge * (c.n_bins + 1);
+      const EdgeValues lo(edges, c.n_bins, c.nbins_d, ulo), hi(edges, c.n_bins, c.nbins_d, uhi);
       const bool same_bin = floor(ulo) == floor(uhi);
       const double iw = 1.0 / (uhi - ulo);
       double gbar[3], dl_dlo = 0.0, dl_dhi = 0.0;
       for (int k = 0; k < 3; ++k) {
         if (same_bin) {
-          gbar[k] = gv.value(k, ulo);
+          gbar[k] = lo.value[k];
         } else {
-          gbar[k] = (gv.cumulative(k, uhi) - gv.cumulative(k, ulo)) * iw;
+          gbar[k] = (hi.cumulative[k] - lo.cumulative[k]) * iw;
           const double ik = qw * iu[k] * c.inv_dt;
-          dl_dhi += ik * (gv.value(k, uhi) - gbar[k]) * iw;
-          dl_dlo += ik * (gbar[k] - gv.value(k, ulo)) * iw;
+          dl_dhi += ik * (hi.value[k] - gbar[k]) * iw;
+          dl_dlo += ik * (gbar[k] - lo.value[k]) * iw;
         }
       }
       // weight: the pair's loss share is linear in qw
@@ -433,11 +449,11 @@ __global__ void __launch_bounds__(256) n0_sum_kernel(const double *part, int64_t
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// ZHS: [Phi tables][per-workgroup n0 partials][F table of a tabulated
+// ZHS: [edge records][per-workgroup n0 partials][F table of a tabulated
 // medium]; Endpoint: the partials and the F table.
 static size_t phi_bytes(const rt_plan &p) {
   if (p.formalism != RT_ZHS) return 0;
-  return align256((size_t)p.det.n_antennas * 3 * (p.det.n_bins + 1) * sizeof(double));
+  return align256((size_t)p.det.n_antennas * kEdge * (p.det.n_bins + 1) * sizeof(double));
 }
 
 using VjpKernel = void (*)(VjpArgs);
