@@ -188,9 +188,14 @@ def bench_batched(args):
     n_tracks = sum(d[3].n for d in dev)
     log(f"inputs resident: {len(dev)} showers, {n_tracks} tracks ({time.perf_counter() - t0:.1f} s)")
 
-    opt, timings, cached = autotune.tune_batch(dev, "mixed", k=rt.K_SI, sample_tracks=args.tune_sample,
-                                               log=log)
-    log(f"autotuned options {opt} ({'cache' if cached else f'{len(timings)} candidates timed'})")
+    if args.batch_options:
+        bt, at, ipc = (int(x) for x in args.batch_options.split(","))
+        opt = rt.BatchOptions(block_threads=bt, max_antennas_per_tile=at, items_per_cu=ipc)
+        log(f"options given: {opt}")
+    else:
+        opt, timings, cached = autotune.tune_batch(dev, "mixed", k=rt.K_SI,
+                                                   sample_tracks=args.tune_sample, log=log)
+        log(f"autotuned options {opt} ({'cache' if cached else f'{len(timings)} candidates timed'})")
     batch = rt.Batch(dev, "mixed", k=rt.K_SI, options=opt)
     log(f"batch: {batch.info}, workspace {batch.workspace.numel() / 1e9:.2f} GB")
 
@@ -613,6 +618,9 @@ def main():
                     help="grid4096: chunks of the workload also timed in FP64 mode (0: none)")
     ap.add_argument("--tune-sample", type=int, default=1 << 16,
                     help="batched: tracks per shower the autotuner times candidates on")
+    ap.add_argument("--batch-options", default=None,
+                    help="batched: block_threads,max_antennas_per_tile,items_per_cu "
+                         "instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

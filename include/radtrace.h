@@ -290,8 +290,11 @@ typedef struct {
 
 /* Launch shape of a batch (a zeroed struct, or NULL, keeps every automatic
  * choice):
- *  block_threads: workgroup size of the persistent kernel, a multiple of 64
- *                 in [64, 512] (0: 512)
+ *  block_threads: workgroup size of the persistent kernels, a multiple of 64
+ *                 in [64, 512] (0: 512), or 1024 together with
+ *                 max_antennas_per_tile 1: one-antenna tiles, taken by one
+ *                 kernel per formalism for the uniform and exponential
+ *                 media (the tabulated and spherical media keep 512)
  *  items_per_cu: work items per compute unit that the track splits aim for
  *                (0: 4); more items balance better, fewer merge less
  *  max_antennas_per_tile: cap on the antennas one item keeps in LDS, 1-3

@@ -81,10 +81,16 @@ def time_launches(fn: Callable[[], None], warmup: int = 1, reps: int = 3) -> flo
 
 
 def tune(key: str, candidates: Sequence, measure: Callable[[object], float],
-         cache: Optional[TuningCache] = None, log: Optional[Callable[[str], None]] = None):
+         cache: Optional[TuningCache] = None, log: Optional[Callable[[str], None]] = None,
+         final_measure: Optional[Callable[[object], float]] = None, finalists: int = 3,
+         family: Callable[[object], object] = lambda c: json.dumps(c)):
     """The candidate with the smallest measure(candidate) (seconds), cached
     under key. A candidate whose measurement raises (for example a shape the
-    library rejects) is skipped. Returns (best, timings, from_cache)."""
+    library rejects) is skipped. With final_measure (say, the whole workload
+    where measure times a sample), the fastest candidate of each of the
+    `finalists` fastest families (family(candidate): candidates that differ
+    only in a minor knob share one) is timed again by it and the fastest of
+    those wins. Returns (best, timings, from_cache)."""
     cache = cache if cache is not None else TuningCache()
     hit = cache.get(key)
     if hit is not None:
@@ -103,6 +109,20 @@ def tune(key: str, candidates: Sequence, measure: Callable[[object], float],
     if not timings:
         raise RuntimeError("no candidate launch shape could be measured")
     best = min(timings, key=lambda ct: ct[1])[0]
+    if final_measure is not None and finalists > 1 and len(timings) > 1:
+        final, seen = [], set()
+        for c, _ in sorted(timings, key=lambda ct: ct[1]):
+            fam = family(c)
+            if fam in seen:
+                continue
+            seen.add(fam)
+            if len(seen) > finalists:
+                break
+            t = final_measure(c)
+            final.append((c, t))
+            if log:
+                log(f"  final {c}: {t * 1e3:.3f} ms")
+        best = min(final, key=lambda ct: ct[1])[0]
     cache.put(key, best, [[c, t] for c, t in timings])
     return best, timings, False
 
@@ -123,25 +143,33 @@ def tune_batch(showers, precision: str = "mixed", k: float = 1.0,
                warmup: int = 1, reps: int = 2, log=None):
     """BatchOptions for the showers (list of (DeviceDetector, medium,
     formalism, DeviceTracks)). Candidates are (block_threads, max antennas
-    per tile, items per CU) triples; sample_tracks times each candidate on
+    per tile, items per CU) triples (1024 threads with one-antenna tiles
+    among them); sample_tracks times each candidate on
     the first tracks of every shower only. The result launches through a HIP
     graph."""
     from . import radtrace as rt
     key = batch_key(showers, precision)
-    cands = candidates or [list(c) for c in itertools.product(BATCH_BLOCKS, BATCH_AT, BATCH_ITEMS)]
+    cands = candidates or ([list(c) for c in itertools.product(BATCH_BLOCKS, BATCH_AT, BATCH_ITEMS)]
+                           + [[1024, 1, i] for i in BATCH_ITEMS])
     sample = showers
     if sample_tracks is not None:
         sample = [(d, m, f, t.slice(0, min(t.n, sample_tracks))) for d, m, f, t in showers]
 
-    def measure(c):
+    def timed(showers_, c, reps_):
         opt = rt.BatchOptions(block_threads=c[0], max_antennas_per_tile=c[1], items_per_cu=c[2],
                               direct_launch=1)
-        b = rt.Batch(sample, precision, k, opt)
-        t = time_launches(b.launch, warmup, reps)
+        b = rt.Batch(showers_, precision, k, opt)
+        t = time_launches(b.launch, warmup, reps_)
         del b
         return t
 
-    best, timings, cached = tune(key, cands, measure, TuningCache(cache_path), log)
+    # shapes within a percent on the sample can order differently on the
+    # whole batch: the best of the three best (workgroup size, tile width)
+    # families are timed again on all tracks
+    final = (lambda c: timed(showers, c, 1)) if sample is not showers else None
+    best, timings, cached = tune(key, cands, lambda c: timed(sample, c, reps),
+                                 TuningCache(cache_path), log, final_measure=final,
+                                 family=lambda c: (c[0], c[1]))
     return rt.BatchOptions(block_threads=best[0], max_antennas_per_tile=best[1],
                            items_per_cu=best[2]), timings, cached
 

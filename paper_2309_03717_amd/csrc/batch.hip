@@ -45,13 +45,20 @@ struct MergeTask {
   int32_t shower, antenna, seg, pad;
 };
 
+// Work-item groups, each taken by its own persistent kernel from its own
+// counter: the uniform and exponential media (all of them, or with
+// one-antenna tiles their Endpoint items, group 0, and their ZHS items,
+// group 1), then the tabulated and spherical media (group 2).
+enum : int { kGroupLight = 0, kGroupLightZhs = 1, kGroupHeavy = 2, kGroups = 3 };
+
 struct BatchArgs {
   const ShowerDesc *sh;
-  const WorkItem *items;       // [n_light) uniform / exponential, then the others
+  const WorkItem *items;       // grouped: [group_begin[g], group_begin[g + 1])
   const MergeTask *merges;
   const int64_t *cum_blocks;   // [n_showers + 1] first wave block of each shower
-  int32_t n_showers, n_items, n_light;
-  int *counter;                // [2]: next light item, next other item
+  int32_t n_showers, n_items;
+  int32_t group_begin[kGroups + 1];
+  int *counter;                // [kGroups]: next item of each group
   double *rec;
   double *partial;
   double *tables;              // F tables of the tabulated showers
@@ -59,14 +66,56 @@ struct BatchArgs {
 };
 
 __global__ void batch_reset_kernel(int *counter) {
-  if (threadIdx.x < 2 && blockIdx.x == 0) counter[threadIdx.x] = 0;
+  if (threadIdx.x < kGroups && blockIdx.x == 0) counter[threadIdx.x] = 0;
 }
 
-// The constants of a shower as the kernels use them: a tabulated medium
-// reads its F table from the workspace.
+// A wave-uniform copy of a 4- or 8-byte value: values a workgroup reads from
+// a shower descriptor in global memory are the same in every lane, and
+// saying so lets them live in scalar registers.
+template <class T>
+__device__ __forceinline__ T uniform(T x) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+  if constexpr (sizeof(T) == 4) {
+    int v;
+    __builtin_memcpy(&v, &x, 4);
+    v = __builtin_amdgcn_readfirstlane(v);
+    __builtin_memcpy(&x, &v, 4);
+  } else {
+    long long v;
+    __builtin_memcpy(&v, &x, 8);
+    const int lo = __builtin_amdgcn_readfirstlane((int)v);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    v = (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    __builtin_memcpy(&x, &v, 8);
+  }
+  return x;
+}
+
+// The constants of a shower as the kernels use them (wave-uniform): a
+// tabulated medium reads its F table from the workspace. The quadrature
+// nodes stay as loaded (the spherical path mean indexes them).
 __device__ __forceinline__ Consts shower_consts(const ShowerDesc &s, const BatchArgs &b) {
   Consts c = s.c;
   if (c.medium == 2) c.tabF = b.tables + s.tab_off;
+  c.inv_c = uniform(c.inv_c);
+  c.inv_dt = uniform(c.inv_dt);
+  c.k = uniform(c.k);
+  c.n_uniform = uniform(c.n_uniform);
+  c.n0m1 = uniform(c.n0m1);
+  c.h = uniform(c.h);
+  c.n0h = uniform(c.n0h);
+  c.nbins_d = uniform(c.nbins_d);
+  c.n_bins = uniform(c.n_bins);
+  c.medium = uniform(c.medium);
+  c.tab = uniform(c.tab);
+  c.tabF = uniform(c.tabF);
+  c.n_tab = uniform(c.n_tab);
+  c.tz0 = uniform(c.tz0);
+  c.tdz = uniform(c.tdz);
+  c.tinv_dz = uniform(c.tinv_dz);
+  c.re = uniform(c.re);
+  c.re2 = uniform(c.re2);
+  c.re_twice = uniform(c.re_twice);
   return c;
 }
 
@@ -117,12 +166,13 @@ __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int
                                           hi, (double)lo, (double)hi, c);
 }
 
-template <int F, int P, int MED>
+// Tile width switch; ATMAX = 1 compiles the one-antenna path only.
+template <int ATMAX, int F, int P, int MED>
 __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b_first,
                                             int64_t b_end, const AntPtrs &an, const Consts &c,
                                             acc_t *tile, int64_t a_begin, int n_ant, int row_len,
                                             int lo, int hi) {
-  if (at == 1)
+  if (ATMAX == 1 || at == 1)
     run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
   else if (at == 2)
     run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
@@ -130,31 +180,32 @@ __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b
     run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
 }
 
-// Persistent workgroups: take items until the counter passes the last one.
-// Every workgroup leaves the loop once the counter has handed out its item
-// range, so the grid always drains. The runtime switch over formalism,
-// medium and tile width keeps the union of their live registers, hence at
-// most 512 threads per workgroup (about 200 VGPRs, two waves per SIMD).
-// HEAVY = 0 takes the items of the uniform and exponential media (counter 0),
-// HEAVY = 1 those of the tabulated and spherical ones (counter 1), so that the
-// common case keeps its registers.
-template <int P, int HEAVY>
-__global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  acc_t *tile = reinterpret_cast<acc_t *>(smem);
-  __shared__ int cur;
-  const int first = HEAVY ? b.n_light : 0, last = HEAVY ? b.n_items : b.n_light;
+// Persistent workgroups: take the items of one group until its counter
+// passes the group's last one. Every workgroup leaves the loop once the
+// counter has handed out the group's range, so the grid always drains.
+// HEAVY: the group's two media (0: uniform, exponential; 1: tabulated,
+// spherical). FF: the one formalism compiled in, or -1 for a run-time switch
+// between both. ATMAX: the widest tile compiled in (1 or 3).
+template <int P, int HEAVY, int FF, int ATMAX>
+__device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t *tile,
+                                           int *cur) {
+  const int first = b.group_begin[group], last = b.group_begin[group + 1];
   for (;;) {
     __syncthreads();   // everyone has read cur and flushed the previous tile
-    if (threadIdx.x == 0) cur = first + atomicAdd(b.counter + HEAVY, 1);
+    if (threadIdx.x == 0) *cur = first + atomicAdd(b.counter + group, 1);
     __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(cur);
+    const int it = __builtin_amdgcn_readfirstlane(*cur);
     if (it >= last) break;
     const WorkItem w = b.items[it];
     const ShowerDesc &sd = b.sh[w.shower];
     const Consts c = shower_consts(sd, b);
-    const AntPtrs an = sd.an;
-    const int at = sd.at, seg_len = sd.seg_len;
+    AntPtrs an = sd.an;
+    an.x = uniform(an.x);
+    an.y = uniform(an.y);
+    an.z = uniform(an.z);
+    an.t_start = uniform(an.t_start);
+    an.m = uniform(an.m);
+    const int at = ATMAX == 1 ? 1 : uniform(sd.at), seg_len = uniform(sd.seg_len);
     const int64_t a_begin = (int64_t)w.atile * at;
     const int n_ant = (int)min((int64_t)at, an.m - a_begin);
     const int lo = w.seg * seg_len;
@@ -162,26 +213,62 @@ __global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
     const int row_len = (hi - lo) * 3;
     for (int i = threadIdx.x; i < at * row_len; i += blockDim.x) tile[i] = 0.0;
     __syncthreads();
-    const double *rec = b.rec + sd.rec_block0 * (kRec * 64);
-    const int64_t b_first = (int64_t)w.split * sd.blocks_per_split + (threadIdx.x >> 6);
-    const int64_t b_end = min(sd.n_blocks, (int64_t)(w.split + 1) * sd.blocks_per_split);
+    const double *rec = b.rec + uniform(sd.rec_block0) * (kRec * 64);
+    const int64_t per_split = uniform(sd.blocks_per_split);
+    const int64_t b_first = (int64_t)w.split * per_split + (threadIdx.x >> 6);
+    const int64_t b_end = min(uniform(sd.n_blocks), (int64_t)(w.split + 1) * per_split);
     constexpr int M0 = HEAVY ? 2 : 0, M1 = HEAVY ? 3 : 1;   // this kernel's two media
-    const int kind = sd.formalism * 2 + (c.medium == M1);
-    if (kind == 0)
-      run_item_at<0, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
-    else if (kind == 1)
-      run_item_at<0, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
-    else if (kind == 2)
-      run_item_at<1, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
-    else
-      run_item_at<1, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    const bool m1 = c.medium == M1;
+    const int f = FF >= 0 ? FF : uniform(sd.formalism);
+    if (FF != 1 && f == 0) {
+      if (m1)
+        run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
+                                     row_len, lo, hi);
+      else
+        run_item_at<ATMAX, 0, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
+                                     row_len, lo, hi);
+    } else if (FF != 0) {
+      if (m1)
+        run_item_at<ATMAX, 1, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
+                                     row_len, lo, hi);
+      else
+        run_item_at<ATMAX, 1, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
+                                     row_len, lo, hi);
+    }
     __syncthreads();
-    const int64_t slot = ((int64_t)w.atile * sd.n_segs + w.seg) * sd.splits + w.split;
-    acc_t *dst = b.partial + sd.part0 + slot * sd.slot_len;
+    const int64_t slot_len = uniform(sd.slot_len);
+    const int64_t slot =
+        ((int64_t)w.atile * uniform(sd.n_segs) + w.seg) * uniform(sd.splits) + w.split;
+    acc_t *dst = b.partial + uniform(sd.part0) + slot * slot_len;
     for (int a = 0; a < n_ant; ++a)
       for (int i = threadIdx.x; i < row_len; i += blockDim.x)
         dst[(int64_t)a * seg_len * 3 + i] = tile[a * row_len + i];
   }
+}
+
+// Any formalism and tile width, switched at run time: the union of their
+// live registers (about 185 VGPRs) allows two waves per SIMD, hence at most
+// 512 threads per workgroup. HEAVY = 0 takes group 0 (the uniform and
+// exponential media), HEAVY = 1 group 2 (the tabulated and spherical ones),
+// so that the common case keeps its registers.
+template <int P, int HEAVY>
+__global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int cur;
+  take_items<P, HEAVY, -1, 3>(b, HEAVY ? kGroupHeavy : kGroupLight,
+                              reinterpret_cast<acc_t *>(smem), &cur);
+}
+
+// One-antenna tiles of the uniform and exponential media in one formalism F
+// (group 0 Endpoint, group 1 ZHS): without the formalism and tile-width
+// switches the registers fit 1024-thread workgroups, four waves per SIMD, as
+// in the single-plan deposit.
+template <int P, int F>
+__global__ void __launch_bounds__(1024) batch_deposit_one_kernel(BatchArgs b) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int cur;
+  take_items<P, 0, F, 1>(b, F == 0 ? kGroupLight : kGroupLightZhs,
+                         reinterpret_cast<acc_t *>(smem), &cur);
 }
 
 // One workgroup per (shower, antenna, segment): traces += sum over the
@@ -211,15 +298,15 @@ __global__ void __launch_bounds__(kMergeThreads) batch_merge_kernel(BatchArgs b)
 struct rt_batch {
   int precision = 0;
   int device = 0;
-  int block = 512;
-  int grid = 1;
+  int block = 512;             // 1024: one-antenna tiles, per-formalism kernels
+  int grid = 1;                // persistent workgroups of each deposit kernel
   bool direct = false;
   size_t lds_bytes = 0;
   std::vector<rt::ShowerDesc> sh;
   std::vector<rt::WorkItem> items;
   std::vector<rt::MergeTask> merges;
   std::vector<int64_t> cum;
-  int32_t n_light = 0;         // items of the uniform and exponential media, listed first
+  int32_t group_begin[rt::kGroups + 1] = {0, 0, 0, 0};   // items, grouped
   int64_t total_blocks = 0, total_partial = 0, total_pairs = 0;
   int64_t total_tab = 0;       // doubles of the tabulated showers' F tables
   rt::ShowerDesc *d_sh = nullptr;
@@ -259,7 +346,7 @@ static BatchArgs batch_args(const rt_batch &b, void *workspace) {
   a.cum_blocks = b.d_cum;
   a.n_showers = (int32_t)b.sh.size();
   a.n_items = (int32_t)b.items.size();
-  a.n_light = b.n_light;
+  for (int g = 0; g <= kGroups; ++g) a.group_begin[g] = b.group_begin[g];
   a.counter = b.d_counter;
   char *ws = reinterpret_cast<char *>(workspace);
   a.rec = reinterpret_cast<double *>(ws);
@@ -269,16 +356,29 @@ static BatchArgs batch_args(const rt_batch &b, void *workspace) {
   return a;
 }
 
-static void *deposit_fn(int precision, int heavy) {
-  if (precision == RT_FP64)
-    return heavy ? (void *)batch_deposit_kernel<0, 1> : (void *)batch_deposit_kernel<0, 0>;
-  return heavy ? (void *)batch_deposit_kernel<1, 1> : (void *)batch_deposit_kernel<1, 0>;
+using BatchKernel = void (*)(BatchArgs);
+
+// The deposit kernel of an item group and its workgroup size.
+static BatchKernel deposit_fn(const rt_batch &b, int group, int *threads) {
+  const bool one = b.block == 1024 && group != kGroupHeavy;
+  *threads = one ? 1024 : std::min(b.block, 512);
+  if (b.precision == RT_FP64) {
+    if (one) return group == kGroupLight ? batch_deposit_one_kernel<0, 0> : batch_deposit_one_kernel<0, 1>;
+    return group == kGroupHeavy ? batch_deposit_kernel<0, 1> : batch_deposit_kernel<0, 0>;
+  }
+  if (one) return group == kGroupLight ? batch_deposit_one_kernel<1, 0> : batch_deposit_one_kernel<1, 1>;
+  return group == kGroupHeavy ? batch_deposit_kernel<1, 1> : batch_deposit_kernel<1, 0>;
 }
 
 static bool is_heavy(int medium) { return medium == RT_TABULATED || medium == RT_SPHERICAL; }
 
-// reset counters, F tables, records, the persistent deposits (uniform and
-// exponential showers, then the others), merge
+static int item_group(const rt_batch &b, const ShowerDesc &d) {
+  if (is_heavy(d.c.medium)) return kGroupHeavy;
+  return b.block == 1024 && d.formalism == RT_ZHS ? kGroupLightZhs : kGroupLight;
+}
+
+// reset counters, F tables, records, the persistent deposits of each item
+// group, merge
 static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t stream,
                                 hipEvent_t ev0, hipEvent_t ev1) {
   if (b.items.empty()) return hipSuccess;
@@ -291,17 +391,11 @@ static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t 
   else
     batch_prepare_kernel<1><<<pblocks, 256, 0, stream>>>(a);
   if (ev0) (void)hipEventRecord(ev0, stream);
-  if (b.n_light > 0) {
-    if (b.precision == RT_FP64)
-      batch_deposit_kernel<0, 0><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
-    else
-      batch_deposit_kernel<1, 0><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
-  }
-  if ((size_t)b.n_light < b.items.size()) {
-    if (b.precision == RT_FP64)
-      batch_deposit_kernel<0, 1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
-    else
-      batch_deposit_kernel<1, 1><<<b.grid, b.block, b.lds_bytes, stream>>>(a);
+  for (int g = 0; g < kGroups; ++g) {
+    if (b.group_begin[g + 1] == b.group_begin[g]) continue;
+    int threads = 0;
+    const BatchKernel k = deposit_fn(b, g, &threads);
+    hipLaunchKernelGGL(k, dim3(b.grid), dim3(threads), b.lds_bytes, stream, a);
   }
   if (ev1) (void)hipEventRecord(ev1, stream);
   if (b.precision == RT_FP64)
@@ -362,21 +456,23 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     b.total_pairs += in.tracks.n * in.det.n_antennas;
   }
   b.lds_bytes = (size_t)std::max<int64_t>(max_slot, 1) * sizeof(acc_t);
+  // the run-time-switched kernels hold two waves per SIMD (512 threads per
+  // CU), the one-antenna kernels four (1024 threads)
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(lds_cu / (b.lds_bytes + 256),
-                                                               512 / b.block));
+                                                               512 / std::min(b.block, 512)));
   b.grid = num_cus * per_cu;
   // Track splits: items of similar cost (track x antenna evaluations, which
   // every bin segment repeats), about items_per_cu of them per compute unit,
   // counted apart for the two deposit kernels (their pairs cost differently).
-  double group_cost[2] = {0.0, 0.0};
+  double group_cost[kGroups] = {0.0, 0.0, 0.0};
   for (const ShowerDesc &d : b.sh)
-    group_cost[is_heavy(d.c.medium)] += (double)d.n_blocks * 64 * d.at * d.n_atiles * d.n_segs;
+    group_cost[item_group(b, d)] += (double)d.n_blocks * 64 * d.at * d.n_atiles * d.n_segs;
   b.cum.assign(n + 1, 0);
   for (int s = 0; s < n; ++s) {
     ShowerDesc &d = b.sh[s];
     const rt_tiling *user = (opt && opt->per_shower) ? &opt->per_shower[s] : nullptr;
     const double target =
-        std::max(1.0, group_cost[is_heavy(d.c.medium)] / ((double)b.grid * items_per_cu));
+        std::max(1.0, group_cost[item_group(b, d)] / ((double)b.grid * items_per_cu));
     int64_t splits = user && user->track_splits > 0
                          ? user->track_splits
                          : (int64_t)std::ceil((double)d.n_blocks * 64 * d.at / target);
@@ -405,18 +501,21 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
         }
   }
   if (all.size() > (size_t)INT32_MAX - 1024) return "too many work items";
-  auto heavy = [&b](const WorkItem &w) { return is_heavy(b.sh[w.shower].c.medium); };
+  auto group = [&b](const WorkItem &w) { return item_group(b, b.sh[w.shower]); };
   std::stable_sort(all.begin(), all.end(),
-                   [&heavy](const std::pair<int64_t, WorkItem> &x,
+                   [&group](const std::pair<int64_t, WorkItem> &x,
                             const std::pair<int64_t, WorkItem> &y) {
-                     const bool hx = heavy(x.second), hy = heavy(y.second);
-                     return hx != hy ? hy : x.first > y.first;
+                     const int gx = group(x.second), gy = group(y.second);
+                     return gx != gy ? gx < gy : x.first > y.first;
                    });
   b.items.reserve(all.size());
+  int64_t count[kGroups] = {0, 0, 0};
   for (auto &x : all) {
     b.items.push_back(x.second);
-    if (!heavy(x.second)) ++b.n_light;
+    ++count[group(x.second)];
   }
+  b.group_begin[0] = 0;
+  for (int g = 0; g < kGroups; ++g) b.group_begin[g + 1] = b.group_begin[g] + (int32_t)count[g];
   for (int s = 0; s < n; ++s) {
     if (b.sh[s].n_blocks == 0) continue;
     for (int64_t a = 0; a < b.sh[s].an.m; ++a)
@@ -457,13 +556,18 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
   if (!batch) return rt_fail(RT_E_INVALID, "batch output pointer is NULL");
   *batch = nullptr;
   if (!showers || n_showers < 1) return rt_fail(RT_E_INVALID, "need at least one shower");
+  const bool one_antenna = options && options->block_threads == 1024;
   if (options) {
     const int bt = options->block_threads;
-    if (bt != 0 && (bt < 64 || bt > 512 || bt % 64))
-      return rt_fail(RT_E_INVALID, "block_threads must be a multiple of 64 in [64, 512]");
+    if (bt != 0 && bt != 1024 && (bt < 64 || bt > 512 || bt % 64))
+      return rt_fail(RT_E_INVALID,
+                     "block_threads must be a multiple of 64 in [64, 512], or 1024 with "
+                     "max_antennas_per_tile 1");
     if (options->items_per_cu < 0) return rt_fail(RT_E_INVALID, "items_per_cu must be >= 0");
     if (options->max_antennas_per_tile < 0 || options->max_antennas_per_tile > 3)
       return rt_fail(RT_E_INVALID, "max_antennas_per_tile must be in [0, 3]");
+    if (one_antenna && options->max_antennas_per_tile != 1)
+      return rt_fail(RT_E_INVALID, "block_threads 1024 needs max_antennas_per_tile 1");
   }
   for (int32_t s = 0; s < n_showers; ++s) {
     const rt_shower &sh = showers[s];
@@ -481,6 +585,8 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
           (t.bins_per_segment > 0 && t.bins_per_segment % 64 && t.bins_per_segment != sh.det.n_bins))
         return rt_fail(RT_E_INVALID, where + "per-shower tiling out of range (antennas_per_block "
                                              "0-3, bins_per_segment a multiple of 64 or n_bins)");
+      if (one_antenna && t.antennas_per_block > 1)
+        return rt_fail(RT_E_INVALID, where + "block_threads 1024 takes one-antenna tiles only");
     }
   }
   int dev = 0, cus = 0;
@@ -501,10 +607,12 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
   if (e == hipSuccess) e = rt::upload(&b->d_items, b->items);
   if (e == hipSuccess) e = rt::upload(&b->d_merges, b->merges);
   if (e == hipSuccess) e = rt::upload(&b->d_cum, b->cum);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(int));
-  for (int heavy = 0; heavy < 2 && e == hipSuccess; ++heavy)
-    e = hipFuncSetAttribute(rt::deposit_fn(precision, heavy),
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, rt::kGroups * sizeof(int));
+  for (int g = 0; g < rt::kGroups && e == hipSuccess; ++g) {
+    int threads = 0;
+    e = hipFuncSetAttribute((const void *)rt::deposit_fn(*b, g, &threads),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes);
+  }
   if (e == hipSuccess && !b->direct) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     rt::release(b);

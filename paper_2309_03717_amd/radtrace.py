@@ -461,8 +461,9 @@ def _medium_struct(medium, table: Optional[torch.Tensor] = None) -> rt_medium:
 @dataclass
 class BatchOptions:
     """Launch shape of a batch (rt_batch_options); 0 keeps the automatic
-    choice. per_shower: None or a list of (antennas_per_block, track_splits,
-    bins_per_segment) per shower."""
+    choice. block_threads 1024 (with max_antennas_per_tile 1) runs one-antenna
+    tiles in one kernel per formalism. per_shower: None or a list of
+    (antennas_per_block, track_splits, bins_per_segment) per shower."""
     block_threads: int = 0
     items_per_cu: int = 0
     max_antennas_per_tile: int = 0

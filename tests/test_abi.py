@@ -114,9 +114,10 @@ def _shower(rt):
     return rt.rt_shower(det, med, rt.RT_ENDPOINT, rt.rt_tracks(), None), keep
 
 
-@pytest.mark.parametrize("case", ["null_showers", "zero_showers", "bad_block", "bad_at",
-                                  "bad_items", "bad_detector", "bad_formalism", "null_traces",
-                                  "bad_per_shower", "bad_precision"])
+@pytest.mark.parametrize("case", ["null_showers", "zero_showers", "bad_block", "bad_block_768",
+                                  "bad_at", "bad_items", "bad_detector", "bad_formalism",
+                                  "null_traces", "bad_per_shower", "one_antenna_wide_tile",
+                                  "bad_precision"])
 def test_batch_create_rejects_invalid_arguments(rt, case):
     sh, keep = _shower(rt)
     arr = (rt.rt_shower * 2)(sh, sh)
@@ -127,8 +128,11 @@ def test_batch_create_rejects_invalid_arguments(rt, case):
         arr = None
     elif case == "zero_showers":
         n = 0
-    elif case == "bad_block":
+    elif case == "bad_block":   # 1024 threads take one-antenna tiles only
         opt.block_threads = 1024
+    elif case == "bad_block_768":
+        opt.block_threads = 768
+        opt.max_antennas_per_tile = 1
     elif case == "bad_at":
         opt.max_antennas_per_tile = 4
     elif case == "bad_items":
@@ -143,13 +147,18 @@ def test_batch_create_rejects_invalid_arguments(rt, case):
     elif case == "bad_per_shower":
         tl[1].bins_per_segment = 100
         opt.per_shower = C.cast(tl, C.POINTER(rt.rt_tiling))
+    elif case == "one_antenna_wide_tile":
+        opt.block_threads = 1024
+        opt.max_antennas_per_tile = 1
+        tl[1].antennas_per_block = 2
+        opt.per_shower = C.cast(tl, C.POINTER(rt.rt_tiling))
     elif case == "bad_precision":
         precision = 2
     handle = C.c_void_p()
     st = rt._lib.rt_batch_create(C.byref(handle), arr, n, precision, 1.0, C.byref(opt))
     assert st == rt.RT_E_INVALID, rt.rt_last_error()
     assert handle.value is None
-    if case in ("bad_detector", "null_traces", "bad_per_shower"):
+    if case in ("bad_detector", "null_traces", "bad_per_shower", "one_antenna_wide_tile"):
         assert rt.rt_last_error().startswith("shower 1:")
 
 

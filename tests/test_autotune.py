@@ -54,3 +54,45 @@ def test_signature_depends_on_every_shape():
     c = autotune.signature([("endpoint", "uniform", 16, 2048, 1000)])
     assert len({a, b, c}) == 3
     assert a == autotune.signature([("zhs", "uniform", 16, 2048, 1000)])
+
+
+def test_finalists_are_timed_again_on_the_whole_workload(tmp_path):
+    """The sample ranks (1024, 1) first by a hair; the whole workload ranks
+    (512, 3) first: the final stage re-times the three best and takes its
+    winner, and never times the fourth."""
+    sample = {(1024, 1): 1.00, (512, 3): 1.01, (512, 2): 1.02, (256, 1): 2.0}
+    whole = {(1024, 1): 10.3, (512, 3): 10.0, (512, 2): 10.2, (256, 1): 1.0}
+    finals = []
+
+    def final(c):
+        finals.append(tuple(c))
+        return whole[tuple(c)]
+
+    cands = [[256, 1], [512, 2], [512, 3], [1024, 1]]
+    best, timings, cached = autotune.tune("f", cands, lambda c: sample[tuple(c)],
+                                          autotune.TuningCache(str(tmp_path / "f.json")),
+                                          final_measure=final)
+    assert best == [512, 3] and not cached
+    assert sorted(finals) == [(512, 2), (512, 3), (1024, 1)]
+    best2, _, _ = autotune.tune("g", cands, lambda c: sample[tuple(c)],
+                                autotune.TuningCache(str(tmp_path / "g.json")))
+    assert best2 == [1024, 1]   # without the final stage the sample decides
+
+
+def test_finalists_come_from_distinct_families(tmp_path):
+    """Three variants of one family lead the sample; the final stage takes
+    only the best of them and goes on to the next families."""
+    sample = {(1024, 1, 2): 1.00, (1024, 1, 4): 1.001, (1024, 1, 8): 1.002,
+              (512, 3, 2): 1.01, (512, 2, 2): 1.02, (256, 1, 2): 1.03}
+    whole = {(1024, 1, 2): 10.3, (512, 3, 2): 10.0, (512, 2, 2): 10.2}
+    finals = []
+
+    def final(c):
+        finals.append(tuple(c))
+        return whole[tuple(c)]
+
+    best, _, _ = autotune.tune("h", [list(c) for c in sample], lambda c: sample[tuple(c)],
+                               autotune.TuningCache(str(tmp_path / "h.json")),
+                               final_measure=final, family=lambda c: (c[0], c[1]))
+    assert best == [512, 3, 2]
+    assert finals == [(1024, 1, 2), (512, 3, 2), (512, 2, 2)]

@@ -147,7 +147,8 @@ def test_heavy_media_batch_matches_oracle(rt, orc, precision):
 
 
 HEAVY_OPTIONS = [dict(), dict(items_per_cu=64, max_antennas_per_tile=1),
-                 dict(block_threads=128, direct_launch=1)]
+                 dict(block_threads=128, direct_launch=1),
+                 dict(block_threads=1024, max_antennas_per_tile=1)]
 
 
 @pytest.mark.parametrize("opt", HEAVY_OPTIONS, ids=[str(o) for o in HEAVY_OPTIONS])
@@ -183,6 +184,8 @@ def test_batch_equals_single_plans(rt, precision):
 OPTIONS = [
     dict(block_threads=256),
     dict(block_threads=64, items_per_cu=1),
+    dict(block_threads=1024, max_antennas_per_tile=1),
+    dict(block_threads=1024, max_antennas_per_tile=1, items_per_cu=1, direct_launch=1),
     dict(items_per_cu=64),
     dict(max_antennas_per_tile=1),
     dict(max_antennas_per_tile=2, direct_launch=1),
