@@ -276,15 +276,15 @@ vjp_kernel(VjpArgs v) {
       const double d[3] = {ax - mx, ay - my, az - mz};
       const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
       if (r2 == 0.0) continue;
-      const double r = sqrt(r2);
-      const double ir = 1.0 / r, ir2 = ir * ir;
+      // mixed precision: refined hardware estimates (about 1e-15 relative)
+      const double ir = P == 0 ? 1.0 / sqrt(r2) : fast_rsq(r2), ir2 = ir * ir;
       const double bd = (b[0] * d[0] + b[1] * d[1]) + b[2] * d[2];
       double iu[3];   // integral per unit weight
       for (int k = 0; k < 3; ++k) iu[k] = kdt * (b[k] - bd * ir2 * d[k]) * ir;
       const double *edges = v.phi + (size_t)a * kEdge * (c.n_bins + 1);
       const EdgeValues lo(edges, c.n_bins, c.nbins_d, ulo), hi(edges, c.n_bins, c.nbins_d, uhi);
       const bool same_bin = floor(ulo) == floor(uhi);
-      const double iw = 1.0 / (uhi - ulo);
+      const double iw = P == 0 ? 1.0 / (uhi - ulo) : fast_rcp(uhi - ulo);
       double gbar[3], dl_dlo = 0.0, dl_dhi = 0.0;
       for (int k = 0; k < 3; ++k) {
         if (same_bin) {
@@ -317,7 +317,8 @@ vjp_kernel(VjpArgs v) {
       const double dl_ds = (start_lo ? dl_dlo : dl_dhi) * c.inv_dt * c.inv_c;
       const double dl_de = (start_lo ? dl_dhi : dl_dlo) * c.inv_dt * c.inv_c;
       // d (n_eff R) / d P = -n_eff d / R + R grad n_eff
-      const double n0r = ne0 / r0, n1r = ne1 / r1;
+      const double n0r = P == 0 ? ne0 / r0 : ne0 * fast_rcp(r0);
+      const double n1r = P == 0 ? ne1 / r1 : ne1 * fast_rcp(r1);
       gp0[0] += dl_ds * (-n0r * d0x + r0 * gn0[0]);
       gp0[1] += dl_ds * (-n0r * d0y + r0 * gn0[1]);
       gp0[2] += dl_ds * (-n0r * d0z + r0 * gn0[2]);
@@ -399,7 +400,8 @@ __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
         const int j = (int)u;
         const double g[3] = {(double)ga[3 * j], (double)ga[3 * j + 1], (double)ga[3 * j + 2]};
         const double s = e == 0 ? 1.0 : -1.0;
-        const double ir2 = 1.0 / r2, ir = r * ir2, inum = 1.0 / num;
+        const double ir2 = P == 0 ? 1.0 / r2 : fast_rcp(r2), ir = r * ir2;
+        const double inum = P == 0 ? 1.0 / num : fast_rcp(num);
         const double q = bd * ir2;
         double w[3];
         for (int k = 0; k < 3; ++k) w[k] = fma(d[k], q, -b[k]);

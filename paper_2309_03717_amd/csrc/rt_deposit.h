@@ -194,17 +194,6 @@ __device__ __forceinline__ void put3_clamped(acc_t *row, int j, int lo, int hi, 
   if (j < hi) put3(row, j - lo, vx, vy, vz);
 }
 
-// 1/x and 1/sqrt(x) from the hardware estimate plus one Newton step.
-__device__ __forceinline__ double fast_rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-__device__ __forceinline__ double fast_rsq(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  double h = fma(-0.5 * x * y, y, 1.5);
-  return y * h;
-}
 
 // Endpoint impulse of one track end at one antenna: s k qw [r x (r x beta)] /
 // ((1 - n_src beta.r) R dt), evaluated as sc (d (beta.d) / R^2 - beta) / num

@@ -157,6 +157,19 @@ __device__ __forceinline__ double path_index(double zp, double za, double pp, do
   return 1.0 + c.n0m1 * exp(-(((zp + za) * 0.5) / c.h));
 }
 
+// 1/x and 1/sqrt(x) from the hardware estimate plus one Newton step (about
+// 1e-15 relative; the mixed-precision amplitudes and adjoints use them).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double fast_rsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = fma(-0.5 * x * y, y, 1.5);
+  return y * h;
+}
+
 // Correctly rounded sqrt: the hardware reciprocal square root refined by
 // Newton steps (the same operations as the compiler's own expansion, without
 // its range scaling); inputs outside (2^-767, inf) take the library sqrt.
