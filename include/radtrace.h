@@ -69,7 +69,7 @@ typedef enum { RT_ENDPOINT = 0, RT_ZHS = 1 } rt_formalism;
 typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
 
 /* Refractive-index model of the environment the propagator is built from
- * (§2, Listing 2; "media with varying properties", §1):
+ * (§2, Listing 2; media whose properties vary, §1):
  *   RT_UNIFORM:     n(z) = 1 + n0_minus_1
  *   RT_EXPONENTIAL: n(z) = 1 + n0_minus_1 * exp(-z / scale_height)
  *   RT_TABULATED:   n(z) = 1 + n0_minus_1 * f(z), f piecewise linear through

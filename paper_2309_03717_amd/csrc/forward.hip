@@ -3,7 +3,7 @@
 // track records, a fixed-order merge of track-split partials (with the ZHS
 // prefix scan), and the propagator alone.
 //
-// Work decomposition (the analogue of §4's "bunch of antennas" per task): a
+// Work decomposition (the analogue of the antenna bunch a thread takes in §4): a
 // workgroup owns a tile of up to kMaxTile antennas x one segment of bins in
 // LDS and streams one range ("split") of the tracks past it; each lane takes
 // one track and loops over the tile's antennas, so track loads are coalesced
