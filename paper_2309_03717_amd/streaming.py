@@ -28,8 +28,9 @@ class HostTrackStream:
     elements (positions and times float64; velocities and weights float64 for
     FP64 plans, float32 for mixed ones); ``traces`` holds one trace tensor per
     plan, to which the chunk's traces are added. The deposits are enqueued on
-    the current stream, the copy on the object's copy stream, and push returns
-    at once: the caller leaves each pushed host chunk unchanged until
+    the current stream (the caller orders that stream after any other stream
+    that uses the same trace tensors), the copy on the object's copy stream,
+    and push returns at once: the caller leaves each pushed host chunk unchanged until
     ``synchronize`` returns (dropping the tensors early is safe: torch's pinned
     allocator reuses a block only after the copies that read it).
     """

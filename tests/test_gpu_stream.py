@@ -45,9 +45,18 @@ def test_streamed_chunks_equal_resident_and_oracle(rt, orc, precision):
             p.accumulate(dt, tr)
     streamed = [p.new_traces() for p in plans]
     st = S.HostTrackStream(plans, CHUNK)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
     for rep in range(2):   # two passes: the buffers are reused across calls
-        for part in parts:
-            st.push(S.pinned_chunk(part), streamed)
+        # the second pass runs with another current stream: the stream's own
+        # copies and buffer reuse order through its events; the traces both
+        # passes add to are the caller's, so the caller orders the two streams
+        if rep == 1:
+            side.wait_stream(main)
+        with torch.cuda.stream(side if rep == 1 else main):
+            for part in parts:
+                st.push(S.pinned_chunk(part), streamed)
     st.synchronize()
     torch.cuda.synchronize()
     allt = W.Tracks.concat(parts)
