@@ -245,7 +245,7 @@ def bench_batched(args):
         import oracle
         oracle._load()
         cores = max(1, min(len(os.sched_getaffinity(0)), 16))
-        k = min(16, len(showers))
+        k = min(args.cpu_sample or 48, len(showers))
         t1 = time.perf_counter()
         cpu_pairs = 0
         for sh, d in zip(showers[:k], dev[:k]):
@@ -375,7 +375,7 @@ def bench_adjoint(args):
                       "precision": "mixed"},
            "per_formalism": per}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_adjoint(w, min(args.cpu_sample, n), grad)
+        out["cpu_baseline"] = cpu_baseline_adjoint(w, min(args.cpu_sample or (1 << 19), n), grad)
     print(json.dumps(out), flush=True)
 
 
@@ -424,7 +424,7 @@ def bench_oracle(args):
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
     w = W.config(2)
-    tr = w.tracks(args.cpu_sample).to_mixed().widened()
+    tr = w.tracks(args.cpu_sample or (1 << 14)).to_mixed().widened()
     pairs = tr.n * w.array.m
     runs = []
     sweep = sorted({1, 2, 4, 8, 16} & set(range(1, cores + 1)) | {cores})
@@ -595,7 +595,11 @@ def main():
     ap.add_argument("--tracks", type=int, default=None,
                     help="override the track count (smaller runs for profiling)")
     ap.add_argument("--formalisms", default="endpoint,zhs")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 17)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="tracks (showers for batched) the CPU oracle baseline runs on; "
+                         "defaults sized for about 10-15 s of oracle work on 16 threads: "
+                         "grid 2^19 tracks (2^18 over the spherical Earth), adjoint 2^19 "
+                         "tracks, batched 48 showers, oracle sweep 2^14 tracks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
     ap.add_argument("--workload", default="grid4096",
@@ -768,7 +772,9 @@ def main():
                                w.array.m, {f: out["per_formalism"][f]["pairs_per_s"]
                                            for f in formalisms})
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample, n_total), medium)
+        # the spherical medium's oracle takes ~2.5x longer per pair
+        default = 1 << 18 if args.medium == "spherical" else 1 << 19
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample or default, n_total), medium)
     print(json.dumps(out), flush=True)
 
 
