@@ -64,7 +64,7 @@ FP32_PEAK_PUBLISHED = 157.3e12
 # the copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
 # they were taken on (hash below); otherwise the bench reports null.
 TRAFFIC_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
-TRAFFIC_HASH = "0626c49b20e79c00"
+TRAFFIC_HASH = "b4293e667d1120af"
 TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.5, "write": 1048576.0 / 1048576.0}
 TRAFFIC_KIB = {"endpoint": {"fetch": 9145407.8, "write": 393216.0},
                "zhs": {"fetch": 18267371.3, "write": 3145728.0}}

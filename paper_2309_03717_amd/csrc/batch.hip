@@ -93,7 +93,7 @@ __device__ __forceinline__ T uniform(T x) {
 
 // The constants of a shower as the kernels use them (wave-uniform): a
 // tabulated medium reads its F table from the workspace. The quadrature
-// nodes stay as loaded (the spherical path mean indexes them).
+// nodes are not used from here: the deposits read the LDS copy (LdsNodes).
 __device__ __forceinline__ Consts shower_consts(const ShowerDesc &s, const BatchArgs &b) {
   Consts c = s.c;
   if (c.medium == 2) c.tabF = b.tables + s.tab_off;
@@ -152,18 +152,28 @@ __global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
   }
 }
 
+// The quadrature nodes and weights of a spherical shower, copied to LDS for
+// the item (kGl nodes, then kGl weights): every lane reads the same node, so
+// the reads are broadcasts, and the constants copied per item need no
+// dynamically indexed array.
+struct LdsNodes {
+  const double *p;
+  __device__ __forceinline__ double s(int k) const { return p[k]; }
+  __device__ __forceinline__ double w(int k) const { return p[kGl + k]; }
+};
+
 // The deposits of one work item into the LDS tile.
 template <int F, int P, int MED, int AT>
 __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int64_t b_end,
                                          const AntPtrs &an, const Consts &c, acc_t *tile,
                                          int64_t a_begin, int n_ant, int row_len, int lo,
-                                         int hi) {
+                                         int hi, const double *nodes) {
   Tile<AT> t;
   load_tile<AT, MED>(an, a_begin, n_ant, c, t);
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
   deposit_blocks<F, P, MED, AT, MED != 3>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
-                                          hi, (double)lo, (double)hi, c);
+                                          hi, (double)lo, (double)hi, c, LdsNodes{nodes});
 }
 
 // Tile width switch; ATMAX = 1 compiles the one-antenna path only.
@@ -171,13 +181,16 @@ template <int ATMAX, int F, int P, int MED>
 __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b_first,
                                             int64_t b_end, const AntPtrs &an, const Consts &c,
                                             acc_t *tile, int64_t a_begin, int n_ant, int row_len,
-                                            int lo, int hi) {
+                                            int lo, int hi, const double *nodes) {
   if (ATMAX == 1 || at == 1)
-    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi,
+                           nodes);
   else if (at == 2)
-    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi,
+                           nodes);
   else
-    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi);
+    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi,
+                           nodes);
 }
 
 // Persistent workgroups: take the items of one group until its counter
@@ -186,9 +199,10 @@ __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b
 // HEAVY: the group's two media (0: uniform, exponential; 1: tabulated,
 // spherical). FF: the one formalism compiled in, or -1 for a run-time switch
 // between both. ATMAX: the widest tile compiled in (1 or 3).
+// nodes: 2 kGl doubles of LDS for a spherical shower's quadrature rule.
 template <int P, int HEAVY, int FF, int ATMAX>
-__device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t *tile,
-                                           int *cur) {
+__device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t *tile, int *cur,
+                                           double *nodes) {
   const int first = b.group_begin[group], last = b.group_begin[group + 1];
   for (;;) {
     __syncthreads();   // everyone has read cur and flushed the previous tile
@@ -212,6 +226,9 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t 
     const int hi = min(lo + seg_len, c.n_bins);
     const int row_len = (hi - lo) * 3;
     for (int i = threadIdx.x; i < at * row_len; i += blockDim.x) tile[i] = 0.0;
+    if (HEAVY && c.medium == 3 && threadIdx.x < 2 * kGl)
+      nodes[threadIdx.x] =
+          threadIdx.x < kGl ? sd.c.gl_s[threadIdx.x] : sd.c.gl_w[threadIdx.x - kGl];
     __syncthreads();
     const double *rec = b.rec + uniform(sd.rec_block0) * (kRec * 64);
     const int64_t per_split = uniform(sd.blocks_per_split);
@@ -223,17 +240,17 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t 
     if (FF != 1 && f == 0) {
       if (m1)
         run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi);
+                                     row_len, lo, hi, nodes);
       else
         run_item_at<ATMAX, 0, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi);
+                                     row_len, lo, hi, nodes);
     } else if (FF != 0) {
       if (m1)
         run_item_at<ATMAX, 1, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi);
+                                     row_len, lo, hi, nodes);
       else
         run_item_at<ATMAX, 1, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi);
+                                     row_len, lo, hi, nodes);
     }
     __syncthreads();
     const int64_t slot_len = uniform(sd.slot_len);
@@ -255,8 +272,9 @@ template <int P, int HEAVY>
 __global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int cur;
+  __shared__ double nodes[HEAVY ? 2 * kGl : 1];
   take_items<P, HEAVY, -1, 3>(b, HEAVY ? kGroupHeavy : kGroupLight,
-                              reinterpret_cast<acc_t *>(smem), &cur);
+                              reinterpret_cast<acc_t *>(smem), &cur, nodes);
 }
 
 // One-antenna tiles of the uniform and exponential media in one formalism F
@@ -268,7 +286,7 @@ __global__ void __launch_bounds__(1024) batch_deposit_one_kernel(BatchArgs b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int cur;
   take_items<P, 0, F, 1>(b, F == 0 ? kGroupLight : kGroupLightZhs,
-                         reinterpret_cast<acc_t *>(smem), &cur);
+                         reinterpret_cast<acc_t *>(smem), &cur, nullptr);
 }
 
 // One workgroup per (shower, antenna, segment): traces += sum over the

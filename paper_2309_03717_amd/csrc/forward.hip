@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   // record prefetch where delivery bounds the loop: the Endpoint deposit,
   // except over the spherical Earth, whose per-pair quadrature dominates
   deposit_blocks<F, P, MED, AT, F == 0 && MED != 3>(g.rec, b_first, b_end, waves, mask, t, tile,
-                                                    row_len, lo, hi, lo_d, hi_d, g.c);
+                                                    row_len, lo, hi, lo_d, hi_d, g.c,
+                                                    ConstNodes{g.c});
   __syncthreads();
 
   acc_t *dst = reinterpret_cast<acc_t *>(g.partial);

@@ -274,10 +274,12 @@ struct Tile {
 // antennas selected by mask.
 // H: the height factors were loaded (deposit_blocks loads them where they are
 // used).
-template <int F, int P, int MED, int AT, bool H>
+// Nodes: where the spherical path mean reads its quadrature nodes.
+template <int F, int P, int MED, int AT, bool H, class Nodes>
 __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, const Tile<AT> &t,
                                                acc_t *tile, int row_len, int lo, int hi,
-                                               double lo_d, double hi_d, const Consts &c) {
+                                               double lo_d, double hi_d, const Consts &c,
+                                               const Nodes &nd) {
   const double x0 = v[R_X0], y0 = v[R_Y0], z0 = v[R_Z0], t0 = v[R_T0];
   const double x1 = v[R_X1], y1 = v[R_Y1], z1 = v[R_Z1], t1 = v[R_T1];
   constexpr bool kOff = MED != 0 && H;   // off-reference antennas can be handled
@@ -310,8 +312,8 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
         double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
         double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
         if (MED == 3) {
-          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
-          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
+          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c, nd);
+          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c, nd);
         } else if (kOff && !t.at_ref[a]) {
           const double p0 = MED == 2 ? tab_F(z0, c) : e0;
           const double p1 = MED == 2 ? tab_F(z1, c) : e1;
@@ -335,8 +337,8 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
         double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
         double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
         if (MED == 3) {
-          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c);
-          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c);
+          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c, nd);
+          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c, nd);
         } else if (kOff && !t.at_ref[a]) {
           const double p0 = MED == 2 ? tab_F(z0, c) : e0;
           const double p1 = MED == 2 ? tab_F(z1, c) : e1;
@@ -362,12 +364,12 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 // (the Endpoint deposit) or few waves share a SIMD (the 512-thread batch
 // kernel); the single-plan ZHS deposit, with more arithmetic per record and
 // four waves per SIMD, runs faster without the register copies it costs.
-template <int F, int P, int MED, int AT, bool H, bool PF>
+template <int F, int P, int MED, int AT, bool H, bool PF, class Nodes>
 __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_first,
                                                  int64_t b_end, int64_t waves, uint64_t mask,
                                                  const Tile<AT> &t, acc_t *tile, int row_len,
                                                  int lo, int hi, double lo_d, double hi_d,
-                                                 const Consts &c) {
+                                                 const Consts &c, const Nodes &nd) {
   const int lane = threadIdx.x & 63;
   if (!PF) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
@@ -379,7 +381,7 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
 #pragma unroll
         for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
       }
-      deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
+      deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c, nd);
     }
     return;
   }
@@ -410,27 +412,28 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
           if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
       }
     }
-    deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c);
+    deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c, nd);
   }
 }
 
 // As deposit_blocks_n, reading the height factors only where they are used:
 // the Endpoint source index in non-uniform media, and tiles with an antenna off
 // the reference height (whose path index is taken per pair from them).
-template <int F, int P, int MED, int AT, bool PF>
+template <int F, int P, int MED, int AT, bool PF, class Nodes>
 __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
                                                int64_t waves, uint64_t mask, const Tile<AT> &t,
                                                acc_t *tile, int row_len, int lo, int hi,
-                                               double lo_d, double hi_d, const Consts &c) {
+                                               double lo_d, double hi_d, const Consts &c,
+                                               const Nodes &nd) {
   bool off = false;
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
   if (MED == 3 ? F == 0 : MED != 0 && (F == 0 || off))
     deposit_blocks_n<F, P, MED, AT, true, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
-                                              lo, hi, lo_d, hi_d, c);
+                                              lo, hi, lo_d, hi_d, c, nd);
   else
     deposit_blocks_n<F, P, MED, AT, false, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
-                                               lo, hi, lo_d, hi_d, c);
+                                               lo, hi, lo_d, hi_d, c, nd);
 }
 
 // Loads the tile antennas [a_begin, a_begin + n_ant) (uniform per workgroup).

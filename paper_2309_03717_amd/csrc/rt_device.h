@@ -201,12 +201,23 @@ __device__ __forceinline__ double sph_factor(double x, double y, double z, const
   return exp(-sph_exponent((x * x + y * y) + z * (z + c.re_twice), c));
 }
 
+// The quadrature nodes and weights of the spherical path mean as the
+// constants hold them (a single plan's kernel arguments).
+struct ConstNodes {
+  const Consts &c;
+  __device__ __forceinline__ double s(int k) const { return c.gl_s[k]; }
+  __device__ __forceinline__ double w(int k) const { return c.gl_w[k]; }
+};
+
 // Path mean of n over the straight path from P to the antenna X (spherical
 // Earth): 1 + n0m1 * (sum over the nodes of w_k * exp(-(H(q_k) / h))), the
 // nodes taken in ascending order. Along q = P + s d (d = X - P), rho2 is the
 // quadratic A + s (B + s D) with A = rho2(P), B = 2 (P - C).d, D = d.d.
+// Nodes: where the nodes and weights are read from (s(k), w(k)).
+template <class Nodes>
 __device__ __forceinline__ double sph_path_index(double px, double py, double pz, double ax,
-                                                 double ay, double az, const Consts &c) {
+                                                 double ay, double az, const Consts &c,
+                                                 const Nodes &nd) {
   const double dx = ax - px, dy = ay - py, dz = az - pz;
   const double qa = (px * px + py * py) + pz * (pz + c.re_twice);
   const double qb = 2.0 * ((px * dx + py * dy) + (pz + c.re) * dz);
@@ -214,10 +225,15 @@ __device__ __forceinline__ double sph_path_index(double px, double py, double pz
   double s = 0.0;
 #pragma unroll 1
   for (int k = 0; k < kGl; ++k) {
-    const double sk = c.gl_s[k];
-    s = s + c.gl_w[k] * exp(-sph_exponent(qa + sk * (qb + sk * qd), c));
+    const double sk = nd.s(k);
+    s = s + nd.w(k) * exp(-sph_exponent(qa + sk * (qb + sk * qd), c));
   }
   return 1.0 + c.n0m1 * s;
+}
+
+__device__ __forceinline__ double sph_path_index(double px, double py, double pz, double ax,
+                                                 double ay, double az, const Consts &c) {
+  return sph_path_index(px, py, pz, ax, ay, az, c, ConstNodes{c});
 }
 
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an
