@@ -381,10 +381,12 @@ static BatchKernel deposit_fn(const rt_batch &b, int group, int *threads) {
   const bool one = b.block == 1024 && group != kGroupHeavy;
   *threads = one ? 1024 : std::min(b.block, 512);
   if (b.precision == RT_FP64) {
-    if (one) return group == kGroupLight ? batch_deposit_one_kernel<0, 0> : batch_deposit_one_kernel<0, 1>;
+    if (one)
+      return group == kGroupLight ? batch_deposit_one_kernel<0, 0> : batch_deposit_one_kernel<0, 1>;
     return group == kGroupHeavy ? batch_deposit_kernel<0, 1> : batch_deposit_kernel<0, 0>;
   }
-  if (one) return group == kGroupLight ? batch_deposit_one_kernel<1, 0> : batch_deposit_one_kernel<1, 1>;
+  if (one)
+    return group == kGroupLight ? batch_deposit_one_kernel<1, 0> : batch_deposit_one_kernel<1, 1>;
   return group == kGroupHeavy ? batch_deposit_kernel<1, 1> : batch_deposit_kernel<1, 0>;
 }
 
