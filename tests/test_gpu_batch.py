@@ -290,6 +290,41 @@ def test_empty_nonfinite_and_odd_showers(rt, orc):
         assert rel_l2(got[i], ref).max() <= FP64_BOUND, i
 
 
+@pytest.mark.parametrize("opt", [dict(), dict(block_threads=1024, max_antennas_per_tile=1)],
+                         ids=["default", "one-antenna"])
+def test_heavy_media_empty_and_nonfinite_showers(rt, orc, opt):
+    """Heavier-media showers that are empty or carry non-finite tracks, next
+    to a light shower whose group is then the only non-empty light one:
+    empty showers stay zero, the others match the oracle (the bad tracks
+    contribute nothing), and a batch whose only heavy shower is empty
+    launches no heavy kernel."""
+    mix = heavy_mix()
+    lay, sph, light = mix[1], mix[2], mix[0]
+    tr_lay = host_tracks(lay, "fp64")
+    bad = tr_lay.arrays()
+    bad["z0"] = bad["z0"].copy()
+    bad["z0"][::4] = np.nan
+    bad["qw"] = bad["qw"].copy()
+    bad["qw"][2::7] = np.inf
+    bad_tr = W.Tracks(**bad)
+    empty_sph = host_tracks(sph, "fp64").slice(0, 0)
+    light_tr = host_tracks(light, "fp64")
+    showers = [lay, sph, light, sph]
+    tracks = [bad_tr, empty_sph, light_tr, host_tracks(sph, "fp64")]
+    dev = device_showers(rt, showers, "fp64", tracks)
+    got = fetch(rt.Batch(dev, "fp64", options=rt.BatchOptions(**opt)).launch())
+    assert not np.any(got[1])
+    for i in (0, 2, 3):
+        ref = oracle_of(orc, showers[i], tracks[i], "fp64")
+        assert np.all(np.isfinite(got[i])) and np.abs(ref).max() > 0
+        assert rel_l2(got[i], ref).max() <= FP64_BOUND, i
+    only_empty = fetch(rt.Batch(device_showers(rt, [light, sph], "fp64",
+                                               [light_tr, empty_sph]), "fp64").launch())
+    assert not np.any(only_empty[1])
+    ref = oracle_of(orc, light, light_tr, "fp64")
+    assert rel_l2(only_empty[0], ref).max() <= FP64_BOUND
+
+
 def test_all_empty_batch_is_a_noop(rt):
     sh = small_showers(2, 10)
     tr = [host_tracks(s, "fp64").slice(0, 0) for s in sh]
