@@ -525,7 +525,9 @@ hipError_t launch_vjp(const rt_plan &p, const rt_tracks &t, const void *grad, do
   v.n0_part = part;
   const int64_t blocks = (t.n + kVjpBlock - 1) / kVjpBlock;
   const int kind = p.formalism * 8 + p.precision * 4 + p.med.kind;
-  vjp_kernel_for(kind)<<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
+  // no tracks: no per-track launch (a grid of zero workgroups is not a
+  // valid launch); the n0 - 1 gradient is then the empty sum, 0
+  if (blocks > 0) vjp_kernel_for(kind)<<<(unsigned)blocks, kVjpBlock, 0, stream>>>(v);
   n0_sum_kernel<<<1, 256, 0, stream>>>(part, blocks, g_n0);
   return hipGetLastError();
 }

@@ -346,3 +346,52 @@ def test_autograd_with_a_spherical_medium(rt, orc):
     print("autograd spherical", {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= 1e-9, (k, v)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formalism", ["zhs", "endpoint"])
+def test_vjp_invalid_degenerate_and_empty_tracks(rt, orc, formalism, precision):
+    """Tracks with non-finite fields get zero gradients and change nothing
+    else; a zero-length track (t1 = t0, p1 = p0) and a track with beta = 0 go
+    through the same definitions as in the oracle; a call with no tracks
+    returns empty per-track gradients and a zero n0 - 1 gradient."""
+    import torch
+    w = W.config(3)
+    a = w.tracks(600).arrays()
+    for f in a:
+        a[f] = a[f].copy()
+    a["z0"][::5] = np.nan
+    a["qw"][3] = np.inf
+    a["t1"][9] = -np.inf
+    for f in ("x", "y", "z", "t"):          # zero length
+        a[f + "1"][7] = a[f + "0"][7]
+    for f in ("bx", "by", "bz"):            # at rest
+        a[f][11] = 0.0
+    tr = W.Tracks(**a)
+    grad = np.random.default_rng(8).normal(size=(w.array.m, w.array.n_bins, 3))
+    if precision == "mixed":
+        grad = grad.astype(np.float32)
+        tr = tr.to_mixed()
+    det = rt.DeviceDetector.from_array(w.array)
+    plan = rt.Plan(det, w.medium, formalism, precision)
+    g = torch.from_numpy(grad).to("cuda")
+    out = [o.cpu().numpy() for o in plan.vjp(rt.DeviceTracks.from_tracks(tr), g)]
+    gq, gp0, gp1, gn = out
+    for o in out:
+        assert np.all(np.isfinite(o))
+    bad = np.zeros(tr.n, bool)
+    bad[::5] = bad[3] = bad[9] = True
+    assert not gq[bad].any() and not gp0[:, bad].any() and not gp1[:, bad].any()
+    ref_fn = orc.zhs_vjp if formalism == "zhs" else orc.endpoint_vjp
+    ref = ref_fn(tr.widened() if precision == "mixed" else tr, w.array, w.medium,
+                 grad.astype(np.float64), n_threads=8)
+    bound = 1e-9 if formalism == "zhs" else 1e-7
+    errs = {"qw": rel(gq, ref["qw"]), "p0": rel(gp0, ref["p0"]), "p1": rel(gp1, ref["p1"]),
+            "n0m1": rel(gn[0], ref["n0m1"])}
+    print(formalism, precision, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= bound, (k, v)
+    empty = rt.DeviceTracks.from_tracks(tr.slice(0, 0))
+    eq, ep0, ep1, en = [o.cpu().numpy() for o in plan.vjp(empty, g)]
+    assert eq.shape == (0,) and ep0.shape == (3, 0) and ep1.shape == (3, 0)
+    assert en.shape == (1,) and en[0] == 0.0
