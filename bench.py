@@ -598,8 +598,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=None,
                     help="tracks (showers for batched) the CPU oracle baseline runs on; "
                          "defaults sized for about 10-15 s of oracle work on 16 threads: "
-                         "grid 2^19 tracks (2^18 over the spherical Earth), adjoint 2^19 "
-                         "tracks, batched 48 showers, oracle sweep 2^14 tracks")
+                         "grid 2^19 tracks (2^18 in the tabulated and spherical media), "
+                         "adjoint 2^19 tracks, batched 48 showers, oracle sweep 2^14 tracks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tiling", default=None, help="at,splits,block,seg,pass override")
     ap.add_argument("--workload", default="grid4096",
@@ -772,8 +772,8 @@ def main():
                                w.array.m, {f: out["per_formalism"][f]["pairs_per_s"]
                                            for f in formalisms})
     if not args.no_cpu_baseline:
-        # the spherical medium's oracle takes ~2.5x longer per pair
-        default = 1 << 18 if args.medium == "spherical" else 1 << 19
+        # the spherical and tabulated media's oracle takes 2.5-3x longer per pair
+        default = 1 << 19 if args.medium == "exponential" else 1 << 18
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample or default, n_total), medium)
     print(json.dumps(out), flush=True)
 
