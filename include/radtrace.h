@@ -229,6 +229,32 @@ int rt_plan_set_timing_events(rt_plan *plan, void *start_event, void *stop_event
 int rt_propagate(const rt_plan *plan, const rt_tracks *tracks, double *t_arrival, int32_t *bin,
                  void *stream);
 
+/* The track filter (§2, Fig. 1: each track is checked for relevance to the
+ * radio calculation before the antenna loop). Copies the tracks of `in` that
+ * can radiate to the first n_kept entries of `out`, in their input order:
+ * a track is kept when every field is finite, |qw| > qw_min, some velocity
+ * component is nonzero and its end differs from its start in position or
+ * time. With qw_min = 0 every dropped track contributes exactly nothing to
+ * either formalism, so rt_accumulate on the kept tracks equals it on all of
+ * them up to floating-point summation order; qw_min > 0 also drops the
+ * tracks of smaller weight, by choice.
+ *   in: device tracks (n >= 0; bx, by, bz, qw double for RT_FP64, float for
+ *       RT_MIXED)
+ *   out: device arrays of the same types whose capacity out->n is >= in->n;
+ *        must not overlap `in`
+ *   n_kept: device, one int64, written with the number of kept tracks (read
+ *           it after the stream reaches this call)
+ *   workspace: device, >= rt_filter_workspace_bytes(in->n) bytes, used by
+ *              this call only
+ * Errors: RT_E_INVALID (NULL pointers, qw_min negative or not finite, a
+ * capacity below in->n), RT_E_WORKSPACE, RT_E_UNSUPPORTED (more than
+ * (2^31 - 1) * 256 tracks). */
+int rt_filter_tracks(const rt_tracks *in, int precision, double qw_min, const rt_tracks *out,
+                     int64_t *n_kept, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Device workspace (bytes) rt_filter_tracks needs for n_tracks tracks. */
+int rt_filter_workspace_bytes(int64_t n_tracks, size_t *bytes);
+
 /* Device workspace (bytes) rt_zhs_vjp or rt_endpoint_vjp (by the plan's
  * formalism) needs for n_tracks tracks. */
 int rt_plan_vjp_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes);

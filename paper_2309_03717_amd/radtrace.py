@@ -105,6 +105,9 @@ _lib.rt_batch_get_info.argtypes = [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32
                                    C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
 _lib.rt_batch_launch.argtypes = [_P, _P, C.c_size_t, _P]
 _lib.rt_batch_set_timing_events.argtypes = [_P, _P, _P]
+_lib.rt_filter_tracks.argtypes = [C.POINTER(rt_tracks), C.c_int, C.c_double,
+                                  C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
+_lib.rt_filter_workspace_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
 
 
 class RadtraceError(RuntimeError):
@@ -302,6 +305,41 @@ def rt_endpoint_vjp(plan: int, tracks: rt_tracks, grad_traces: torch.Tensor,
                                 _ptr(grad_p0), _ptr(grad_p1), _ptr(grad_n0m1), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)),
            "rt_endpoint_vjp")
+
+
+def rt_filter_workspace_bytes(n_tracks: int) -> int:
+    b = C.c_size_t()
+    _check(_lib.rt_filter_workspace_bytes(n_tracks, C.byref(b)), "rt_filter_workspace_bytes")
+    return b.value
+
+
+def rt_filter_tracks(tracks: rt_tracks, precision: int, qw_min: float, out: rt_tracks,
+                     n_kept: torch.Tensor, workspace: torch.Tensor, stream=None) -> None:
+    _check(_lib.rt_filter_tracks(C.byref(tracks), precision, qw_min, C.byref(out), _ptr(n_kept),
+                                 _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                 _stream(stream)), "rt_filter_tracks")
+
+
+def filter_tracks(tracks: "DeviceTracks", precision: str = "mixed", qw_min: float = 0.0,
+                  stream=None) -> "DeviceTracks":
+    """The tracks that can radiate (rt_filter_tracks), compacted in input
+    order into new device tensors, on the current stream or on `stream` (a
+    torch.cuda.Stream). Waits for that stream to read the count."""
+    prec = PRECISION[precision]
+    src = tracks.struct(prec)
+    dev = tracks.x0.device
+    out = DeviceTracks(**{f: torch.empty_like(getattr(tracks, f)) for f in _TRACK_FIELDS})
+    n_kept = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(rt_filter_workspace_bytes(tracks.n), 256), dtype=torch.uint8, device=dev)
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream(dev))   # the new tensors are ready
+        for t in [getattr(out, f) for f in _TRACK_FIELDS] + [n_kept, ws]:
+            t.record_stream(stream)
+    rt_filter_tracks(src, prec, float(qw_min), out.struct(prec), n_kept, ws, stream)
+    if stream is not None:
+        stream.synchronize()
+    k = int(n_kept.item())
+    return out.slice(0, k)
 
 
 def rt_batch_create(showers, precision: int, k: float, options: Optional[rt_batch_options] = None

@@ -262,3 +262,56 @@ def test_plan_create_rejects_more_than_int32_antennas(rt):
     st = rt._lib.rt_plan_create(C.byref(handle), C.byref(det), C.byref(med), rt.RT_ZHS,
                                 rt.RT_MIXED, 1.0)
     assert st == rt.RT_E_UNSUPPORTED and "antennas" in rt.rt_last_error()
+
+
+def test_filter_workspace_bytes(rt):
+    """Two 256-byte-aligned arrays of one int64 per 256-track workgroup."""
+    b = C.c_size_t()
+    for n, want in [(0, 512), (1, 512), (256 * 32, 512), (256 * 33, 1024), (10 ** 6, 2 * 31488)]:
+        assert rt._lib.rt_filter_workspace_bytes(n, C.byref(b)) == rt.RT_OK
+        assert b.value == want, (n, b.value)
+        assert rt.rt_filter_workspace_bytes(n) == want
+    assert rt._lib.rt_filter_workspace_bytes(-1, C.byref(b)) == rt.RT_E_INVALID
+    assert rt._lib.rt_filter_workspace_bytes(5, None) == rt.RT_E_INVALID
+
+
+@pytest.mark.parametrize("case", ["null_in", "null_out", "null_count", "bad_precision",
+                                  "negative_qw_min", "nan_qw_min", "inf_qw_min", "null_field",
+                                  "small_capacity", "null_out_field", "small_workspace"])
+def test_filter_rejects_invalid_arguments(rt, case):
+    """Every invalid argument is refused before the device is touched."""
+    buf = (C.c_double * 16)()
+    p = C.addressof(buf)
+    tin = rt.rt_tracks(10, *([p] * 12))
+    tout = rt.rt_tracks(10, *([p + 64] * 12))
+    count = p + 8
+    ws, ws_bytes = p, 1 << 20
+    precision, qw_min = rt.RT_MIXED, 0.0
+    args = None
+    if case == "null_in":
+        args = (None, precision, qw_min, C.byref(tout), count, ws, ws_bytes, None)
+    elif case == "null_out":
+        args = (C.byref(tin), precision, qw_min, None, count, ws, ws_bytes, None)
+    elif case == "null_count":
+        args = (C.byref(tin), precision, qw_min, C.byref(tout), None, ws, ws_bytes, None)
+    elif case == "bad_precision":
+        precision = 5
+    elif case == "negative_qw_min":
+        qw_min = -1e-3
+    elif case == "nan_qw_min":
+        qw_min = float("nan")
+    elif case == "inf_qw_min":
+        qw_min = float("inf")
+    elif case == "null_field":
+        tin.qw = None
+    elif case == "small_capacity":
+        tout.n = 9
+    elif case == "null_out_field":
+        tout.x1 = None
+    elif case == "small_workspace":
+        ws_bytes = 100
+    if args is None:
+        args = (C.byref(tin), precision, qw_min, C.byref(tout), count, ws, ws_bytes, None)
+    st = rt._lib.rt_filter_tracks(*args)
+    want = rt.RT_E_WORKSPACE if case == "small_workspace" else rt.RT_E_INVALID
+    assert st == want, (case, st, rt.rt_last_error())
