@@ -767,6 +767,7 @@ def main():
                                  **{k: (round(v, 4) if isinstance(v, float) else v)
                                     for k, v in per[f].items()}} for f in formalisms},
            "roofline": roofline}
+    out["track_filter"] = filter_leg(rt, chunks[0])
     if args.fp64_chunks > 0:
         out["fp64"] = fp64_leg(rt, det, medium, chunks[:args.fp64_chunks], formalisms,
                                w.array.m, {f: out["per_formalism"][f]["pairs_per_s"]
@@ -776,6 +777,34 @@ def main():
         default = 1 << 19 if args.medium == "exponential" else 1 << 18
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_sample or default, n_total), medium)
     print(json.dumps(out), flush=True)
+
+
+def filter_leg(rt, chunk, reps=5):
+    """The track filter (rt_filter_tracks, qw_min = 0) on one chunk, timed
+    with HIP events outside the timed steps: its cost beside the deposits and
+    its HBM rate (each track read twice, kept ones written once)."""
+    import torch
+    from paper_2309_03717_amd import workloads as W
+    prec = rt.RT_MIXED
+    src = chunk.struct(prec)
+    out = rt.DeviceTracks(**{f: torch.empty_like(getattr(chunk, f)) for f in W.TRACK_FIELDS})
+    dst = out.struct(prec)
+    n_kept = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ws = torch.empty(max(rt.rt_filter_workspace_bytes(chunk.n), 256), dtype=torch.uint8,
+                     device="cuda")
+    rt.rt_filter_tracks(src, prec, 0.0, dst, n_kept, ws)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        rt.rt_filter_tracks(src, prec, 0.0, dst, n_kept, ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    kept = int(n_kept.item())
+    per_track = sum(getattr(chunk, f).element_size() for f in W.TRACK_FIELDS)
+    moved = (2 * chunk.n + kept) * per_track
+    return {"tracks": chunk.n, "kept": kept, "ms": round(ms, 4),
+            "GBps": round(moved / (ms / 1e3) / 1e9, 1)}
 
 
 def fp64_leg(rt, det, medium, chunks, formalisms, m, mixed_rate):
