@@ -773,3 +773,82 @@ def test_spherical_adjoints_on_far_tracks(orc, formalism):
                 assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-6 * scale, (i, key, an, fd)
                 checked += 1
     assert checked >= 20
+
+
+def test_oracle_rounding_against_50_digit_evaluation(orc):
+    """The oracle's FP64 arrival times are within 4 ulp of the same definition
+    evaluated with 50 significant digits (mpmath, exact inputs), its bins are
+    the 50-digit floor unless an arrival lies within 1e-9 bins of an edge, and
+    each Endpoint impulse is within 1e-11 relative of its 50-digit value. A
+    pin of the FP64 evaluation order and rounding (the formulas themselves are
+    pinned by the closed forms and quadratures above)."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    w = config(1)
+    md = w.medium                                     # exponential
+    tr = w.tracks(8)
+    pts = np.array([[25.0, 0.0, 0.0], [0.0, -300.0, 35.0], [212.0, 212.0, 120.0],
+                    [-480.0, 60.0, 0.0005]])          # antennas at four heights
+    t_start = np.array([w.array.t_start[0]] * 4)
+    arr = antennas(pts, t_start, w.array.dt, w.array.n_bins)
+    t_orc, u_orc, b_orc = orc.propagate(tr, arr, md)
+    c = mp.mpf(C_LIGHT)
+    n0m1, h = mp.mpf(md.n0m1), mp.mpf(md.h)
+    dt = mp.mpf(arr.dt)
+    nb = arr.n_bins
+    F = lambda v: mp.mpf(float(v))
+
+    def neff(zp, za):
+        if abs(zp - za) >= mp.mpf("1e-3"):
+            return 1 + n0m1 * h * (mp.exp(-za / h) - mp.exp(-zp / h)) / (zp - za)
+        return 1 + n0m1 * mp.exp(-(zp + za) / (2 * h))
+
+    ends = [("x0", "y0", "z0", "t0"), ("x1", "y1", "z1", "t1")]
+    impulses = {}
+    for e, (fx, fy, fz, ft) in enumerate(ends):
+        for i in range(tr.n):
+            p = [F(getattr(tr, f)[i]) for f in (fx, fy, fz)]
+            T = F(getattr(tr, ft)[i])
+            beta = [F(getattr(tr, f)[i]) for f in ("bx", "by", "bz")]
+            for a in range(arr.m):
+                x = [F(arr.x[a]), F(arr.y[a]), F(arr.z[a])]
+                d = [x[k] - p[k] for k in range(3)]
+                r = mp.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+                t = T + neff(p[2], x[2]) * r / c
+                u = (t - F(arr.t_start[a])) / dt
+                tf = float(t_orc[e, i, a])
+                assert abs(mp.mpf(tf) - t) <= 4 * np.spacing(abs(tf)), (e, i, a)
+                k = int(mp.floor(u))
+                near_edge = abs(u - mp.nint(u)) < mp.mpf("1e-9")
+                want = k if 0 <= u < nb else -1
+                if not near_edge:
+                    assert int(b_orc[e, i, a]) == want, (e, i, a, float(u))
+                if want >= 0:
+                    rhat = [v / r for v in d]
+                    br = sum(beta[k2] * rhat[k2] for k2 in range(3))
+                    nsrc = 1 + n0m1 * mp.exp(-p[2] / h)
+                    D = 1 - nsrc * br
+                    s = 1 if e == 0 else -1
+                    qw = F(tr.qw[i])
+                    E = [s * qw * (rhat[k2] * br - beta[k2]) / (D * r * dt) for k2 in range(3)]
+                    impulses.setdefault((i, a), []).append((want, E))
+    checked = 0
+    for i in range(tr.n):
+        got = orc.traces("endpoint", tr.take([i]), arr, md, k=1.0)
+        for a in range(arr.m):
+            want = {}
+            for k, E in impulses.get((i, a), []):
+                acc = want.setdefault(k, [mp.mpf(0)] * 3)
+                for k2 in range(3):
+                    acc[k2] += E[k2]
+            nz = set(np.nonzero(np.any(got[a] != 0, axis=1))[0].tolist())
+            assert nz <= set(want), (i, a)
+            for k, E in want.items():
+                scale = max(abs(v) for v in E)
+                if scale == 0:
+                    continue
+                for k2 in range(3):
+                    assert abs(mp.mpf(float(got[a, k, k2])) - E[k2]) <= mp.mpf("1e-11") * scale, \
+                        (i, a, k, k2)
+                checked += 1
+    assert checked >= 16
