@@ -1,11 +1,14 @@
 """Host-resident track streams (streaming.HostTrackStream): chunks copied
 from pinned host memory on a copy stream, double-buffered, deposited by the
 library's plans. The streamed traces must equal those of the same chunks
-deposited from device memory (up to LDS summation order) and the oracle's."""
+deposited from device memory (up to LDS summation order) and the oracle's.
+With a filter threshold, the streamed traces equal the deposits of the numpy
+selection of each chunk's kept tracks, and every kept track is counted once."""
 import numpy as np
 import pytest
 
 from paper_2309_03717_amd import workloads as W
+from helpers import expected_mask, planted
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +79,66 @@ def test_streamed_chunks_equal_resident_and_oracle(rt, orc, precision):
         assert err <= (1e-5 if precision == "fp64" else 1e-6)
 
 
+def planted_chunks(precision):
+    """The chunk sizes above with droppable tracks planted, plus a chunk in
+    which every track is dropped."""
+    parts, lo = [], 0
+    for i, n in enumerate(SIZES):
+        parts.append(planted(n, precision, seed=10 + i, start=lo))
+        lo += n
+    a = planted(3000, precision, seed=9, start=lo).arrays()
+    a["qw"] = np.zeros_like(a["qw"])
+    parts.insert(2, W.Tracks(**a))
+    return parts
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("qw_min", [0.0, 1e-3])
+def test_filtered_stream_equals_deposits_of_kept_tracks(rt, precision, qw_min):
+    import torch
+    from paper_2309_03717_amd import streaming as S
+    w = W.config(1)
+    parts = planted_chunks(precision)
+    det = rt.DeviceDetector.from_array(w.array)
+    plans = [rt.Plan(det, w.medium, f, precision) for f in ("endpoint", "zhs")]
+    ref = [p.new_traces() for p in plans]
+    n_kept = 0
+    for part in parts:
+        mask = expected_mask(part, qw_min)
+        n_kept += int(mask.sum())
+        if mask.any():
+            sel = W.Tracks(**{f: np.asarray(getattr(part, f))[mask] for f in W.TRACK_FIELDS})
+            dt = rt.DeviceTracks.from_tracks(sel)
+            for p, tr in zip(plans, ref):
+                p.accumulate(dt, tr)
+    assert 0 < n_kept < sum(p.n for p in parts)
+    streamed = [p.new_traces() for p in plans]
+    st = S.HostTrackStream(plans, CHUNK, qw_min=qw_min)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    for rep in range(2):
+        # the second pass runs on another stream: the first pass's last chunk
+        # is flushed (deposited on its own stream) before that stream waits;
+        # the last chunk of all is flushed by synchronize, on the side stream
+        if rep == 1:
+            st.flush()
+            side.wait_stream(main)
+        with torch.cuda.stream(side if rep == 1 else main):
+            for part in parts:
+                st.push(S.pinned_chunk(part), streamed)
+    st.synchronize()
+    torch.cuda.synchronize()
+    assert st.kept == 2 * n_kept
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    for f, r, s in zip(("endpoint", "zhs"), ref, streamed):
+        r = r.double().cpu().numpy()
+        s = s.double().cpu().numpy()
+        scale = np.abs(r).max()
+        assert scale > 0
+        np.testing.assert_allclose(s, 2 * r, rtol=0, atol=2 * tol * scale, err_msg=f)
+
+
 def test_stream_rejects_bad_chunks(rt):
     import torch
     from paper_2309_03717_amd import streaming as S
@@ -101,6 +164,9 @@ def test_stream_rejects_bad_chunks(rt):
         st.push(short, tr)
     with pytest.raises(ValueError, match="one trace tensor per plan"):
         st.push(ok, tr * 2)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(ValueError, match="qw_min"):
+            S.HostTrackStream([plan], 1000, qw_min=bad)
     fp64 = rt.Plan(det, w.medium, "zhs", "fp64")
     with pytest.raises(ValueError, match="precision"):
         S.HostTrackStream([plan, fp64], 1000)
