@@ -638,7 +638,8 @@ def main():
                     help="grid4096: 1e8 tracks x 4096 antennas (default); batched: 256 showers; "
                          "adjoint: forward + VJP on 1e6 tracks x 64 antennas; "
                          "shower: shower-like vs random tracks on the grid; "
-                         "stream: the grid workload copied from pinned host memory; "
+                         "stream: the grid workload copied from pinned host memory (plain, "
+                         "device-resident and filtered legs); "
                          "copy: byte-counter calibration; oracle: the CPU oracle alone "
                          "at 1 and all host threads and several antenna bunch sizes")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: MiB per launch")
