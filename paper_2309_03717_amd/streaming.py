@@ -48,6 +48,10 @@ class HostTrackStream:
     the stream current at its push, but they are enqueued one push later, or
     by ``flush``/``synchronize``: call ``flush`` before another stream waits
     for the traces. ``kept`` counts the tracks deposited so far.
+
+    The device buffers are read on streams the allocator does not track, so
+    call ``synchronize`` before dropping the object, or use it as a context
+    manager, whose exit does.
     """
 
     def __init__(self, plans: Sequence["rt.Plan"], max_chunk: int,
@@ -162,6 +166,12 @@ class HostTrackStream:
                 for plan, tr in zip(self.plans, traces):
                     plan.accumulate(kept, tr)
         self.deposited[b].record(stream)
+
+    def __enter__(self) -> "HostTrackStream":
+        return self
+
+    def __exit__(self, *exc) -> None:
+        self.synchronize()
 
     def synchronize(self) -> None:
         """Flushes, then waits for every push so far; the host chunks are free

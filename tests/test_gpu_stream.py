@@ -113,21 +113,21 @@ def test_filtered_stream_equals_deposits_of_kept_tracks(rt, precision, qw_min):
                 p.accumulate(dt, tr)
     assert 0 < n_kept < sum(p.n for p in parts)
     streamed = [p.new_traces() for p in plans]
-    st = S.HostTrackStream(plans, CHUNK, qw_min=qw_min)
     side = torch.cuda.Stream()
     torch.cuda.synchronize()
     main = torch.cuda.current_stream()
-    for rep in range(2):
-        # the second pass runs on another stream: the first pass's last chunk
-        # is flushed (deposited on its own stream) before that stream waits;
-        # the last chunk of all is flushed by synchronize, on the side stream
-        if rep == 1:
-            st.flush()
-            side.wait_stream(main)
-        with torch.cuda.stream(side if rep == 1 else main):
-            for part in parts:
-                st.push(S.pinned_chunk(part), streamed)
-    st.synchronize()
+    with S.HostTrackStream(plans, CHUNK, qw_min=qw_min) as st:
+        for rep in range(2):
+            # the second pass runs on another stream: the first pass's last
+            # chunk is flushed (deposited on its own stream) before that
+            # stream waits; the last chunk of all is flushed on exit, on the
+            # side stream
+            if rep == 1:
+                st.flush()
+                side.wait_stream(main)
+            with torch.cuda.stream(side if rep == 1 else main):
+                for part in parts:
+                    st.push(S.pinned_chunk(part), streamed)
     torch.cuda.synchronize()
     assert st.kept == 2 * n_kept
     tol = 1e-12 if precision == "fp64" else 1e-6
