@@ -3,9 +3,9 @@
 Workload: 1e8 straight tracks (streamed in chunks of 2^22, all resident in
 HBM before timing) x 4096 antennas on a 64 x 64 grid of 50 m spacing,
 exponential refractivity, 4096 bins of 0.2 ns x 3 components, mixed
-precision (FP64 arrival time and bins, FP32 amplitudes and traces); one step
-is the Endpoint pass plus the ZHS pass over all tracks. The metric is
-antenna-track pairs per second over both formalisms.
+precision (float beta, qw and traces; the arithmetic is double precision);
+one step is the Endpoint pass plus the ZHS pass over all tracks. The metric
+is antenna-track pairs per second over both formalisms.
 
 With --workload batched it measures instead 256 independent showers in one
 persistent, graph-replayed launch per step (launch shape from the autotuner).
@@ -30,49 +30,67 @@ sys.path.insert(0, ROOT)
 
 METRIC = "antenna-track pairs/sec (Endpoint, ZHS), % FP32 VALU peak; mixed vs FP64"
 
-# Algorithmic floating-point operations of the definition (add, sub, mul, div,
-# sqrt each count 1; comparisons and index arithmetic are not counted), mixed
-# mode, split into the part every pair needs (the arrival-time chain, which
-# decides whether the pair lands in the window) and the part only pairs that
-# land need (amplitude and deposit). Per-track and per-antenna work is
-# excluded.
+# Algorithmic floating-point operations of the definition per pair (add, sub,
+# mul, div and sqrt count 1 each; comparisons, conversions and index
+# arithmetic are not counted), split into the part every pair needs (the
+# arrival-time chain, which decides whether the pair lands in the window) and
+# the part only pairs that land need (amplitude and deposit). Per-track and
+# per-antenna work is excluded. Every one of these operations executes in
+# double precision in both modes: RT_MIXED differs in its inputs (float beta
+# and qw), its outputs (float traces) and its refined-reciprocal divisions, not
+# in the width of its arithmetic, so no FP32 work is counted.
 OPS = {
-    # per track end: timing 14 (FP64); amplitude and deposit 21 (10 FP64: beta.d,
-    # n beta.d, R - n beta.d, three accumulating adds; 11 FP32: (beta.d)/R^2,
-    # d q - beta, s k qw / (num dt), a V)
-    "endpoint": {"timing_per_end": 14, "amp_per_end_fp64": 10, "amp_per_end_fp32": 11},
-    # per pair: timing of both ends 28 (FP64); box 61 (16 FP64: width, the two
-    # edge shares, twelve accumulating adds; 45 FP32: midpoint geometry 27, box
-    # height 4, deposit values 14)
-    "zhs": {"timing": 28, "box_fp64": 16, "box_fp32": 45},
+    # per track end: timing 14; amplitude and deposit 21 (beta.d 5, the Doppler
+    # numerator 2, (beta.d)/R^2 1, d q - beta 6, s k qw / (num dt) 1, a V 3,
+    # three accumulating adds)
+    "endpoint": {"timing_per_end": 14, "amp_per_end": 21},
+    # per pair: timing of both ends 28; box 61 (midpoint geometry 27, box
+    # height 4, edges 4, deposit values 14, twelve accumulating adds)
+    "zhs": {"timing": 28, "box": 61},
 }
 # Spherical Earth: the path mean of n per track end by 8-point quadrature, 19
 # FP64 operations per node (the node point 6, rho^2 5, the radius sum and its
 # sqrt 2, the height quotient 2, the exponent quotient 1, exp 1, the weighted
 # sum 2) and 2 to scale the sum: 154 per end on top of the timing chain.
 SPHERICAL_TIMING_PER_END = 8 * 19 + 2
-# MI355X VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.32e12
-# lane-operations/s for FP64 and for unpacked FP32 (packed FP32 is disabled in
-# this build); the published 78.6 TFLOP/s counts an FMA as two operations.
-VALU_OPS_PEAK = 256 * 64 * 2.4e9
-FP32_PEAK_PUBLISHED = 157.3e12
+# MI355X published FP64 vector peak (an FMA counts as two operations); the
+# published FP32 vector peak (157.3e12) needs packed FP32 instructions, which
+# this build does not use, and no counted operation executes in FP32.
+FP64_PEAK = 78.6e12
+# VALU issue rate, a diagnostic: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane
+# instructions per second (one wave64 instruction takes 4 cycles on a SIMD).
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 
-# HBM-side bytes per deposit launch of 2^20 tracks on this workload, from the
-# FETCH_SIZE and WRITE_SIZE counter runs summarised in
-# profiles/deposit_grid4096_mixed_hbm_bytes.md (KiB per dispatch), scaled by
-# what the same counters read for a 1 GiB device copy (FETCH_SIZE reads half
-# the copied bytes, WRITE_SIZE all of them). Valid only for the kernel sources
-# they were taken on (hash below); otherwise the bench reports null.
-TRAFFIC_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
-TRAFFIC_HASH = "b4293e667d1120af"
+# Stored hardware-counter figures per deposit launch of 2^20 tracks on this
+# workload, from counter runs of the kernels whose sources hash to
+# COUNTERS_HASH: HBM bytes from FETCH_SIZE and WRITE_SIZE (KiB per dispatch,
+# scaled by what the same counters read for a 1 GiB device copy: FETCH_SIZE
+# reads half the copied bytes, WRITE_SIZE all of them), and SQ_INSTS_VALU
+# (wave instructions per dispatch). They are reported, labelled as stored,
+# only while the kernel sources and the launch shape are the measured ones;
+# otherwise null.
+COUNTER_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
+COUNTERS_HASH = "b4293e667d1120af"
+COUNTERS_PROFILE = {"traffic": "profiles/deposit_grid4096_mixed_hbm_bytes.md",
+                    "valu": "profiles/deposit_grid4096_mixed_counters.md"}
 TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.5, "write": 1048576.0 / 1048576.0}
 TRAFFIC_KIB = {"endpoint": {"fetch": 9145407.8, "write": 393216.0},
                "zhs": {"fetch": 18267371.3, "write": 3145728.0}}
-TRAFFIC_PASS = 1 << 20
+SQ_INSTS_VALU = {"endpoint": 8.337e9, "zhs": 1.062e10}
+COUNTERS_PASS = 1 << 20
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_cores():
+    """Host threads this process may run on (all of them are used by the CPU
+    oracle baselines)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def in_window_fractions(rt, plan, dtr, n_sample):
@@ -97,42 +115,38 @@ def in_window_fractions(rt, plan, dtr, n_sample):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in COUNTER_SOURCES:
         with open(os.path.join(ROOT, "paper_2309_03717_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_bytes(formalism, tiling):
-    """Counter-measured HBM bytes per deposit launch, or None when the kernel
-    sources or the launch shape differ from those the counters were taken
-    on."""
-    if kernel_source_hash() != TRAFFIC_HASH or tiling[4] != TRAFFIC_PASS:
+def stored_counters(formalism, tiling):
+    """The stored counter figures of one deposit launch (HBM bytes, VALU
+    wave instructions), or None when the kernel sources or the launch shape
+    differ from those the counters were taken on."""
+    if kernel_source_hash() != COUNTERS_HASH or tiling[4] != COUNTERS_PASS:
         return None
     k = TRAFFIC_KIB[formalism]
-    return 1024.0 * (k["fetch"] * TRAFFIC_SCALE["fetch"] + k["write"] * TRAFFIC_SCALE["write"])
+    return {"traffic": 1024.0 * (k["fetch"] * TRAFFIC_SCALE["fetch"]
+                                 + k["write"] * TRAFFIC_SCALE["write"]),
+            "valu_insts": SQ_INSTS_VALU[formalism]}
 
 
 def ops_per_pair(formalism, ends_in, box_in, medium="exponential"):
+    """Algorithmic operations per pair at the measured landing fractions (all
+    of them executed in double precision)."""
     o = OPS[formalism]
     extra = 2 * SPHERICAL_TIMING_PER_END if medium == "spherical" else 0
     if formalism == "endpoint":
-        f64 = 2 * (o["timing_per_end"] + ends_in * o["amp_per_end_fp64"]) + extra
-        f32 = 2 * ends_in * o["amp_per_end_fp32"]
-    else:
-        f64 = o["timing"] + box_in * o["box_fp64"] + extra
-        f32 = box_in * o["box_fp32"]
-    return f64, f32
+        return 2 * (o["timing_per_end"] + ends_in * o["amp_per_end"]) + extra
+    return o["timing"] + box_in * o["box"] + extra
 
 
 def cpu_baseline(workload, n_sample, medium=None):
     import oracle
     oracle._load()
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores = host_cores()
     tr = workload.tracks(n_sample).to_mixed().widened()
     secs = {}
     for f in ("endpoint", "zhs"):
@@ -150,19 +164,17 @@ def cpu_baseline(workload, n_sample, medium=None):
 
 
 def shower_ops(rt, dev_showers, n_sample=2048):
-    """Algorithmic FP64 and FP32 operations of a batch, from each shower's own
-    in-window fractions (library propagator on its first tracks)."""
-    f64 = f32 = 0.0
+    """Algorithmic operations of a batch (all executed in double precision),
+    from each shower's own in-window fractions (library propagator on its
+    first tracks)."""
+    ops = 0.0
     for det, md, f, dtr in dev_showers:
         if dtr.n == 0:
             continue
         plan = rt.Plan(det, md, f, "mixed")
         ends_in, box_in = in_window_fractions(rt, plan, dtr, min(dtr.n, n_sample))
-        a, b = ops_per_pair(f, ends_in, box_in)
-        pairs = dtr.n * det.m
-        f64 += a * pairs
-        f32 += b * pairs
-    return f64, f32
+        ops += ops_per_pair(f, ends_in, box_in) * dtr.n * det.m
+    return ops
 
 
 def bench_batched(args):
@@ -226,25 +238,26 @@ def bench_batched(args):
     torch.cuda.synchronize()
     kernel_ms = sum(a.elapsed_time(b) for a, b in durs) / len(durs)
     pairs = batch.pairs
-    f64, f32 = shower_ops(rt, dev)
-    achieved = (f64 + f32) / (kernel_ms / 1e3) / 1e12
-    peak = VALU_OPS_PEAK / 1e12
+    ops = shower_ops(rt, dev)
+    achieved = ops / (kernel_ms / 1e3) / 1e12
+    peak = FP64_PEAK / 1e12
     out = {"metric": METRIC, "value": pairs / (ms_step / 1e3), "unit": "pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64+f32", "data": "synthetic",
+           "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"batched-{len(dev)}-showers" + (f"[max {args.tracks}]" if args.tracks else ""),
                       "n_showers": len(dev), "n_tracks": n_tracks, "pairs": pairs,
                       "precision": "mixed", "options": vars(opt), "launch": "hipGraph replay",
                       "items": batch.info["items"], "workgroups": batch.info["workgroups"]},
            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                         "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                        "peak_kind": "published FP64 vector peak (all arithmetic is FP64)",
                         "kernel": "batch_deposit_kernel<mixed>", "kernel_ms_avg": round(kernel_ms, 3),
-                        "ops_per_pair": {"fp64": round(f64 / pairs, 3), "fp32": round(f32 / pairs, 3)}}}
+                        "flops_per_pair": round(ops / pairs, 3)}}
     if not args.no_cpu_baseline:
         import oracle
         oracle._load()
-        cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+        cores = host_cores()
         k = min(args.cpu_sample or 48, len(showers))
         t1 = time.perf_counter()
         cpu_pairs = 0
@@ -308,7 +321,7 @@ def bench_shower(args):
            "value": tot["shower"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": 1, "ms_per_step": round(sum(v["deposit_ms"] for v in res["shower"].values()), 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64+f32", "data": "synthetic",
+           "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"shower-{n}trk-grid4096-expn-mixed", "n_tracks": n,
                       "n_antennas": w.array.m},
            "random_tracks_value": tot["random"], "per_kind": res}
@@ -369,7 +382,7 @@ def bench_adjoint(args):
            "value": 2 * 2 * pairs / (ms_step / 1e3), "unit": "pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64+f32", "data": "synthetic",
+           "dtype": "f64", "data": "synthetic",
            "config": {"workload": w.name if n == w.n_tracks else f"{w.name}[{n}]",
                       "n_tracks": n, "n_antennas": w.array.m, "n_bins": w.array.n_bins,
                       "precision": "mixed"},
@@ -385,11 +398,7 @@ def cpu_baseline_adjoint(workload, n_sample, grad):
     upstream gradient), in the bench's unit: forward + adjoint pairs/s."""
     import oracle
     oracle._load()
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores = host_cores()
     tr = workload.tracks(n_sample).to_mixed().widened()
     g = grad.double().cpu().numpy()
     secs = {}
@@ -410,7 +419,7 @@ def cpu_baseline_adjoint(workload, n_sample, grad):
 def bench_oracle(args):
     """The FP64 oracle alone on the host (no GPU): the grid workload's first
     args.cpu_sample tracks x all 4096 antennas, both formalisms, at 1, 2, 4,
-    8, 16 and all host threads (at most 16), the latter also with the antenna
+    8, 16 and all host threads, the latter also with the antenna
     bunch sizes {1, 4, 16, 64} (the paper's unit of work per thread) beside
     the default ceil(M / threads); then the whole 16-antenna, star and
     differentiable workloads at all host threads. Reported for context: the
@@ -418,11 +427,7 @@ def bench_oracle(args):
     import oracle
     from paper_2309_03717_amd import workloads as W
     oracle._load()
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    cores = host_cores()
     w = W.config(2)
     tr = w.tracks(args.cpu_sample or (1 << 14)).to_mixed().widened()
     pairs = tr.n * w.array.m
@@ -604,7 +609,7 @@ def bench_stream(args):
            "value": pairs / (ms_step / 1e3), "unit": "pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64+f32", "data": "synthetic",
+           "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"grid4096-{n_total}trk-expn-mixed-host-streamed",
                       "n_tracks": n_total, "n_antennas": w.array.m, "chunk": chunk,
                       "host_bytes_per_step": host_bytes},
@@ -757,35 +762,49 @@ def main():
         durs = [s.elapsed_time(e) / passes for s, e in kernel_events[f]]
         n_launch = len(durs)
         avg_ms = sum(durs) / n_launch
-        f64, f32 = ops_per_pair(f, ends_in, box_in, args.medium)
+        ops = ops_per_pair(f, ends_in, box_in, args.medium)
         pairs_per_launch = pairs_per_formalism * args.steps / (n_launch * passes)
-        achieved = (f64 + f32) * pairs_per_launch / (avg_ms / 1e3)
+        achieved = ops * pairs_per_launch / (avg_ms / 1e3)
         per[f] = {"kernel_ms_avg": avg_ms, "launches": n_launch * passes,
                   "kernel_ms_total_per_step": sum(durs) * passes / args.steps,
                   "pairs_per_s_kernel": pairs_per_launch / (avg_ms / 1e3),
-                  "ops_per_pair": {"fp64": round(f64, 3), "fp32": round(f32, 3)},
-                  "achieved_tops": achieved / 1e12,
-                  "fp32_peak_frac_literal": f32 * pairs_per_launch / (avg_ms / 1e3) / FP32_PEAK_PUBLISHED}
+                  "pairs_per_launch": pairs_per_launch,
+                  "flops_per_pair": round(ops, 3),
+                  "achieved_tflops": achieved / 1e12,
+                  "fp64_peak_frac": achieved / FP64_PEAK,
+                  "fp32_valu_peak_frac": 0.0}
     dom = max(formalisms, key=lambda f: per[f]["kernel_ms_total_per_step"])
-    achieved = per[dom]["achieved_tops"]
-    peak = VALU_OPS_PEAK / 1e12
-    traffic = (traffic_bytes(dom, plans[dom].tiling(chunk))
-               if n_total >= chunk and args.medium == "exponential" else None)
+    achieved = per[dom]["achieved_tflops"]
+    peak = FP64_PEAK / 1e12
+    stored = (stored_counters(dom, plans[dom].tiling(chunk))
+              if n_total >= chunk and args.medium == "exponential" else None)
+    kms = per[dom]["kernel_ms_avg"]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": None if traffic is None else round(traffic),
-                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_rate_GBps": None if traffic is None else
-                round(traffic / (per[dom]["kernel_ms_avg"] / 1e3) / 1e9, 1),
+                "peak_kind": "published FP64 vector peak: every counted operation executes "
+                             "in FP64 (none in FP32, so the FP32 VALU fraction is 0)",
+                "traffic": None if stored is None else round(stored["traffic"]),
+                "traffic_source": None if stored is None else
+                f"stored counter runs ({COUNTERS_PROFILE['traffic']}), kernel sources "
+                f"{COUNTERS_HASH}: FETCH_SIZE + WRITE_SIZE, copy-calibrated, bytes per launch",
+                "traffic_rate_GBps": None if stored is None else
+                round(stored["traffic"] / (kms / 1e3) / 1e9, 1),
                 "kernel": f"deposit_kernel<{dom},mixed,{medium.kind}>",
-                "kernel_ms_avg": round(per[dom]["kernel_ms_avg"], 3),
-                "ops_per_pair": per[dom]["ops_per_pair"],
-                "in_window": {"endpoint_ends": round(ends_in, 4), "zhs_boxes": round(box_in, 4)}}
+                "kernel_ms_avg": round(kms, 3),
+                "pairs_per_launch": per[dom]["pairs_per_launch"],
+                "flops_per_pair": per[dom]["flops_per_pair"],
+                "in_window": {"endpoint_ends": round(ends_in, 4), "zhs_boxes": round(box_in, 4)},
+                "valu_issue_diagnostic": None if stored is None else {
+                    "lane_instructions_per_s": stored["valu_insts"] * 64 / (kms / 1e3),
+                    "peak": VALU_ISSUE_PEAK, "unit": "lane-instructions/s",
+                    "frac": round(stored["valu_insts"] * 64 / (kms / 1e3) / VALU_ISSUE_PEAK, 4),
+                    "source": f"stored SQ_INSTS_VALU ({COUNTERS_PROFILE['valu']})"}}
 
     out = {"metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64+f32", "data": "synthetic",
+           "dtype": "f64", "io": "tracks: FP64 points and times, FP32 beta and qw; traces FP32",
+           "data": "synthetic",
            "config": {"workload": (w.name if n_total == w.n_tracks else f"{w.name}[{n_total}]")
                       + ("" if args.medium == "exponential" else "+" + args.medium),
                       "n_tracks": n_total, "n_antennas": w.array.m, "n_bins": w.array.n_bins,

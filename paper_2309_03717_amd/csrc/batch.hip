@@ -165,32 +165,28 @@ struct LdsNodes {
 // The deposits of one work item into the LDS tile.
 template <int F, int P, int MED, int AT>
 __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int64_t b_end,
-                                         const AntPtrs &an, const Consts &c, acc_t *tile,
-                                         int64_t a_begin, int n_ant, int row_len, int lo,
-                                         int hi, const double *nodes) {
+                                         const AntPtrs &an, const Consts &c, const TileRef &tr,
+                                         int64_t a_begin, int n_ant, const double *nodes) {
   Tile<AT> t;
   load_tile<AT, MED>(an, a_begin, n_ant, c, t);
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
-  deposit_blocks<F, P, MED, AT, MED != 3>(rec, b_first, b_end, waves, mask, t, tile, row_len, lo,
-                                          hi, (double)lo, (double)hi, c, LdsNodes{nodes});
+  deposit_blocks<F, P, MED, AT, MED != 3, false>(rec, b_first, b_end, waves, mask, t, tr, c,
+                                                 LdsNodes{nodes});
 }
 
 // Tile width switch; ATMAX = 1 compiles the one-antenna path only.
 template <int ATMAX, int F, int P, int MED>
 __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b_first,
                                             int64_t b_end, const AntPtrs &an, const Consts &c,
-                                            acc_t *tile, int64_t a_begin, int n_ant, int row_len,
-                                            int lo, int hi, const double *nodes) {
+                                            const TileRef &tr, int64_t a_begin, int n_ant,
+                                            const double *nodes) {
   if (ATMAX == 1 || at == 1)
-    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi,
-                           nodes);
+    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
   else if (at == 2)
-    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi,
-                           nodes);
+    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
   else
-    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tile, a_begin, n_ant, row_len, lo, hi,
-                           nodes);
+    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
 }
 
 // Persistent workgroups: take the items of one group until its counter
@@ -201,8 +197,8 @@ __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b
 // between both. ATMAX: the widest tile compiled in (1 or 3).
 // nodes: 2 kGl doubles of LDS for a spherical shower's quadrature rule.
 template <int P, int HEAVY, int FF, int ATMAX>
-__device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t *tile, int *cur,
-                                           double *nodes) {
+__device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<acc_t> *tile,
+                                           int *cur, double *nodes) {
   const int first = b.group_begin[group], last = b.group_begin[group + 1];
   for (;;) {
     __syncthreads();   // everyone has read cur and flushed the previous tile
@@ -225,7 +221,9 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t 
     const int lo = w.seg * seg_len;
     const int hi = min(lo + seg_len, c.n_bins);
     const int row_len = (hi - lo) * 3;
-    for (int i = threadIdx.x; i < at * row_len; i += blockDim.x) tile[i] = 0.0;
+    const int stride = (seg_len + kTilePad) * 3;
+    for (int i = threadIdx.x; i < at * stride; i += blockDim.x) tile[i] = 0.0;
+    const TileRef tr{tile, stride, lo, (double)lo, (double)hi, 0.0};
     if (HEAVY && c.medium == 3 && threadIdx.x < 2 * kGl)
       nodes[threadIdx.x] =
           threadIdx.x < kGl ? sd.c.gl_s[threadIdx.x] : sd.c.gl_w[threadIdx.x - kGl];
@@ -239,18 +237,14 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t 
     const int f = FF >= 0 ? FF : uniform(sd.formalism);
     if (FF != 1 && f == 0) {
       if (m1)
-        run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi, nodes);
+        run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
       else
-        run_item_at<ATMAX, 0, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi, nodes);
+        run_item_at<ATMAX, 0, P, M0>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
     } else if (FF != 0) {
       if (m1)
-        run_item_at<ATMAX, 1, P, M1>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi, nodes);
+        run_item_at<ATMAX, 1, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
       else
-        run_item_at<ATMAX, 1, P, M0>(at, rec, b_first, b_end, an, c, tile, a_begin, n_ant,
-                                     row_len, lo, hi, nodes);
+        run_item_at<ATMAX, 1, P, M0>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
     }
     __syncthreads();
     const int64_t slot_len = uniform(sd.slot_len);
@@ -259,7 +253,7 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, acc_t 
     acc_t *dst = b.partial + uniform(sd.part0) + slot * slot_len;
     for (int a = 0; a < n_ant; ++a)
       for (int i = threadIdx.x; i < row_len; i += blockDim.x)
-        dst[(int64_t)a * seg_len * 3 + i] = tile[a * row_len + i];
+        dst[(int64_t)a * seg_len * 3 + i] = tile[a * stride + i];
   }
 }
 
@@ -273,8 +267,8 @@ __global__ void __launch_bounds__(512) batch_deposit_kernel(BatchArgs b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int cur;
   __shared__ double nodes[HEAVY ? 2 * kGl : 1];
-  take_items<P, HEAVY, -1, 3>(b, HEAVY ? kGroupHeavy : kGroupLight,
-                              reinterpret_cast<acc_t *>(smem), &cur, nodes);
+  take_items<P, HEAVY, -1, 3>(b, HEAVY ? kGroupHeavy : kGroupLight, (lds<acc_t> *)smem, &cur,
+                              nodes);
 }
 
 // One-antenna tiles of the uniform and exponential media in one formalism F
@@ -285,8 +279,8 @@ template <int P, int F>
 __global__ void __launch_bounds__(1024) batch_deposit_one_kernel(BatchArgs b) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int cur;
-  take_items<P, 0, F, 1>(b, F == 0 ? kGroupLight : kGroupLightZhs,
-                         reinterpret_cast<acc_t *>(smem), &cur, nullptr);
+  take_items<P, 0, F, 1>(b, F == 0 ? kGroupLight : kGroupLightZhs, (lds<acc_t> *)smem, &cur,
+                         nullptr);
 }
 
 // One workgroup per (shower, antenna, segment): traces += sum over the
@@ -304,9 +298,9 @@ __global__ void __launch_bounds__(kMergeThreads) batch_merge_kernel(BatchArgs b)
                       (int64_t)ai * s.seg_len * 3;
   T *out = reinterpret_cast<T *>(s.traces) + ((size_t)mt.antenna * s.c.n_bins + lo) * 3;
   if (s.formalism == RT_ENDPOINT)
-    merge_segment<0, T>(part, s.slot_len, s.splits, out, nb);
+    merge_segment<0, T>(part, s.slot_len, s.splits, out, nb, 1.0);
   else
-    merge_segment<1, T>(part, s.slot_len, s.splits, out, nb);
+    merge_segment<1, T>(part, s.slot_len, s.splits, out, nb, 1.0);
 }
 
 }  // namespace rt
@@ -437,7 +431,8 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
   const int at_cap = (opt && opt->max_antennas_per_tile > 0) ? opt->max_antennas_per_tile : 3;
   const size_t row_bytes = 3 * sizeof(acc_t);
   const size_t budget = lds_block - 256;   // room for the kernel's own LDS words
-  const int max_bins = (int)(budget / row_bytes) / 64 * 64;
+  // a tile row holds a segment's bins plus kTilePad padding bins
+  const int max_bins = (int)(budget / row_bytes - kTilePad) / 64 * 64;
   b.sh.resize(n);
   int64_t max_slot = 0;
   for (int s = 0; s < n; ++s) {
@@ -450,10 +445,11 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
       int segs = (B + max_bins - 1) / max_bins;
       seg = ((B + segs - 1) / segs + 63) / 64 * 64;
     }
+    const size_t tile_row = (size_t)(seg + kTilePad) * row_bytes;
     int at = user && user->antennas_per_block > 0 ? user->antennas_per_block
-                                                  : std::min<int>(at_cap, (int)(budget / ((size_t)seg * row_bytes)));
+                                                  : std::min<int>(at_cap, (int)(budget / tile_row));
     at = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)at, 3, in.det.n_antennas}));
-    if ((size_t)at * seg * row_bytes > budget)
+    if ((size_t)at * tile_row > budget)
       return "the LDS tile of shower " + std::to_string(s) + " does not fit";
     d.tr = track_ptrs(in.tracks);
     d.an = ant_ptrs(in.det);
@@ -472,7 +468,7 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
       d.tab_off = b.total_tab;
       b.total_tab += ((int64_t)c.n_tab + 31) / 32 * 32;
     }
-    if (d.n_blocks > 0) max_slot = std::max(max_slot, d.slot_len);
+    if (d.n_blocks > 0) max_slot = std::max(max_slot, (int64_t)at * (seg + kTilePad) * 3);
     b.total_pairs += in.tracks.n * in.det.n_antennas;
   }
   b.lds_bytes = (size_t)std::max<int64_t>(max_slot, 1) * sizeof(acc_t);

@@ -39,22 +39,149 @@ struct PrepArgs {
   Consts c;
   double *rec;
   int64_t n_blocks;   // wave blocks (tracks rounded up to 64)
+  // fixed-point ZHS calls: the antennas' bounding box (written by
+  // bbox_kernel) and, per prepare workgroup, the sum and the maximum of the
+  // per-track deposit bounds; null otherwise
+  const double *bbox;
+  double *fx_part;
 };
+
+constexpr int kPrepThreads = 256;
+constexpr int kPrepMaxBlocks = 65536;
+
+// Bound on every ZHS deposit value of one track (mixed record v) at any
+// antenna of the box [xlo, xhi] x [ylo, yhi] x [zlo, zhi]: each of the four
+// difference deposits is at most |Ibar| = |cz| |beta_perp| / R_m per
+// component, and R_m (midpoint to antenna) is at least the midpoint's distance
+// to the box. Factor 1.01 covers the rounding of the deposit arithmetic.
+// Infinite when the midpoint lies in the box or more than 1e100 m from it (a
+// distance whose square would overflow the deposit geometry); 0 for a track
+// that deposits nothing (zero amplitude, or NaN times).
+__device__ __forceinline__ double zhs_track_bound(const double *v, const double *bb) {
+  const double cz = fabs((double)lo32(v[M_AB]));
+  const double bx = hi32(v[M_AB]), by = lo32(v[M_YZ]), bz = hi32(v[M_YZ]);
+  if (cz == 0.0 || isnan(v[R_T0])) return 0.0;
+  const double mx = (v[R_X0] + v[R_X1]) * 0.5, my = (v[R_Y0] + v[R_Y1]) * 0.5,
+               mz = (v[R_Z0] + v[R_Z1]) * 0.5;
+  const double ox = fmax(fmax(bb[0] - mx, mx - bb[1]), 0.0);
+  const double oy = fmax(fmax(bb[2] - my, my - bb[3]), 0.0);
+  const double oz = fmax(fmax(bb[4] - mz, mz - bb[5]), 0.0);
+  const double d2 = ox * ox + oy * oy + oz * oz;
+  if (!(d2 > 0.0 && d2 < 1e200)) return __builtin_inf();
+  return 1.01 * cz * sqrt(bx * bx + by * by + bz * bz) / sqrt(d2);
+}
 
 // One thread per (padded) track. A track with any non-finite field, and the
 // padding past the last track, get NaN times so that no antenna window
-// accepts them.
+// accepts them. Fixed-point ZHS calls also reduce the per-track deposit
+// bounds of each workgroup (fixed order: a tree over its threads) into
+// fx_part.
 template <int F, int P>
-__global__ void __launch_bounds__(256) prepare_kernel(PrepArgs g) {
+__global__ void __launch_bounds__(kPrepThreads) prepare_kernel(PrepArgs g) {
   const double z_ref = g.an.z[0];
   const double e_ref = g.c.medium == 1 || g.c.medium == 2 ? path_factor(z_ref, g.c) : 0.0;
   const int64_t n_pad = g.n_blocks * 64;
+  constexpr bool kFx = F == 1 && P == 1;
+  double bsum = 0.0, bmax = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
        i += (int64_t)gridDim.x * blockDim.x) {
     double v[kRec];
     make_record<F, P>(g.tr, i, i < g.tr.n, g.c, z_ref, e_ref, v);
     store_record<P>(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v);
+    if (kFx && g.fx_part) {
+      const double b = zhs_track_bound(v, g.bbox);
+      bsum += b;
+      bmax = fmax(bmax, b);
+    }
   }
+  if (kFx && g.fx_part) {
+    __shared__ double ssum[kPrepThreads], smax[kPrepThreads];
+    ssum[threadIdx.x] = bsum;
+    smax[threadIdx.x] = bmax;
+    __syncthreads();
+    for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        ssum[threadIdx.x] += ssum[threadIdx.x + h];
+        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      g.fx_part[2 * blockIdx.x] = ssum[0];
+      g.fx_part[2 * blockIdx.x + 1] = smax[0];
+    }
+  }
+}
+
+// The antennas' bounding box: bbox = {xmin, xmax, ymin, ymax, zmin, zmax}.
+// One workgroup of kPrepThreads threads.
+__global__ void __launch_bounds__(kPrepThreads) bbox_kernel(AntPtrs an, double *bbox) {
+  __shared__ double red[6][kPrepThreads];
+  double v[6] = {__builtin_inf(), -__builtin_inf(), __builtin_inf(), -__builtin_inf(),
+                 __builtin_inf(), -__builtin_inf()};
+  for (int64_t a = threadIdx.x; a < an.m; a += kPrepThreads) {
+    const double x = an.x[a], y = an.y[a], z = an.z[a];
+    v[0] = fmin(v[0], x); v[1] = fmax(v[1], x);
+    v[2] = fmin(v[2], y); v[3] = fmax(v[3], y);
+    v[4] = fmin(v[4], z); v[5] = fmax(v[5], z);
+  }
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 6; ++k)
+        red[k][threadIdx.x] = (k & 1) ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + h])
+                                      : fmin(red[k][threadIdx.x], red[k][threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) bbox[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// The call's fixed-point unit from the prepare workgroups' bound sums and
+// maxima (summed in a fixed order, so the unit depends only on the tracks),
+// written as fx = {unit, 1 / unit}, both powers of two, or {0, 0} when the
+// call keeps the double-precision tile. With S the sum of the track bounds
+// and B their maximum:
+//  - no int64 bin of any tile, split partial or merge sum can overflow: a
+//    track adds at most four deposits to a bin (the folded first bin of a
+//    segment), each at most its bound plus half a unit, and 4.04 S / unit <=
+//    2^62;
+//  - every deposit stays in the exact range of the rounding FMA: B / unit <
+//    2^50;
+//  - a unit coarser than 2^-30 of the mean track bound (one dominant track,
+//    or more than about 2^28 tracks in one call) would round typical
+//    deposits too coarsely: the double tile is kept.
+__global__ void fx_reduce_kernel(const double *fx_part, int n_parts, int64_t n_tracks,
+                                 double *fx) {
+  __shared__ double ssum[kPrepThreads], smax[kPrepThreads];
+  double sum = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < n_parts; i += kPrepThreads) {
+    sum += fx_part[2 * i];
+    mx = fmax(mx, fx_part[2 * i + 1]);
+  }
+  ssum[threadIdx.x] = sum;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      ssum[threadIdx.x] += ssum[threadIdx.x + h];
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double S = ssum[0], B = smax[0];
+  double unit = 0.0;
+  if (S == 0.0) {
+    unit = 1.0;   // nothing deposits: any unit
+  } else if (S < 1e300 && B > 0.0) {
+    // smallest powers of two with 4.04 S / 2^e <= 2^62 and B / 2^e < 2^50
+    const int e = max(ilogb(4.04 * S) + 1 - 62, ilogb(B) + 1 - 50);
+    if (e > -1000 && e < 1000 && ldexp(1.0, e) <= ldexp(S / (double)n_tracks, -30))
+      unit = ldexp(1.0, e);
+  }
+  fx[0] = unit;
+  fx[1] = unit > 0.0 ? 1.0 / unit : 0.0;
 }
 
 // ------------------------------------------------------------------ deposits
@@ -63,19 +190,39 @@ struct DepositArgs {
   AntPtrs an;
   Consts c;
   const double *rec;       // per-track records of this pass (first wave block)
-  void *partial;           // [splits][M][n_bins][3] doubles
+  void *partial;           // [splits][M][n_bins][3] doubles (int64 for fixed-point tiles)
+  const double *fx;        // fixed-point ZHS calls: {unit, 1 / unit}, unit 0 = off; else null
   int64_t n_blocks;        // wave blocks of tracks in this pass
   int64_t blocks_per_split;
   int n_atiles, n_segs, seg_len;
   int accumulate;          // 0: first pass writes the partials; 1: later passes add
 };
 
+// Adds (or, on a call's first pass, writes) the tile rows of the workgroup's
+// antennas into their partial slots.
+template <typename A>
+__device__ __forceinline__ void flush_tile(const DepositArgs &g, lds<acc_t> *tile, int stride,
+                                           int split, int64_t a_begin, int n_ant, int lo,
+                                           int row_len) {
+  A *dst = reinterpret_cast<A *>(g.partial);
+  for (int a = 0; a < n_ant; ++a) {
+    A *out = dst + (((size_t)split * g.an.m + (size_t)(a_begin + a)) * g.c.n_bins + lo) * 3;
+    const lds<A> *src = reinterpret_cast<lds<A> *>(tile) + a * stride;
+    if (g.accumulate)
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] += src[i];
+    else
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = src[i];
+  }
+}
+
 // F: 0 Endpoint, 1 ZHS.  P: 0 FP64, 1 mixed.  MED: 0 uniform, 1 exponential,
-// 2 tabulated, 3 spherical Earth.  AT: antennas per tile.
+// 2 tabulated, 3 spherical Earth.  AT: antennas per tile. Mixed ZHS calls
+// accumulate in int64 fixed point when the call's unit allows it (g.fx[0] >
+// 0) and in double otherwise.
 template <int F, int P, int MED, int AT>
 __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  acc_t *tile = reinterpret_cast<acc_t *>(smem);
+  lds<acc_t> *tile = (lds<acc_t> *)smem;
 
   const int v = xcd_major(blockIdx.x, gridDim.x);
   const int n_tiles = g.n_atiles * g.n_segs;
@@ -87,13 +234,16 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int n_ant = (int)min((int64_t)AT, g.an.m - a_begin);
   const int lo = seg * g.seg_len;
   const int hi = min(lo + g.seg_len, g.c.n_bins);
-  const double lo_d = (double)lo, hi_d = (double)hi;
   const int row_len = (hi - lo) * 3;
+  const int stride = (g.seg_len + kTilePad) * 3;
 
-  for (int i = threadIdx.x; i < AT * row_len; i += blockDim.x) tile[i] = 0.0;
+  for (int i = threadIdx.x; i < AT * stride; i += blockDim.x) tile[i] = 0.0;
 
   Tile<AT> t;
   load_tile<AT, MED>(g.an, a_begin, n_ant, g.c, t);
+  constexpr bool kFxCap = F == 1 && P == 1;
+  const double fx_unit = kFxCap ? g.fx[0] : 0.0;
+  const TileRef tr{tile, stride, lo, (double)lo, (double)hi, kFxCap ? g.fx[1] : 0.0};
   __syncthreads();
 
   const uint64_t mask = (1ull << n_ant) - 1;
@@ -102,20 +252,19 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int64_t b_end = min(g.n_blocks, (int64_t)(split + 1) * g.blocks_per_split);
   // record prefetch where delivery bounds the loop: the Endpoint deposit,
   // except over the spherical Earth, whose per-pair quadrature dominates
-  deposit_blocks<F, P, MED, AT, F == 0 && MED != 3>(g.rec, b_first, b_end, waves, mask, t, tile,
-                                                    row_len, lo, hi, lo_d, hi_d, g.c,
-                                                    ConstNodes{g.c});
+  constexpr bool kPf = F == 0 && MED != 3;
+  if (kFxCap && fx_unit > 0.0)
+    deposit_blocks<F, P, MED, AT, kPf, true>(g.rec, b_first, b_end, waves, mask, t, tr, g.c,
+                                             ConstNodes{g.c});
+  else
+    deposit_blocks<F, P, MED, AT, kPf, false>(g.rec, b_first, b_end, waves, mask, t, tr, g.c,
+                                              ConstNodes{g.c});
   __syncthreads();
 
-  acc_t *dst = reinterpret_cast<acc_t *>(g.partial);
-  for (int a = 0; a < n_ant; ++a) {
-    acc_t *out = dst + (((size_t)split * g.an.m + (size_t)(a_begin + a)) * g.c.n_bins + lo) * 3;
-    const acc_t *src = tile + a * row_len;
-    if (g.accumulate)
-      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] += src[i];
-    else
-      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = src[i];
-  }
+  if (kFxCap && fx_unit > 0.0)
+    flush_tile<long long>(g, tile, stride, split, a_begin, n_ant, lo, row_len);
+  else
+    flush_tile<acc_t>(g, tile, stride, split, a_begin, n_ant, lo, row_len);
 }
 
 // ------------------------------------------------------------------ merge
@@ -125,15 +274,22 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
 template <int F, int P>
 __global__ void __launch_bounds__(kMergeThreads) merge_kernel(const void *partial, void *traces,
                                                               int64_t m, int n_bins, int splits,
-                                                              int seg_len, int n_segs) {
+                                                              int seg_len, int n_segs,
+                                                              const double *fx) {
   using T = typename Prec<P>::out;
   const int64_t a = blockIdx.x / n_segs;
   const int seg = blockIdx.x % n_segs;
   const int lo = seg * seg_len;
   const int nb = min(lo + seg_len, n_bins) - lo;
   const size_t base = ((size_t)a * n_bins + lo) * 3;
-  merge_segment<F, T>(reinterpret_cast<const acc_t *>(partial) + base, (int64_t)m * n_bins * 3,
-                      splits, reinterpret_cast<T *>(traces) + base, nb);
+  const int64_t stride = (int64_t)m * n_bins * 3;
+  T *out = reinterpret_cast<T *>(traces) + base;
+  if (F == 1 && P == 1 && fx[0] > 0.0)
+    merge_segment<F, T>(reinterpret_cast<const long long *>(partial) + base, stride, splits, out,
+                        nb, fx[0]);
+  else
+    merge_segment<F, T>(reinterpret_cast<const acc_t *>(partial) + base, stride, splits, out, nb,
+                        1.0);
 }
 
 // ------------------------------------------------------------------ propagator
@@ -172,9 +328,23 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static int64_t wave_blocks(int64_t n) { return (n + 63) / 64; }
 
-// Workspace: [records][partials][tabulated profile's cumulative integral]
+// Workspace: [records][fixed-point region][partials][tabulated profile's
+// cumulative integral]. The fixed-point region (mixed ZHS plans) holds the
+// antennas' bounding box (6 doubles), the unit pair fx (2 doubles), then the
+// sum and maximum of the track bounds of every prepare workgroup.
 size_t prep_bytes(const rt_plan &, int64_t n) {
   return align256((size_t)wave_blocks(n) * kRec * 64 * sizeof(double));
+}
+
+static int prep_blocks(int64_t n) {
+  return (int)std::min<int64_t>((wave_blocks(n) * 64 + kPrepThreads - 1) / kPrepThreads,
+                                kPrepMaxBlocks);
+}
+
+static bool uses_fx(const rt_plan &p) { return p.formalism == RT_ZHS && p.precision == RT_MIXED; }
+
+static size_t fx_bytes(const rt_plan &p, int64_t n) {
+  return uses_fx(p) ? align256((8 + 2 * (size_t)prep_blocks(n)) * sizeof(double)) : 0;
 }
 
 size_t table_bytes(const rt_plan &p) {
@@ -197,19 +367,22 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
   const int B = p.det.n_bins;
   const int64_t M = p.det.n_antennas;
   const size_t budget = p.lds_per_block;
+  // a tile row holds the segment's bins plus kTilePad padding bins
   int seg = p.seg_user > 0 ? p.seg_user : B;
-  if ((size_t)seg * 3 * acc > budget) seg = (int)(budget / (3 * acc)) / 64 * 64;
+  if ((size_t)(seg + kTilePad) * 3 * acc > budget)
+    seg = (int)(budget / (3 * acc) - kTilePad) / 64 * 64;
   if (seg > B) seg = B;
   if (seg < 1) seg = 1;
   t.seg_len = seg;
   t.n_segs = (B + seg - 1) / seg;
-  int at = p.at_user > 0 ? p.at_user : (int)(budget / ((size_t)seg * 3 * acc));
+  const size_t row_bytes = (size_t)(seg + kTilePad) * 3 * acc;
+  int at = p.at_user > 0 ? p.at_user : (int)(budget / row_bytes);
   if (at > kMaxTile) at = kMaxTile;
   if (at < 1) at = 1;
   if (at > M) at = (int)M;
   t.at = at;
   t.n_atiles = (int)((M + at - 1) / at);
-  t.lds_bytes = (size_t)at * seg * 3 * acc;
+  t.lds_bytes = (size_t)at * row_bytes;
   // 1024 threads: with one workgroup per CU (the trace tile fills most of
   // the LDS) this keeps four waves per SIMD to hide the LDS atomics and the
   // record loads; the deposit kernels are built for at most 128 VGPRs
@@ -243,7 +416,7 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
 
 size_t workspace_bytes(const rt_plan &p, int64_t n) {
   Tiling t = choose_tiling(p, n);
-  return prep_bytes(p, n) +
+  return prep_bytes(p, n) + fx_bytes(p, n) +
          align256((size_t)t.splits * p.det.n_antennas * p.det.n_bins * 3 * acc_bytes(p.precision)) +
          table_bytes(p);
 }
@@ -288,7 +461,7 @@ static PrepFn pick_prep(int f, int prec) {
   return prec == RT_FP64 ? prepare_kernel<1, 0> : prepare_kernel<1, 1>;
 }
 
-using MergeFn = void (*)(const void *, void *, int64_t, int, int, int, int);
+using MergeFn = void (*)(const void *, void *, int64_t, int, int, int, int, const double *);
 
 static MergeFn pick_merge(int f, int prec) {
   if (f == RT_ENDPOINT) return prec == RT_FP64 ? merge_kernel<0, 0> : merge_kernel<0, 1>;
@@ -311,14 +484,25 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
   pa.c = c;
   pa.rec = reinterpret_cast<double *>(ws);
   pa.n_blocks = wave_blocks(t.n);
-  {
-    int blocks = (int)std::min<int64_t>((pa.n_blocks * 64 + 255) / 256, 65536);
-    pick_prep(p.formalism, p.precision)<<<blocks, 256, 0, stream>>>(pa);
+  pa.bbox = nullptr;
+  pa.fx_part = nullptr;
+  double *fx = nullptr;
+  const int blocks = prep_blocks(t.n);
+  if (uses_fx(p)) {
+    // bounding box -> records and per-workgroup bounds -> the call's unit
+    double *region = reinterpret_cast<double *>(ws + prep_bytes(p, t.n));
+    pa.bbox = region;
+    fx = region + 6;
+    pa.fx_part = region + 8;
+    bbox_kernel<<<1, kPrepThreads, 0, stream>>>(pa.an, region);
   }
+  pick_prep(p.formalism, p.precision)<<<blocks, kPrepThreads, 0, stream>>>(pa);
+  if (uses_fx(p)) fx_reduce_kernel<<<1, kPrepThreads, 0, stream>>>(pa.fx_part, blocks, t.n, fx);
   DepositArgs g;
   g.an = pa.an;
   g.c = c;
-  g.partial = ws + prep_bytes(p, t.n);
+  g.fx = fx;
+  g.partial = ws + prep_bytes(p, t.n) + fx_bytes(p, t.n);
   g.blocks_per_split = tl.blocks_per_split;
   g.n_atiles = tl.n_atiles;
   g.n_segs = tl.n_segs;
@@ -346,7 +530,7 @@ hipError_t launch_forward(const rt_plan &p, const rt_tracks &t, void *traces, vo
   }
   if (p.ev_stop) (void)hipEventRecord(p.ev_stop, stream);
   mf<<<dim3((unsigned)(p.det.n_antennas * tl.n_segs)), dim3(kMergeThreads), 0, stream>>>(
-      g.partial, traces, p.det.n_antennas, p.det.n_bins, tl.splits, tl.seg_len, tl.n_segs);
+      g.partial, traces, p.det.n_antennas, p.det.n_bins, tl.splits, tl.seg_len, tl.n_segs, fx);
   return hipGetLastError();
 }
 

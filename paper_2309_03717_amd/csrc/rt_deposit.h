@@ -10,6 +10,25 @@ namespace rt {
 
 using acc_t = double;
 
+// Rows of an LDS trace tile carry kTilePad bins past the segment end, which
+// take the ZHS difference deposits that fall just beyond it (at most two bins:
+// the box's last bin is clamped to the segment end first) and are never read.
+constexpr int kTilePad = 2;
+
+// Fixed-point ZHS accumulation (RT_MIXED): every deposit value v, scaled by
+// the call's power-of-two inverse unit s, is rounded to the nearest integer by
+// adding kFxMagic = 1.5 * 2^52 in one FMA (for |v s| < 2^51 the sum's exponent
+// is fixed and its low mantissa bits are round(v s) + 2^51), so that the bits
+// of fma(v, s, kFxMagic) minus kFxMagicBits are round(v s) as a two's
+// complement integer. Integer sums are exact and independent of their order,
+// which makes these traces bitwise reproducible for any tiling and launch.
+constexpr double kFxMagic = 0x1.8p52;
+constexpr unsigned long long kFxMagicBits = 0x4338000000000000ull;
+
+__device__ __forceinline__ long long fx_round(double v, double s) {
+  return (long long)((unsigned long long)__double_as_longlong(fma(v, s, kFxMagic)) - kFxMagicBits);
+}
+
 template <int P>
 struct Prec;
 template <>
@@ -178,28 +197,30 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
   }
 }
 
-__device__ __forceinline__ void put3(acc_t *row, int j, double vx, double vy, double vz) {
-  acc_t *p = row + 3 * j;
+// The three components of bin j of a tile row (24-bit offset arithmetic: a
+// row holds fewer than 2^21 bins).
+__device__ __forceinline__ void put3(lds<acc_t> *row, int j, double vx, double vy, double vz) {
+  lds<acc_t> *p = lds_elem(row, 3u * (unsigned)j);
   lds_add(p, vx);
   lds_add(p + 1, vy);
   lds_add(p + 2, vz);
 }
 
-// ZHS difference deposit at absolute bin j of a segment [lo, hi): bins before
-// the segment fold into its first bin (the segment's prefix scan starts
-// there), bins at or after its end are dropped.
-__device__ __forceinline__ void put3_clamped(acc_t *row, int j, int lo, int hi, double vx,
-                                             double vy, double vz) {
-  if (j < lo) j = lo;
-  if (j < hi) put3(row, j - lo, vx, vy, vz);
+// The same as fixed-point integers: round(v s) added to an int64 tile.
+__device__ __forceinline__ void put3_fx(lds<acc_t> *row, int j, double vx, double vy, double vz,
+                                        double s) {
+  lds<unsigned long long> *p =
+      lds_elem(reinterpret_cast<lds<unsigned long long> *>(row), 3u * (unsigned)j);
+  lds_add(p, (unsigned long long)fx_round(vx, s));
+  lds_add(p + 1, (unsigned long long)fx_round(vy, s));
+  lds_add(p + 2, (unsigned long long)fx_round(vz, s));
 }
-
 
 // Endpoint impulse of one track end at one antenna: s k qw [r x (r x beta)] /
 // ((1 - n_src beta.r) R dt), evaluated as sc (d (beta.d) / R^2 - beta) / num
 // with num = R - n_src (beta.d) = (1 - n_src beta.r) R and sc = s k qw / dt.
 template <int P>
-__device__ __forceinline__ void endpoint_amp(acc_t *row, int lo, double lo_d, double hi_d,
+__device__ __forceinline__ void endpoint_amp(lds<acc_t> *row, int lo, double lo_d, double hi_d,
                                              double u, double sc, double dx, double dy, double dz,
                                              double r, double r2, double nsrc, double bx,
                                              double by, double bz) {
@@ -224,9 +245,13 @@ __device__ __forceinline__ void endpoint_amp(acc_t *row, int lo, double lo_d, do
 // The box [u_lo, u_hi] of time integral I = k qw beta_perp (t1-t0) /
 // R_mid has bin averages Ibar * overlap / (u_hi - u_lo), Ibar = I / dt; it is
 // deposited as at most four differences whose prefix sum is that average,
-// each bounded by |Ibar|.
-template <int P>
-__device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double lo_d, double hi_d,
+// each bounded by |Ibar|. Differences before the segment [lo, hi) fold into
+// its first bin (its prefix scan starts there); those at or past its end land
+// in the row's padding (the last bin is clamped to hi first, so they reach at
+// most hi + 1). FX: fixed-point deposits, cz already scaled by the inverse
+// unit.
+template <int P, bool FX>
+__device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, double hi_d,
                                         double us, double ue, double dx0, double dy0, double dz0,
                                         double dx1, double dy1, double dz1, double cz, double bx,
                                         double by, double bz) {
@@ -253,13 +278,24 @@ __device__ __forceinline__ void zhs_box(acc_t *row, int lo, int hi, double lo_d,
   double s2 = one ? -1.0 : (two ? -a : (1.0 - flo) * wi);
   double s3 = two ? bb : -((1.0 - fhi) * wi);
   double s4 = -bb;
-  int jl = (int)fmax(kl, lo_d - 2.0);
-  int jh = (int)fmin(kh, hi_d);
-  put3_clamped(row, jl, lo, hi, ix * s1, iy * s1, iz * s1);
-  put3_clamped(row, jl + 1, lo, hi, ix * s2, iy * s2, iz * s2);
-  if (!one) {
-    put3_clamped(row, jh, lo, hi, ix * s3, iy * s3, iz * s3);
-    put3_clamped(row, jh + 1, lo, hi, ix * s4, iy * s4, iz * s4);
+  // kl <= hi - 1 (the box starts before the segment end) and lo <= jh <= hi
+  const int jl = (int)fmax(kl, lo_d - 2.0) - lo;
+  const int jh = (int)fmin(kh, hi_d) - lo;
+  const int j1 = max(jl, 0), j2 = max(jl + 1, 0);
+  if (FX) {
+    put3_fx(row, j1, ix, iy, iz, s1);
+    put3_fx(row, j2, ix, iy, iz, s2);
+    if (!one) {
+      put3_fx(row, jh, ix, iy, iz, s3);
+      put3_fx(row, jh + 1, ix, iy, iz, s4);
+    }
+  } else {
+    put3(row, j1, ix * s1, iy * s1, iz * s1);
+    put3(row, j2, ix * s2, iy * s2, iz * s2);
+    if (!one) {
+      put3(row, jh, ix * s3, iy * s3, iz * s3);
+      put3(row, jh + 1, ix * s4, iy * s4, iz * s4);
+    }
   }
 }
 
@@ -270,15 +306,28 @@ struct Tile {
   bool at_ref[AT];   // at the height of antenna 0: the record's path index applies
 };
 
+// Where one workgroup deposits: its LDS tile (rows of `stride` doubles, one
+// per tile antenna), the bin segment [lo, hi) the rows hold, and for
+// fixed-point tiles the call's inverse unit.
+struct TileRef {
+  lds<acc_t> *tile;
+  int stride;        // doubles per row: (segment bins + kTilePad) * 3
+  int lo;            // first bin of the segment
+  double lo_d, hi_d;
+  double fx_inv;     // fixed-point tiles: 1 / unit (a power of two)
+  __device__ __forceinline__ lds<acc_t> *row(int a) const {
+    return lds_elem(tile, (unsigned)(a * stride));
+  }
+};
+
 // All deposits of one track record (this lane's track) into the tile
 // antennas selected by mask.
 // H: the height factors were loaded (deposit_blocks loads them where they are
-// used).
+// used). FX: fixed-point ZHS tile.
 // Nodes: where the spherical path mean reads its quadrature nodes.
-template <int F, int P, int MED, int AT, bool H, class Nodes>
+template <int F, int P, int MED, int AT, bool H, bool FX, class Nodes>
 __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, const Tile<AT> &t,
-                                               acc_t *tile, int row_len, int lo, int hi,
-                                               double lo_d, double hi_d, const Consts &c,
+                                               const TileRef &tr, const Consts &c,
                                                const Nodes &nd) {
   const double x0 = v[R_X0], y0 = v[R_Y0], z0 = v[R_Z0], t0 = v[R_T0];
   const double x1 = v[R_X1], y1 = v[R_Y1], z1 = v[R_Z1], t1 = v[R_T1];
@@ -303,57 +352,51 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
       e1 = v[M_E1];
     }
   }
+  if (FX) amp *= tr.fx_inv;   // exact: a power of two
   const double ns0 = MED != 0 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
   const double ns1 = MED != 0 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
-  if (F == 0) {
 #pragma unroll
-    for (int a = 0; a < AT; ++a) {
-      if ((mask >> a) & 1) {
-        double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
-        double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
-        if (MED == 3) {
-          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c, nd);
-          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c, nd);
-        } else if (kOff && !t.at_ref[a]) {
-          const double p0 = MED == 2 ? tab_F(z0, c) : e0;
-          const double p1 = MED == 2 ? tab_F(z1, c) : e1;
-          ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
-          ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
-        }
-        acc_t *row = tile + a * row_len;
-        double dx0, dy0, dz0, r0, q0, dx1, dy1, dz1, r1, q1;
-        double u0 = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c,
-                                 dx0, dy0, dz0, r0, q0);
-        double u1 = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c,
-                                 dx1, dy1, dz1, r1, q1);
-        endpoint_amp<P>(row, lo, lo_d, hi_d, u0, amp, dx0, dy0, dz0, r0, q0, ns0, bx, by, bz);
-        endpoint_amp<P>(row, lo, lo_d, hi_d, u1, -amp, dx1, dy1, dz1, r1, q1, ns1, bx, by, bz);
+  for (int a = 0; a < AT; ++a) {
+    if ((mask >> a) & 1) {
+      double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
+      double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
+      if (MED == 3) {
+        ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c, nd);
+        ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c, nd);
+      } else if (kOff && !t.at_ref[a]) {
+        const double p0 = MED == 2 ? tab_F(z0, c) : e0;
+        const double p1 = MED == 2 ? tab_F(z1, c) : e1;
+        ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
+        ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
+      }
+      lds<acc_t> *row = tr.row(a);
+      double dx0, dy0, dz0, r0, q0, dx1, dy1, dz1, r1, q1;
+      const double u0 = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c,
+                                     dx0, dy0, dz0, r0, q0);
+      const double u1 = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c,
+                                     dx1, dy1, dz1, r1, q1);
+      if (F == 0) {
+        endpoint_amp<P>(row, tr.lo, tr.lo_d, tr.hi_d, u0, amp, dx0, dy0, dz0, r0, q0, ns0, bx, by,
+                        bz);
+        endpoint_amp<P>(row, tr.lo, tr.lo_d, tr.hi_d, u1, -amp, dx1, dy1, dz1, r1, q1, ns1, bx,
+                        by, bz);
+      } else {
+        zhs_box<P, FX>(row, tr.lo, tr.lo_d, tr.hi_d, u0, u1, dx0, dy0, dz0, dx1, dy1, dz1, amp, bx,
+                       by, bz);
       }
     }
+  }
+}
+
+// Reads the slots of lane l's record in wave block blk that a deposit uses.
+template <int P, int MED, bool H>
+__device__ __forceinline__ void load_record(const double *rec, int64_t blk, int lane, double *rv) {
+  if constexpr (paired_records<P>()) {
+    load_record_pairs<P, MED, H>(rec + blk * (kRec * 64), lane, rv);
   } else {
+    const double *r = rec + blk * (kRec * 64) + lane;
 #pragma unroll
-    for (int a = 0; a < AT; ++a) {
-      if ((mask >> a) & 1) {
-        double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
-        double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
-        if (MED == 3) {
-          ne0 = sph_path_index(x0, y0, z0, t.ax[a], t.ay[a], t.az[a], c, nd);
-          ne1 = sph_path_index(x1, y1, z1, t.ax[a], t.ay[a], t.az[a], c, nd);
-        } else if (kOff && !t.at_ref[a]) {
-          const double p0 = MED == 2 ? tab_F(z0, c) : e0;
-          const double p1 = MED == 2 ? tab_F(z1, c) : e1;
-          ne0 = path_index_m<MED>(z0, t.az[a], p0, t.ea[a], c);
-          ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
-        }
-        double dx0, dy0, dz0, dx1, dy1, dz1, rr, r2;
-        double us = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c, dx0,
-                                 dy0, dz0, rr, r2);
-        double ue = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c, dx1,
-                                 dy1, dz1, rr, r2);
-        zhs_box<P>(tile + a * row_len, lo, hi, lo_d, hi_d, us, ue, dx0, dy0, dz0, dx1, dy1, dz1,
-                   amp, bx, by, bz);
-      }
-    }
+    for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
   }
 }
 
@@ -364,76 +407,48 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 // (the Endpoint deposit) or few waves share a SIMD (the 512-thread batch
 // kernel); the single-plan ZHS deposit, with more arithmetic per record and
 // four waves per SIMD, runs faster without the register copies it costs.
-template <int F, int P, int MED, int AT, bool H, bool PF, class Nodes>
+template <int F, int P, int MED, int AT, bool H, bool PF, bool FX, class Nodes>
 __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_first,
                                                  int64_t b_end, int64_t waves, uint64_t mask,
-                                                 const Tile<AT> &t, acc_t *tile, int row_len,
-                                                 int lo, int hi, double lo_d, double hi_d,
+                                                 const Tile<AT> &t, const TileRef &tr,
                                                  const Consts &c, const Nodes &nd) {
   const int lane = threadIdx.x & 63;
   if (!PF) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
       double rv[kRec];
-      if constexpr (paired_records<P>()) {
-        load_record_pairs<P, MED, H>(rec + blk * (kRec * 64), lane, rv);
-      } else {
-        const double *r = rec + blk * (kRec * 64) + lane;
-#pragma unroll
-        for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
-      }
-      deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c, nd);
+      load_record<P, MED, H>(rec, blk, lane, rv);
+      deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
     }
     return;
   }
   double nx[kRec];
 #pragma unroll
   for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
-  if (b_first < b_end) {
-    if constexpr (paired_records<P>()) {
-      load_record_pairs<P, MED, H>(rec + b_first * (kRec * 64), lane, nx);
-    } else {
-      const double *r = rec + b_first * (kRec * 64) + lane;
-#pragma unroll
-      for (int f = 0; f < kRec; ++f)
-        if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
-    }
-  }
+  if (b_first < b_end) load_record<P, MED, H>(rec, b_first, lane, nx);
   for (int64_t blk = b_first; blk < b_end; blk += waves) {
     double rv[kRec];
 #pragma unroll
     for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
-    if (blk + waves < b_end) {
-      if constexpr (paired_records<P>()) {
-        load_record_pairs<P, MED, H>(rec + (blk + waves) * (kRec * 64), lane, nx);
-      } else {
-        const double *r = rec + (blk + waves) * (kRec * 64) + lane;
-#pragma unroll
-        for (int f = 0; f < kRec; ++f)
-          if (slot_loaded<P, MED, H>(f)) nx[f] = r[f * 64];
-      }
-    }
-    deposit_record<F, P, MED, AT, H>(rv, mask, t, tile, row_len, lo, hi, lo_d, hi_d, c, nd);
+    if (blk + waves < b_end) load_record<P, MED, H>(rec, blk + waves, lane, nx);
+    deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
   }
 }
 
 // As deposit_blocks_n, reading the height factors only where they are used:
 // the Endpoint source index in non-uniform media, and tiles with an antenna off
 // the reference height (whose path index is taken per pair from them).
-template <int F, int P, int MED, int AT, bool PF, class Nodes>
+template <int F, int P, int MED, int AT, bool PF, bool FX, class Nodes>
 __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
                                                int64_t waves, uint64_t mask, const Tile<AT> &t,
-                                               acc_t *tile, int row_len, int lo, int hi,
-                                               double lo_d, double hi_d, const Consts &c,
+                                               const TileRef &tr, const Consts &c,
                                                const Nodes &nd) {
   bool off = false;
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
   if (MED == 3 ? F == 0 : MED != 0 && (F == 0 || off))
-    deposit_blocks_n<F, P, MED, AT, true, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
-                                              lo, hi, lo_d, hi_d, c, nd);
+    deposit_blocks_n<F, P, MED, AT, true, PF, FX>(rec, b_first, b_end, waves, mask, t, tr, c, nd);
   else
-    deposit_blocks_n<F, P, MED, AT, false, PF>(rec, b_first, b_end, waves, mask, t, tile, row_len,
-                                               lo, hi, lo_d, hi_d, c, nd);
+    deposit_blocks_n<F, P, MED, AT, false, PF, FX>(rec, b_first, b_end, waves, mask, t, tr, c, nd);
 }
 
 // Loads the tile antennas [a_begin, a_begin + n_ant) (uniform per workgroup).
@@ -457,55 +472,57 @@ __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, in
 
 constexpr int kMergeThreads = 256;
 
-// traces[0, nb) += the sum over `splits` partial slots (`stride` doubles
-// apart, added in slot order) of one segment, 3 components per bin. ZHS
-// slots hold differences (every box folded into the segment's first bin
-// where it starts earlier), so their sum is prefix-scanned over the segment:
-// chunks of kMergeThreads bins are summed with coalesced loads into LDS,
-// scanned across the workgroup (within each wave by lane shuffles, then over
-// the wave totals), offset by the carry of the chunks before, and added to
-// the traces with coalesced stores. One workgroup of kMergeThreads threads.
-template <int F, typename T>
-__device__ __forceinline__ void merge_segment(const acc_t *part, int64_t stride, int splits,
-                                              T *out, int nb) {
+// traces[0, nb) += the sum over `splits` partial slots (`stride` elements
+// apart, added in slot order) of one segment, 3 components per bin, times
+// `unit` (the value of one partial unit: 1 for double partials, the call's
+// fixed-point unit for int64 ones, whose sums and scan are exact). ZHS slots
+// hold differences (every box folded into the segment's first bin where it
+// starts earlier), so their sum is prefix-scanned over the segment: chunks of
+// kMergeThreads bins are summed with coalesced loads into LDS, scanned across
+// the workgroup (within each wave by lane shuffles, then over the wave
+// totals), offset by the carry of the chunks before, and added to the traces
+// with coalesced stores. One workgroup of kMergeThreads threads.
+template <int F, typename T, typename A>
+__device__ __forceinline__ void merge_segment(const A *part, int64_t stride, int splits, T *out,
+                                              int nb, double unit) {
   const int tid = threadIdx.x;
   if (F == 0) {
     for (int i = tid; i < nb * 3; i += kMergeThreads) {
-      double s = 0.0;
+      A s = 0;
       for (int sp = 0; sp < splits; ++sp) s += part[sp * stride + i];
-      out[i] = (T)((double)out[i] + s);
+      out[i] = (T)((double)out[i] + (double)s * unit);
     }
     return;
   }
   constexpr int kWaves = kMergeThreads / 64;
-  __shared__ double buf[kMergeThreads * 3];
-  __shared__ double wsum[kWaves][3];
+  __shared__ A buf[kMergeThreads * 3];
+  __shared__ A wsum[kWaves][3];
   const int lane = tid & 63, wave = tid >> 6;
-  double carry[3] = {0.0, 0.0, 0.0};
+  A carry[3] = {0, 0, 0};
   for (int c0 = 0; c0 < nb; c0 += kMergeThreads) {
     const int n = min(kMergeThreads, nb - c0);
-    const acc_t *p = part + 3 * (int64_t)c0;
+    const A *p = part + 3 * (int64_t)c0;
     for (int i = tid; i < 3 * n; i += kMergeThreads) {
-      double s = 0.0;
+      A s = 0;
       for (int sp = 0; sp < splits; ++sp) s += p[sp * stride + i];
       buf[i] = s;
     }
     __syncthreads();
-    double v[3];
+    A v[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[c] = tid < n ? buf[3 * tid + c] : 0.0;
+    for (int c = 0; c < 3; ++c) v[c] = tid < n ? buf[3 * tid + c] : (A)0;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        double y = __shfl_up(v[c], off);
+        A y = __shfl_up(v[c], off);
         if (lane >= off) v[c] += y;
       }
     }
     if (lane == 63)
       for (int c = 0; c < 3; ++c) wsum[wave][c] = v[c];
     __syncthreads();
-    double pre[3], tot[3];
+    A pre[3], tot[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       pre[c] = carry[c];
@@ -513,8 +530,9 @@ __device__ __forceinline__ void merge_segment(const acc_t *part, int64_t stride,
       tot[c] = pre[c];
       for (int w = wave; w < kWaves; ++w) tot[c] += wsum[w][c];
     }
-    // tot is the same in every wave only up to rounding order: take wave 0's
-    // value (pre = carry there) so that all threads carry the same number
+    // tot is the same in every wave only up to rounding order (double
+    // partials): take wave 0's value (pre = carry there) so that all threads
+    // carry the same number
     __syncthreads();
     if (tid < n)
       for (int c = 0; c < 3; ++c) buf[3 * tid + c] = pre[c] + v[c];
@@ -524,7 +542,8 @@ __device__ __forceinline__ void merge_segment(const acc_t *part, int64_t stride,
 #pragma unroll
     for (int c = 0; c < 3; ++c) carry[c] = wsum[0][c];
     T *o = out + 3 * (int64_t)c0;
-    for (int i = tid; i < 3 * n; i += kMergeThreads) o[i] = (T)((double)o[i] + buf[i]);
+    for (int i = tid; i < 3 * n; i += kMergeThreads)
+      o[i] = (T)((double)o[i] + (double)buf[i] * unit);
     __syncthreads();
   }
 }

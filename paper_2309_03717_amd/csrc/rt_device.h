@@ -270,8 +270,19 @@ __device__ __forceinline__ int xcd_major(int b, int grid) {
   return x < rem ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 
+// LDS (address space 3) objects: pointers to them are 32-bit, so offsets
+// into a tile stay in 32-bit arithmetic.
+template <class T>
+using lds = __attribute__((address_space(3))) T;
+
+// Element i of an LDS array by a 24-bit multiply (i * sizeof(T) < 2^24).
+template <class T>
+__device__ __forceinline__ lds<T> *lds_elem(lds<T> *base, unsigned i) {
+  return (lds<T> *)((lds<char> *)base + __umul24(i, (unsigned)sizeof(T)));
+}
+
 template <typename T>
-__device__ __forceinline__ void lds_add(T *p, T v) {
+__device__ __forceinline__ void lds_add(lds<T> *p, T v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
