@@ -175,7 +175,8 @@ int rt_plan_destroy(rt_plan *plan);
  *                   per-track records of a pass stay resident in the
  *                   last-level cache while every antenna tile streams them
  * Results do not depend on the tiling beyond floating-point summation
- * order; bins never change. */
+ * order (RT_MIXED ZHS calls: not at all, see rt_accumulate); bins never
+ * change. */
 typedef struct {
   int32_t antennas_per_block;
   int32_t track_splits;
@@ -207,12 +208,31 @@ int rt_plan_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes
  *             every bin it overlaps.
  * workspace: device, >= rt_plan_workspace_bytes(plan, tracks->n) bytes, used
  * as scratch by this call only. tracks->n == 0 is a no-op; at most 2^31 - 1
- * tracks per call (RT_E_UNSUPPORTED beyond: stream larger inputs in chunks). Partial traces of
- * track splits are merged in a fixed order (no float atomics in global
- * memory), so a call is repeatable for a fixed tiling up to the order of LDS
- * additions within a workgroup. */
+ * tracks per call (RT_E_UNSUPPORTED beyond: stream larger inputs in
+ * chunks). Partial traces of track splits are merged in a fixed order (no
+ * float atomics in global memory), so a call is repeatable for a fixed
+ * tiling up to the order of LDS additions within a workgroup. RT_MIXED ZHS
+ * calls accumulate in 64-bit fixed point instead: every deposit is rounded to
+ * a power-of-two unit chosen per call from the tracks (so that no sum can
+ * overflow) and summed exactly, which makes their traces bitwise identical
+ * for any tiling, launch and repetition; a call whose tracks admit no such
+ * unit (a track midpoint inside the antennas' bounding box, or one track
+ * whose deposit bound dwarfs the others) accumulates in double like the
+ * other modes. */
 int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *workspace,
                   size_t workspace_bytes, void *stream);
+
+/* Refractivity in device memory (the differentiable workflow, where n0 - 1
+ * is a device tensor that changes between calls): with n0m1 non-NULL, every
+ * later call on this plan (rt_accumulate, rt_propagate, the VJPs) reads
+ * n0 - 1 from that device double when its kernels run, in place of
+ * med->n0_minus_1 of rt_plan_create, so no host copy of it is needed;
+ * NULL returns to med->n0_minus_1. The pointer is kept by the plan and must
+ * stay valid while work of those calls can run; the value is not validated
+ * (it should be finite and >= 0, as for rt_medium). The medium kind, scale
+ * height, table and Earth radius stay those of rt_plan_create (§1: the
+ * environment the propagator is built from). */
+int rt_plan_set_n0m1_device(rt_plan *plan, const double *n0m1);
 
 /* Profiling aid: the next rt_accumulate call on this plan records
  * start_event on its stream immediately before its deposit kernel and

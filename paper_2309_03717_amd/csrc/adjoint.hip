@@ -232,7 +232,7 @@ template <int P, int MED>
 __global__ void __launch_bounds__(kVjpBlock) __attribute__((amdgpu_waves_per_eu(3)))
 vjp_kernel(VjpArgs v) {
   using In = typename std::conditional<P == 0, double, float>::type;
-  const Consts &c = v.c;
+  const Consts c = resolve_consts(v.c);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double gn_local = 0.0;
   if (i < v.tr.n) {
@@ -355,7 +355,7 @@ vjp_kernel(VjpArgs v) {
 template <int P, int MED>
 __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
   using In = typename std::conditional<P == 0, double, float>::type;
-  const Consts &c = v.c;
+  const Consts c = resolve_consts(v.c);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double gn_local = 0.0;
   if (i < v.tr.n) {

@@ -173,6 +173,7 @@ void rt_fill_consts(const rt_detector &det, const rt_medium &med, double k, rt::
   c.medium = med.kind;
   fill_table(med, c);
   fill_sphere(med, c);
+  c.n0m1_dev = nullptr;
 }
 
 int rt_hip_fail(hipError_t e, const char *what) { return hip_fail(e, what); }
@@ -361,6 +362,12 @@ static int vjp_call(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
   hipError_t e = rt::launch_vjp(*plan, *tracks, grad_traces, grad_qw, grad_p0, grad_p1, grad_n0m1,
                                 workspace, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "launching the adjoint kernels");
+  return RT_OK;
+}
+
+int rt_plan_set_n0m1_device(rt_plan *plan, const double *n0m1) {
+  if (!plan) return fail(RT_E_INVALID, "plan is NULL");
+  plan->c.n0m1_dev = n0m1;
   return RT_OK;
 }
 

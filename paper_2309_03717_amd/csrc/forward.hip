@@ -49,11 +49,11 @@ struct PrepArgs {
 constexpr int kPrepThreads = 256;
 constexpr int kPrepMaxBlocks = 65536;
 
-// Bound on every ZHS deposit value of one track (mixed record v) at any
-// antenna of the box [xlo, xhi] x [ylo, yhi] x [zlo, zhi]: each of the four
-// difference deposits is at most |Ibar| = |cz| |beta_perp| / R_m per
-// component, and R_m (midpoint to antenna) is at least the midpoint's distance
-// to the box. Factor 1.01 covers the rounding of the deposit arithmetic.
+// Bound on the values a ZHS box of one track (mixed record v) rounds at any
+// antenna of the box [xlo, xhi] x [ylo, yhi] x [zlo, zhi]: its three levels
+// are at most |Ibar| = |cz| |beta_perp| / R_m per component, and R_m
+// (midpoint to antenna) is at least the midpoint's distance to the box.
+// Factor 1.01 covers the rounding of the deposit arithmetic.
 // Infinite when the midpoint lies in the box or more than 1e100 m from it (a
 // distance whose square would overflow the deposit geometry); 0 for a track
 // that deposits nothing (zero amplitude, or NaN times).
@@ -78,15 +78,16 @@ __device__ __forceinline__ double zhs_track_bound(const double *v, const double 
 // fx_part.
 template <int F, int P>
 __global__ void __launch_bounds__(kPrepThreads) prepare_kernel(PrepArgs g) {
+  const Consts c = resolve_consts(g.c);
   const double z_ref = g.an.z[0];
-  const double e_ref = g.c.medium == 1 || g.c.medium == 2 ? path_factor(z_ref, g.c) : 0.0;
+  const double e_ref = c.medium == 1 || c.medium == 2 ? path_factor(z_ref, c) : 0.0;
   const int64_t n_pad = g.n_blocks * 64;
   constexpr bool kFx = F == 1 && P == 1;
   double bsum = 0.0, bmax = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad;
        i += (int64_t)gridDim.x * blockDim.x) {
     double v[kRec];
-    make_record<F, P>(g.tr, i, i < g.tr.n, g.c, z_ref, e_ref, v);
+    make_record<F, P>(g.tr, i, i < g.tr.n, c, z_ref, e_ref, v);
     store_record<P>(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v);
     if (kFx && g.fx_part) {
       const double b = zhs_track_bound(v, g.bbox);
@@ -142,10 +143,11 @@ __global__ void __launch_bounds__(kPrepThreads) bbox_kernel(AntPtrs an, double *
 // written as fx = {unit, 1 / unit}, both powers of two, or {0, 0} when the
 // call keeps the double-precision tile. With S the sum of the track bounds
 // and B their maximum:
-//  - no int64 bin of any tile, split partial or merge sum can overflow: a
-//    track adds at most four deposits to a bin (the folded first bin of a
-//    segment), each at most its bound plus half a unit, and 4.04 S / unit <=
-//    2^62;
+//  - no int64 bin of any tile, split partial or merge sum can overflow: the
+//    deposits a track adds to one bin (all four in the folded first bin of a
+//    segment) are differences of its three rounded levels, so their absolute
+//    values sum to at most 2 (r1 + r2 + r3) <= 6 (bound / unit + 1/2), and
+//    6.06 S / unit <= 2^62 leaves room for the halves of 2^31 tracks;
 //  - every deposit stays in the exact range of the rounding FMA: B / unit <
 //    2^50;
 //  - a unit coarser than 2^-30 of the mean track bound (one dominant track,
@@ -175,8 +177,8 @@ __global__ void fx_reduce_kernel(const double *fx_part, int n_parts, int64_t n_t
   if (S == 0.0) {
     unit = 1.0;   // nothing deposits: any unit
   } else if (S < 1e300 && B > 0.0) {
-    // smallest powers of two with 4.04 S / 2^e <= 2^62 and B / 2^e < 2^50
-    const int e = max(ilogb(4.04 * S) + 1 - 62, ilogb(B) + 1 - 50);
+    // smallest powers of two with 6.06 S / 2^e <= 2^62 and B / 2^e < 2^50
+    const int e = max(ilogb(6.06 * S) + 1 - 62, ilogb(B) + 1 - 50);
     if (e > -1000 && e < 1000 && ldexp(1.0, e) <= ldexp(S / (double)n_tracks, -30))
       unit = ldexp(1.0, e);
   }
@@ -239,8 +241,9 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
 
   for (int i = threadIdx.x; i < AT * stride; i += blockDim.x) tile[i] = 0.0;
 
+  const Consts c = resolve_consts(g.c);
   Tile<AT> t;
-  load_tile<AT, MED>(g.an, a_begin, n_ant, g.c, t);
+  load_tile<AT, MED>(g.an, a_begin, n_ant, c, t);
   constexpr bool kFxCap = F == 1 && P == 1;
   const double fx_unit = kFxCap ? g.fx[0] : 0.0;
   const TileRef tr{tile, stride, lo, (double)lo, (double)hi, kFxCap ? g.fx[1] : 0.0};
@@ -254,11 +257,11 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   // except over the spherical Earth, whose per-pair quadrature dominates
   constexpr bool kPf = F == 0 && MED != 3;
   if (kFxCap && fx_unit > 0.0)
-    deposit_blocks<F, P, MED, AT, kPf, true>(g.rec, b_first, b_end, waves, mask, t, tr, g.c,
-                                             ConstNodes{g.c});
+    deposit_blocks<F, P, MED, AT, kPf, true>(g.rec, b_first, b_end, waves, mask, t, tr, c,
+                                             ConstNodes{c});
   else
-    deposit_blocks<F, P, MED, AT, kPf, false>(g.rec, b_first, b_end, waves, mask, t, tr, g.c,
-                                              ConstNodes{g.c});
+    deposit_blocks<F, P, MED, AT, kPf, false>(g.rec, b_first, b_end, waves, mask, t, tr, c,
+                                              ConstNodes{c});
   __syncthreads();
 
   if (kFxCap && fx_unit > 0.0)
@@ -294,8 +297,9 @@ __global__ void __launch_bounds__(kMergeThreads) merge_kernel(const void *partia
 
 // ------------------------------------------------------------------ propagator
 
-__global__ void __launch_bounds__(256) propagate_kernel(TrackPtrs tr, AntPtrs an, Consts c,
+__global__ void __launch_bounds__(256) propagate_kernel(TrackPtrs tr, AntPtrs an, Consts c0,
                                                         double *t_out, int32_t *bin_out) {
+  const Consts c = resolve_consts(c0);
   const int64_t total = tr.n * an.m;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {

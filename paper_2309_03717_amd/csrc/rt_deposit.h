@@ -15,8 +15,8 @@ using acc_t = double;
 // the box's last bin is clamped to the segment end first) and are never read.
 constexpr int kTilePad = 2;
 
-// Fixed-point ZHS accumulation (RT_MIXED): every deposit value v, scaled by
-// the call's power-of-two inverse unit s, is rounded to the nearest integer by
+// Fixed-point ZHS accumulation (RT_MIXED): every value v, scaled by the
+// call's power-of-two inverse unit s, is rounded to the nearest integer by
 // adding kFxMagic = 1.5 * 2^52 in one FMA (for |v s| < 2^51 the sum's exponent
 // is fixed and its low mantissa bits are round(v s) + 2^51), so that the bits
 // of fma(v, s, kFxMagic) minus kFxMagicBits are round(v s) as a two's
@@ -24,10 +24,6 @@ constexpr int kTilePad = 2;
 // which makes these traces bitwise reproducible for any tiling and launch.
 constexpr double kFxMagic = 0x1.8p52;
 constexpr unsigned long long kFxMagicBits = 0x4338000000000000ull;
-
-__device__ __forceinline__ long long fx_round(double v, double s) {
-  return (long long)((unsigned long long)__double_as_longlong(fma(v, s, kFxMagic)) - kFxMagicBits);
-}
 
 template <int P>
 struct Prec;
@@ -197,23 +193,23 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
   }
 }
 
-// The three components of bin j of a tile row (24-bit offset arithmetic: a
-// row holds fewer than 2^21 bins).
-__device__ __forceinline__ void put3(lds<acc_t> *row, int j, double vx, double vy, double vz) {
-  lds<acc_t> *p = lds_elem(row, 3u * (unsigned)j);
+// Adds (vx, vy, vz) to the three components at p (bin j of a tile row, from
+// lds_bin).
+__device__ __forceinline__ void put3(lds<acc_t> *p, double vx, double vy, double vz) {
   lds_add(p, vx);
   lds_add(p + 1, vy);
   lds_add(p + 2, vz);
 }
 
-// The same as fixed-point integers: round(v s) added to an int64 tile.
-__device__ __forceinline__ void put3_fx(lds<acc_t> *row, int j, double vx, double vy, double vz,
-                                        double s) {
-  lds<unsigned long long> *p =
-      lds_elem(reinterpret_cast<lds<unsigned long long> *>(row), 3u * (unsigned)j);
-  lds_add(p, (unsigned long long)fx_round(vx, s));
-  lds_add(p + 1, (unsigned long long)fx_round(vy, s));
-  lds_add(p + 2, (unsigned long long)fx_round(vz, s));
+__device__ __forceinline__ lds<unsigned long long> *as_u64(lds<acc_t> *p) {
+  return reinterpret_cast<lds<unsigned long long> *>(p);
+}
+
+// Biased fixed-point rounding: the bits of fma(v, s, kFxMagic), which are
+// kFxMagicBits + round(v s) for |v s| < 2^51, so that the difference of two
+// of them is the exact difference of the rounded integers.
+__device__ __forceinline__ unsigned long long fx_biased(double v, double s) {
+  return (unsigned long long)__double_as_longlong(fma(v, s, kFxMagic));
 }
 
 // Endpoint impulse of one track end at one antenna: s k qw [r x (r x beta)] /
@@ -237,7 +233,7 @@ __device__ __forceinline__ void endpoint_amp(lds<acc_t> *row, int lo, double lo_
     q = bd * fast_rcp(r2);
     a = sc * fast_rcp(num);
   }
-  put3(row, j, fma(dx, q, -bx) * a, fma(dy, q, -by) * a, fma(dz, q, -bz) * a);
+  put3(lds_bin(row, j), fma(dx, q, -bx) * a, fma(dy, q, -by) * a, fma(dz, q, -bz) * a);
 }
 
 // ZHS box of one segment at one antenna. us, ue: arrival of start and end in
@@ -248,25 +244,27 @@ __device__ __forceinline__ void endpoint_amp(lds<acc_t> *row, int lo, double lo_
 // each bounded by |Ibar|. Differences before the segment [lo, hi) fold into
 // its first bin (its prefix scan starts there); those at or past its end land
 // in the row's padding (the last bin is clamped to hi first, so they reach at
-// most hi + 1). FX: fixed-point deposits, cz already scaled by the inverse
-// unit.
+// most hi + 1). cz2 = 2 k qw (t1 - t0) / dt (times the inverse unit for
+// fixed-point deposits, FX).
 template <int P, bool FX>
 __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, double hi_d,
                                         double us, double ue, double dx0, double dy0, double dz0,
-                                        double dx1, double dy1, double dz1, double cz, double bx,
+                                        double dx1, double dy1, double dz1, double cz2, double bx,
                                         double by, double bz) {
   double ulo = us < ue ? us : ue;
   double uhi = us < ue ? ue : us;
   if (!(uhi >= lo_d && ulo < hi_d)) return;   // outside this segment (or NaN)
-  // midpoint geometry: Ibar = cz * beta_perp / R_m, cz = k qw (t1 - t0) / dt;
-  // X - M is the mean of the end offsets X - P0, X - P1 the timing computed
-  double dx = (dx0 + dx1) * 0.5, dy = (dy0 + dy1) * 0.5, dz = (dz0 + dz1) * 0.5;
-  double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-  if (r2 == 0.0) return;
-  double rinv = P == 0 ? 1.0 / sqrt(r2) : fast_rsq(r2);
-  double q = fma(bx, dx, fma(by, dy, bz * dz)) * (rinv * rinv);
-  double s = cz * rinv;
-  double ix = fma(-dx, q, bx) * s, iy = fma(-dy, q, by) * s, iz = fma(-dz, q, bz) * s;
+  // midpoint geometry from e = (X - P0) + (X - P1) = 2 (X - M), the end
+  // offsets the timing computed: with r = 1 / |e| = 1 / (2 R_m),
+  // beta_perp = beta - e (beta.e) r^2 and Ibar = cz beta_perp / R_m =
+  // cz2 r beta_perp
+  double ex = dx0 + dx1, ey = dy0 + dy1, ez = dz0 + dz1;
+  double e2 = fma(ex, ex, fma(ey, ey, ez * ez));
+  if (e2 == 0.0) return;
+  double rinv = P == 0 ? 1.0 / sqrt(e2) : fast_rsq(e2);
+  double q = fma(bx, ex, fma(by, ey, bz * ez)) * (rinv * rinv);
+  double s = cz2 * rinv;
+  double ix = fma(-ex, q, bx) * s, iy = fma(-ey, q, by) * s, iz = fma(-ez, q, bz) * s;
   double kl = floor(ulo), kh = floor(uhi);
   const bool one = kl == kh, two = kh == kl + 1.0;
   double w = uhi - ulo;
@@ -274,27 +272,50 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
   double flo = (kl + 1.0) - ulo;   // share of bin kl, in (0, 1]
   double fhi = uhi - kh;           // share of bin kh, in [0, 1)
   double a = flo * wi, bb = fhi * wi;
+  const double t2 = (1.0 - flo) * wi, t3 = (1.0 - fhi) * wi;
   double s1 = one ? 1.0 : a;
-  double s2 = one ? -1.0 : (two ? -a : (1.0 - flo) * wi);
-  double s3 = two ? bb : -((1.0 - fhi) * wi);
+  double s2 = one ? -1.0 : (two ? -a : t2);
+  double s3 = two ? bb : -t3;
   double s4 = -bb;
   // kl <= hi - 1 (the box starts before the segment end) and lo <= jh <= hi
-  const int jl = (int)fmax(kl, lo_d - 2.0) - lo;
-  const int jh = (int)fmin(kh, hi_d) - lo;
-  const int j1 = max(jl, 0), j2 = max(jl + 1, 0);
+  const double lo_m2 = lo_d - 2.0;
+  const int jl = (int)(kl > lo_m2 ? kl : lo_m2) - lo;
+  const int jh = (int)(kh < hi_d ? kh : hi_d) - lo;
+  lds<acc_t> *p1 = lds_bin(row, max(jl, 0));
+  lds<acc_t> *p2 = lds_bin(row, max(jl + 1, 0));
+  lds<acc_t> *p3 = lds_bin(row, jh);
   if (FX) {
-    put3_fx(row, j1, ix, iy, iz, s1);
-    put3_fx(row, j2, ix, iy, iz, s2);
+    // Fixed point: the bin averages are the rounded levels r(l1 I) (bin
+    // kl), r(l2 I) (the whole bins between) and r(l3 I) (bin kh), deposited
+    // as their exact integer differences, so that every box's deposits
+    // telescope to zero after its last bin (no rounding residue reaches the
+    // bins beyond it, whatever the segmentation). Every level is at most 1:
+    // a one-bin box has l1 = 1, l2 = 0; a two-bin box has no whole bin
+    // between (l2 = a, its difference vanishes there).
+    const double l1 = one ? 1.0 : a, l2 = one ? 0.0 : (two ? a : wi), l3 = bb;
+    const double v[3] = {ix, iy, iz};
+    unsigned long long b1[3], b2[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b1[k] = fx_biased(v[k], l1);
+      b2[k] = fx_biased(v[k], l2);
+      lds_add(as_u64(p1) + k, b1[k] - kFxMagicBits);
+      lds_add(as_u64(p2) + k, b2[k] - b1[k]);
+    }
     if (!one) {
-      put3_fx(row, jh, ix, iy, iz, s3);
-      put3_fx(row, jh + 1, ix, iy, iz, s4);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const unsigned long long b3 = fx_biased(v[k], l3);
+        lds_add(as_u64(p3) + k, b3 - b2[k]);
+        lds_add(as_u64(p3) + 3 + k, kFxMagicBits - b3);
+      }
     }
   } else {
-    put3(row, j1, ix * s1, iy * s1, iz * s1);
-    put3(row, j2, ix * s2, iy * s2, iz * s2);
+    put3(p1, ix * s1, iy * s1, iz * s1);
+    put3(p2, ix * s2, iy * s2, iz * s2);
     if (!one) {
-      put3(row, jh, ix * s3, iy * s3, iz * s3);
-      put3(row, jh + 1, ix * s4, iy * s4, iz * s4);
+      put3(p3, ix * s3, iy * s3, iz * s3);
+      put3(p3 + 3, ix * s4, iy * s4, iz * s4);
     }
   }
 }
@@ -352,7 +373,9 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
       e1 = v[M_E1];
     }
   }
-  if (FX) amp *= tr.fx_inv;   // exact: a power of two
+  // ZHS: the box takes twice its amplitude constant (times the inverse unit
+  // for fixed-point tiles; all exact powers of two)
+  if (F == 1) amp *= FX ? 2.0 * tr.fx_inv : 2.0;
   const double ns0 = MED != 0 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
   const double ns1 = MED != 0 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
 #pragma unroll

@@ -54,7 +54,24 @@ struct Consts {
   // [0, 1] (ascending) and weights
   double re, re2, re_twice;
   double gl_s[kGl], gl_w[kGl];
+  // non-null: n0 - 1 is read from this device address by every kernel (the
+  // n0m1, n0h and n_uniform fields above are then recomputed from it)
+  const double *n0m1_dev;
 };
+
+// The constants a kernel works with: n0 - 1 and the values derived from it
+// (n0h = n0m1 * h, n_uniform = 1 + n0m1, the host's operations) taken from
+// device memory when the plan points at it.
+__device__ __forceinline__ Consts resolve_consts(const Consts &c0) {
+  Consts c = c0;
+  if (c.n0m1_dev) {
+    const double n = *c.n0m1_dev;
+    c.n0m1 = n;
+    c.n0h = n * c.h;
+    c.n_uniform = 1.0 + n;
+  }
+  return c;
+}
 
 struct TrackPtrs {
   const double *x0, *y0, *z0, *t0, *x1, *y1, *z1, *t1;
@@ -279,6 +296,13 @@ using lds = __attribute__((address_space(3))) T;
 template <class T>
 __device__ __forceinline__ lds<T> *lds_elem(lds<T> *base, unsigned i) {
   return (lds<T> *)((lds<char> *)base + __umul24(i, (unsigned)sizeof(T)));
+}
+
+// The first of the three components of bin j of a trace row (0 <= j, 24 j
+// sizeof(T) / 8 < 2^24): one 24-bit multiply.
+template <class T>
+__device__ __forceinline__ lds<T> *lds_bin(lds<T> *row, int j) {
+  return (lds<T> *)((lds<char> *)row + __umul24((unsigned)j, 3u * (unsigned)sizeof(T)));
 }
 
 template <typename T>

@@ -94,6 +94,7 @@ _lib.rt_plan_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_accumulate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
 _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
 _lib.rt_plan_set_timing_events.argtypes = [_P, _P, _P]
+_lib.rt_plan_set_n0m1_device.argtypes = [_P, _P]
 _lib.rt_plan_vjp_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_zhs_vjp.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P, _P, _P, _P, C.c_size_t, _P]
 _lib.rt_endpoint_vjp.argtypes = _lib.rt_zhs_vjp.argtypes
@@ -126,6 +127,23 @@ def _stream(stream) -> Optional[int]:
     if stream is None:
         return torch.cuda.current_stream().cuda_stream
     return getattr(stream, "cuda_stream", stream)
+
+
+def _on_stream(stream):
+    """Context for a call on an explicit torch.cuda.Stream other than the
+    current one: that stream first waits for the current stream's work (the
+    call's inputs), and the tensors allocated for the call are taken from
+    that stream's memory pool, so the caching allocator reuses them only
+    after the stream's work on them is done. A no-op for the current stream
+    (or a raw handle)."""
+    import contextlib
+    if not isinstance(stream, torch.cuda.Stream):
+        return contextlib.nullcontext()
+    cur = torch.cuda.current_stream(stream.device)
+    if stream == cur:
+        return contextlib.nullcontext()
+    stream.wait_stream(cur)
+    return torch.cuda.stream(stream)
 
 
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
@@ -276,6 +294,16 @@ def rt_plan_set_timing_events(plan: int, start_event, stop_event) -> None:
            "rt_plan_set_timing_events")
 
 
+def rt_plan_set_n0m1_device(plan: int, n0m1: Optional[torch.Tensor]) -> None:
+    """n0m1: a device float64 tensor of one element (kept alive by the
+    caller while work reading it can run), or None for the plan's medium
+    value."""
+    if n0m1 is not None and (n0m1.dtype != torch.float64 or n0m1.numel() != 1
+                             or not n0m1.is_cuda):
+        raise ValueError("n0m1 must be a one-element float64 device tensor")
+    _check(_lib.rt_plan_set_n0m1_device(plan, _ptr(n0m1)), "rt_plan_set_n0m1_device")
+
+
 def rt_propagate(plan: int, tracks: rt_tracks, t_arrival: Optional[torch.Tensor],
                  bins: Optional[torch.Tensor], stream=None) -> None:
     _check(_lib.rt_propagate(plan, C.byref(tracks), _ptr(t_arrival), _ptr(bins), _stream(stream)),
@@ -421,29 +449,46 @@ class Plan:
 
     def workspace(self, n_tracks: int, stream=None) -> torch.Tensor:
         """The workspace of calls on ``stream`` (default: the current one),
-        grown to what n_tracks tracks need."""
+        grown to what n_tracks tracks need (allocated from that stream's
+        memory pool, so that a replaced workspace is reused only after the
+        stream's work on it)."""
         need = rt_plan_workspace_bytes(self.handle, n_tracks)
         key = _stream(stream)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < need:
-            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.det.x.device)
+            with _on_stream(stream):
+                ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.det.x.device)
             self._ws[key] = ws
         return ws
+
+    def set_n0m1_device(self, n0m1: Optional[torch.Tensor]) -> None:
+        """Read n0 - 1 from a one-element float64 device tensor in every
+        later call (rt_plan_set_n0m1_device); None returns to the medium's
+        value. The plan keeps a reference to the tensor."""
+        rt_plan_set_n0m1_device(self.handle, n0m1)
+        self._n0m1_dev = n0m1
 
     def new_traces(self) -> torch.Tensor:
         return torch.zeros((self.det.m, self.det.n_bins, 3), dtype=self.dtype,
                            device=self.det.x.device)
 
     def accumulate(self, tracks: DeviceTracks, traces: torch.Tensor, stream=None) -> torch.Tensor:
+        """traces += this plan's contribution of the tracks, on ``stream``
+        (default: the current one). With another torch.cuda.Stream, that
+        stream first waits for the current one."""
         if traces.dtype != self.dtype or not traces.is_contiguous() or \
                 tuple(traces.shape) != (self.det.m, self.det.n_bins, 3):
             raise ValueError("traces must be a contiguous [M, n_bins, 3] tensor of the plan dtype")
-        rt_accumulate(self.handle, tracks.struct(self.precision), traces,
-                      self.workspace(tracks.n, stream), stream)
+        ws = self.workspace(tracks.n, stream)
+        with _on_stream(stream):
+            rt_accumulate(self.handle, tracks.struct(self.precision), traces, ws, stream)
         return traces
 
     def traces(self, tracks: DeviceTracks, stream=None) -> torch.Tensor:
-        return self.accumulate(tracks, self.new_traces(), stream)
+        """New traces of the tracks, allocated and zeroed on ``stream``."""
+        with _on_stream(stream):
+            out = self.new_traces()
+        return self.accumulate(tracks, out, stream)
 
     def zhs_vjp(self, tracks: DeviceTracks, grad_traces: torch.Tensor, stream=None):
         """Gradients (qw [n], p0 [3, n], p1 [3, n], n0m1 [1]) of sum(grad * A),
@@ -460,27 +505,32 @@ class Plan:
         return self.vjp(tracks, grad_traces, stream)
 
     def vjp(self, tracks: DeviceTracks, grad_traces: torch.Tensor, stream=None):
-        """The vector-Jacobian product of the plan's formalism."""
+        """The vector-Jacobian product of the plan's formalism, on ``stream``
+        (default: the current one; with another torch.cuda.Stream the
+        outputs belong to that stream, which first waits for the current
+        one)."""
         dev = self.det.x.device
         n = tracks.n
-        g = grad_traces.to(self.dtype).contiguous()
-        if tuple(g.shape) != (self.det.m, self.det.n_bins, 3):
-            raise ValueError("grad_traces must be [M, n_bins, 3]")
-        gq = torch.empty(n, dtype=torch.float64, device=dev)
-        gp0 = torch.empty((3, n), dtype=torch.float64, device=dev)
-        gp1 = torch.empty((3, n), dtype=torch.float64, device=dev)
-        gn = torch.empty(1, dtype=torch.float64, device=dev)
-        ws = torch.empty(max(rt_plan_vjp_workspace_bytes(self.handle, n), 256), dtype=torch.uint8,
-                         device=dev)
-        fn = rt_zhs_vjp if self.formalism == RT_ZHS else rt_endpoint_vjp
-        fn(self.handle, tracks.struct(self.precision), g, gq, gp0, gp1, gn, ws, stream)
+        with _on_stream(stream):
+            g = grad_traces.to(self.dtype).contiguous()
+            if tuple(g.shape) != (self.det.m, self.det.n_bins, 3):
+                raise ValueError("grad_traces must be [M, n_bins, 3]")
+            gq = torch.empty(n, dtype=torch.float64, device=dev)
+            gp0 = torch.empty((3, n), dtype=torch.float64, device=dev)
+            gp1 = torch.empty((3, n), dtype=torch.float64, device=dev)
+            gn = torch.empty(1, dtype=torch.float64, device=dev)
+            ws = torch.empty(max(rt_plan_vjp_workspace_bytes(self.handle, n), 256),
+                             dtype=torch.uint8, device=dev)
+            fn = rt_zhs_vjp if self.formalism == RT_ZHS else rt_endpoint_vjp
+            fn(self.handle, tracks.struct(self.precision), g, gq, gp0, gp1, gn, ws, stream)
         return gq, gp0, gp1, gn
 
     def propagate(self, tracks: DeviceTracks, stream=None):
         shape = (2, tracks.n, self.det.m)
-        t = torch.empty(shape, dtype=torch.float64, device=self.det.x.device)
-        b = torch.empty(shape, dtype=torch.int32, device=self.det.x.device)
-        rt_propagate(self.handle, tracks.struct(self.precision), t, b, stream)
+        with _on_stream(stream):
+            t = torch.empty(shape, dtype=torch.float64, device=self.det.x.device)
+            b = torch.empty(shape, dtype=torch.int32, device=self.det.x.device)
+            rt_propagate(self.handle, tracks.struct(self.precision), t, b, stream)
         return t, b
 
 
