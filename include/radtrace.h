@@ -222,6 +222,22 @@ int rt_plan_workspace_bytes(const rt_plan *plan, int64_t n_tracks, size_t *bytes
 int rt_accumulate(rt_plan *plan, const rt_tracks *tracks, void *traces, void *workspace,
                   size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the call
+ * of rt_accumulate with the workspace taken from a device array of
+ * RT_STATIC_WORKSPACE_BYTES bytes that the library holds on each device until
+ * the process ends, so the caller passes only the tracks and the traces (as
+ * for rt_accumulate: device, [M][n_bins][3], +=). The call allocates
+ * nothing. A call whose workspace (rt_plan_workspace_bytes) exceeds the array
+ * returns RT_E_WORKSPACE with the sizes in rt_last_error (pass fewer tracks
+ * per call). The current device must be the plan's (RT_E_INVALID
+ * otherwise). Every call on one device uses the same array: calls that
+ * overlap in time on one device (two streams, two host threads) race and
+ * must be serialised by the caller; consecutive calls on one stream are
+ * safe. Results equal those of rt_accumulate with the same tiling. */
+#define RT_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int rt_accumulate_static(rt_plan *plan, const rt_tracks *tracks, void *traces, void *stream);
+
 /* Refractivity in device memory (the differentiable workflow, where n0 - 1
  * is a device tensor that changes between calls): with n0m1 non-NULL, every
  * later call on this plan (rt_accumulate, rt_propagate, the VJPs) reads

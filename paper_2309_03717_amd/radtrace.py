@@ -92,6 +92,8 @@ _lib.rt_plan_set_tiling.argtypes = [_P, C.POINTER(rt_tiling)]
 _lib.rt_plan_get_tiling.argtypes = [_P, C.c_int64, C.POINTER(rt_tiling)]
 _lib.rt_plan_workspace_bytes.argtypes = [_P, C.c_int64, C.POINTER(C.c_size_t)]
 _lib.rt_accumulate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
+_lib.rt_accumulate_static.argtypes = [_P, C.POINTER(rt_tracks), _P, _P]
+RT_STATIC_WORKSPACE_BYTES = 64 << 20   # include/radtrace.h
 _lib.rt_propagate.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, _P]
 _lib.rt_plan_set_timing_events.argtypes = [_P, _P, _P]
 _lib.rt_plan_set_n0m1_device.argtypes = [_P, _P]
@@ -276,6 +278,13 @@ def rt_accumulate(plan: int, tracks: rt_tracks, traces: torch.Tensor, workspace:
     _check(_lib.rt_accumulate(plan, C.byref(tracks), _ptr(traces), _ptr(workspace),
                               workspace.numel() * workspace.element_size(), _stream(stream)),
            "rt_accumulate")
+
+
+def rt_accumulate_static(plan: int, tracks: rt_tracks, traces: torch.Tensor, stream=None) -> None:
+    """rt_accumulate with the library's static device workspace (no
+    allocation; calls overlapping in time on one device race)."""
+    _check(_lib.rt_accumulate_static(plan, C.byref(tracks), _ptr(traces), _stream(stream)),
+           "rt_accumulate_static")
 
 
 def _event_handle(ev):
