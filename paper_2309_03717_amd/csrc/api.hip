@@ -245,11 +245,11 @@ int rt_plan_set_tiling(rt_plan *plan, const rt_tiling *tl) {
     return fail(RT_E_INVALID, "tracks_per_pass must be a non-negative multiple of 64");
   const size_t acc = rt::acc_bytes(plan->precision);
   const int seg = seg_in > 0 ? std::min(seg_in, plan->det.n_bins) : 0;
-  // a tile row holds the segment's bins plus rt::kTilePad padding bins
-  if (seg > 0 && (size_t)(seg + rt::kTilePad) * 3 * acc * (at > 0 ? at : 1) > plan->lds_per_block)
+  // a tile row holds the segment's bins plus the formalism's padding bins
+  const int pad = rt::tile_pad(plan->formalism);
+  if (seg > 0 && (size_t)(seg + pad) * 3 * acc * (at > 0 ? at : 1) > plan->lds_per_block)
     return fail(RT_E_UNSUPPORTED, "tile does not fit in LDS");
-  if (at > 0 && seg == 0 &&
-      (size_t)at * (plan->det.n_bins + rt::kTilePad) * 3 * acc > plan->lds_per_block)
+  if (at > 0 && seg == 0 && (size_t)at * (plan->det.n_bins + pad) * 3 * acc > plan->lds_per_block)
     return fail(RT_E_UNSUPPORTED,
                 "antennas_per_block x n_bins does not fit in LDS; also set bins_per_segment");
   plan->at_user = at;

@@ -221,7 +221,8 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     const int lo = w.seg * seg_len;
     const int hi = min(lo + seg_len, c.n_bins);
     const int row_len = (hi - lo) * 3;
-    const int stride = (seg_len + kTilePad) * 3;
+    const int f = FF >= 0 ? FF : uniform(sd.formalism);
+    const int stride = (seg_len + tile_pad(f)) * 3;
     for (int i = threadIdx.x; i < at * stride; i += blockDim.x) tile[i] = 0.0;
     const TileRef tr{tile, stride, lo, (double)lo, (double)hi, 0.0};
     if (HEAVY && c.medium == 3 && threadIdx.x < 2 * kGl)
@@ -234,7 +235,6 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     const int64_t b_end = min(uniform(sd.n_blocks), (int64_t)(w.split + 1) * per_split);
     constexpr int M0 = HEAVY ? 2 : 0, M1 = HEAVY ? 3 : 1;   // this kernel's two media
     const bool m1 = c.medium == M1;
-    const int f = FF >= 0 ? FF : uniform(sd.formalism);
     if (FF != 1 && f == 0) {
       if (m1)
         run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
@@ -431,8 +431,7 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
   const int at_cap = (opt && opt->max_antennas_per_tile > 0) ? opt->max_antennas_per_tile : 3;
   const size_t row_bytes = 3 * sizeof(acc_t);
   const size_t budget = lds_block - 256;   // room for the kernel's own LDS words
-  // a tile row holds a segment's bins plus kTilePad padding bins
-  const int max_bins = (int)(budget / row_bytes - kTilePad) / 64 * 64;
+
   b.sh.resize(n);
   int64_t max_slot = 0;
   for (int s = 0; s < n; ++s) {
@@ -440,12 +439,15 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     ShowerDesc &d = b.sh[s];
     const int B = in.det.n_bins;
     const rt_tiling *user = (opt && opt->per_shower) ? &opt->per_shower[s] : nullptr;
+    // a tile row holds a segment's bins plus the formalism's padding bins
+    const int pad = tile_pad(in.formalism);
+    const int max_bins = (int)(budget / row_bytes - pad) / 64 * 64;
     int seg = user && user->bins_per_segment > 0 ? std::min(user->bins_per_segment, B) : B;
     if (seg > max_bins) {   // equal segments, multiples of 64
       int segs = (B + max_bins - 1) / max_bins;
       seg = ((B + segs - 1) / segs + 63) / 64 * 64;
     }
-    const size_t tile_row = (size_t)(seg + kTilePad) * row_bytes;
+    const size_t tile_row = (size_t)(seg + pad) * row_bytes;
     int at = user && user->antennas_per_block > 0 ? user->antennas_per_block
                                                   : std::min<int>(at_cap, (int)(budget / tile_row));
     at = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)at, 3, in.det.n_antennas}));
@@ -468,7 +470,7 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
       d.tab_off = b.total_tab;
       b.total_tab += ((int64_t)c.n_tab + 31) / 32 * 32;
     }
-    if (d.n_blocks > 0) max_slot = std::max(max_slot, (int64_t)at * (seg + kTilePad) * 3);
+    if (d.n_blocks > 0) max_slot = std::max(max_slot, (int64_t)at * (seg + pad) * 3);
     b.total_pairs += in.tracks.n * in.det.n_antennas;
   }
   b.lds_bytes = (size_t)std::max<int64_t>(max_slot, 1) * sizeof(acc_t);

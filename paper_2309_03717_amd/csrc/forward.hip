@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int lo = seg * g.seg_len;
   const int hi = min(lo + g.seg_len, g.c.n_bins);
   const int row_len = (hi - lo) * 3;
-  const int stride = (g.seg_len + kTilePad) * 3;
+  const int stride = (g.seg_len + tile_pad(F)) * 3;
 
   for (int i = threadIdx.x; i < AT * stride; i += blockDim.x) tile[i] = 0.0;
 
@@ -371,15 +371,15 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
   const int B = p.det.n_bins;
   const int64_t M = p.det.n_antennas;
   const size_t budget = p.lds_per_block;
-  // a tile row holds the segment's bins plus kTilePad padding bins
+  // a tile row holds the segment's bins plus the formalism's padding bins
+  const int pad = tile_pad(p.formalism);
   int seg = p.seg_user > 0 ? p.seg_user : B;
-  if ((size_t)(seg + kTilePad) * 3 * acc > budget)
-    seg = (int)(budget / (3 * acc) - kTilePad) / 64 * 64;
+  if ((size_t)(seg + pad) * 3 * acc > budget) seg = (int)(budget / (3 * acc) - pad) / 64 * 64;
   if (seg > B) seg = B;
   if (seg < 1) seg = 1;
   t.seg_len = seg;
   t.n_segs = (B + seg - 1) / seg;
-  const size_t row_bytes = (size_t)(seg + kTilePad) * 3 * acc;
+  const size_t row_bytes = (size_t)(seg + pad) * 3 * acc;
   int at = p.at_user > 0 ? p.at_user : (int)(budget / row_bytes);
   if (at > kMaxTile) at = kMaxTile;
   if (at < 1) at = 1;

@@ -10,10 +10,13 @@ namespace rt {
 
 using acc_t = double;
 
-// Rows of an LDS trace tile carry kTilePad bins past the segment end, which
-// take the ZHS difference deposits that fall just beyond it (at most two bins:
-// the box's last bin is clamped to the segment end first) and are never read.
-constexpr int kTilePad = 2;
+// Rows of a ZHS trace tile carry two bins past the segment end, which take
+// the difference deposits that fall just beyond it (at most two bins: the
+// box's last bin is clamped to the segment end first) and are never read.
+// Endpoint impulses land inside the segment only.
+// (Measured: predicating those deposits instead costs the ZHS deposit 4%;
+// padding the Endpoint tile past 96 KiB cost its FP64 deposit 20%.)
+__host__ __device__ constexpr int tile_pad(int formalism) { return formalism == 1 ? 2 : 0; }
 
 // Fixed-point ZHS accumulation (RT_MIXED): every value v, scaled by the
 // call's power-of-two inverse unit s, is rounded to the nearest integer by
@@ -332,7 +335,7 @@ struct Tile {
 // fixed-point tiles the call's inverse unit.
 struct TileRef {
   lds<acc_t> *tile;
-  int stride;        // doubles per row: (segment bins + kTilePad) * 3
+  int stride;        // doubles per row: (segment bins + tile_pad) * 3
   int lo;            // first bin of the segment
   double lo_d, hi_d;
   double fx_inv;     // fixed-point tiles: 1 / unit (a power of two)
