@@ -18,11 +18,10 @@
  *    owned by the caller and must stay valid until the work enqueued on
  *    `stream` has completed. "host" pointers are read before the call returns.
  *  - `stream` is a hipStream_t passed as void* (NULL: the null stream). All
- *    device work of a call is enqueued on it; no call synchronizes the stream
- *    or allocates device memory, so calls may be captured into a HIP graph.
- *    The exceptions are the batch calls at the end of this header:
- *    rt_batch_create allocates and fills the batch's small device tables
- *    (synchronously) and rt_batch_destroy frees them.
+ *    device work of a call is enqueued on it; no call allocates device
+ *    memory, and no call except the autotuners synchronizes the stream, so
+ *    calls may be captured into a HIP graph (rt_batch_launch with the
+ *    condition stated there).
  *  - Every function returns an rt_status. On failure nothing is enqueued and
  *    rt_last_error() holds a description (per host thread).
  *    Invalid arguments give RT_E_INVALID; shapes the kernels do not support
@@ -329,6 +328,24 @@ int rt_endpoint_vjp(rt_plan *plan, const rt_tracks *tracks, const void *grad_tra
                     double *grad_qw, double *grad_p0, double *grad_p1, double *grad_n0m1,
                     void *workspace, size_t workspace_bytes, void *stream);
 
+/* Autotuner (the launch shapes of the hot loop chosen by measurement: tile
+ * width, track splits, workgroup size, bin segments, pass length). Times
+ * each of the n_candidates tilings (host array) with HIP events around real
+ * rt_accumulate calls on the caller's sample tracks: one warm-up call, then
+ * reps >= 1 timed calls, median kept. A candidate the plan refuses, or whose
+ * workspace (rt_plan_workspace_bytes with that tiling) exceeds
+ * workspace_bytes, is skipped (time -1). traces (device, [M][n_bins][3]) is
+ * scratch: it receives the sum of every timed call. Outputs: ms (host,
+ * n_candidates floats, may be NULL) and *best (host), the index of the
+ * fastest; the plan keeps that tiling (its previous tiling when none could
+ * be timed: RT_E_UNSUPPORTED). This call synchronizes `stream` (it reads the
+ * events) and allocates no device memory. Choosing candidates and caching
+ * the result per workload are the caller's (the Python binding keeps a JSON
+ * cache keyed by device and shapes). */
+int rt_plan_autotune(rt_plan *plan, const rt_tracks *sample, void *traces, void *workspace,
+                     size_t workspace_bytes, const rt_tiling *candidates, int32_t n_candidates,
+                     int32_t reps, void *stream, float *ms, int32_t *best);
+
 /* ------------------------------------------------------------------ batches
  *
  * Many independent showers in one launch. Each shower is one call of §2's
@@ -378,25 +395,28 @@ typedef struct {
   const rt_tiling *per_shower;
 } rt_batch_options;
 
-typedef struct rt_batch rt_batch;   /* opaque; host object plus device tables */
+typedef struct rt_batch rt_batch;   /* opaque; host object */
 
 /* Plans a batch of n_showers >= 1 showers (showers, options: host, read
  * during the call) for the current device, in one precision (RT_FP64 or
  * RT_MIXED, as for rt_plan_create) and with one field prefactor k. The batch
  * keeps every device pointer of `showers`; to run new inputs, overwrite those
- * buffers and launch again. Allocates the work-item, merge and shower tables
- * (a few bytes per item) on the device and copies them there before
- * returning. Output: *batch (free with rt_batch_destroy). */
+ * buffers and launch again. The work-item, merge and shower tables (a few
+ * bytes per item) are built on the host; the launches copy them into the
+ * workspace. Reads and allocates no device memory. Output: *batch (free
+ * with rt_batch_destroy). */
 int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_showers, int precision,
                     double k, const rt_batch_options *options);
 
-/* Frees a batch, its device tables and its graph (NULL is accepted). The
- * caller makes sure no launch of it is still running. */
+/* Frees a batch, its host tables and its graph (NULL is accepted). The
+ * caller makes sure no launch of it is still running (a launch copies the
+ * host tables asynchronously). */
 int rt_batch_destroy(rt_batch *batch);
 
-/* Device workspace (bytes) rt_batch_launch needs (per-track records of all
- * showers, one partial-trace slot per work item and the cumulative integral
- * of every tabulated shower's profile at its nodes). */
+/* Device workspace (bytes) rt_batch_launch needs (the batch's tables, the
+ * per-track records of all showers, one partial-trace slot per work item and
+ * the cumulative integral of every tabulated shower's profile at its
+ * nodes). */
 int rt_batch_workspace_bytes(const rt_batch *batch, size_t *bytes);
 
 /* Statistics of the plan (out: host; any pointer may be NULL): work items,
@@ -406,9 +426,28 @@ int rt_batch_get_info(const rt_batch *batch, int64_t *n_items, int32_t *n_workgr
 
 /* traces += contribution of the shower's tracks, for every shower (on
  * `stream`, see rt_batch_options.direct_launch for graphs). workspace:
- * device, >= rt_batch_workspace_bytes bytes, used by this launch only;
- * launches of one batch that overlap in time race on its device counter. */
+ * device, >= rt_batch_workspace_bytes bytes. A launch outside a stream
+ * capture first copies the batch's tables from host memory into the start of
+ * the workspace on `stream`; a launch on a stream the caller is capturing
+ * reuses the tables an earlier launch left in the same workspace (so launch
+ * once outside the capture with that workspace first; RT_E_INVALID
+ * otherwise), and the caller's graph replays rely on them staying there.
+ * Launches of one batch that overlap in time race on the workspace. */
 int rt_batch_launch(rt_batch *batch, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Autotuner of batches: plans the showers with each of the n_candidates
+ * launch shapes (host array of rt_batch_options; direct_launch is forced to
+ * 1) and times whole rt_batch_launch calls on the caller's workspace (one
+ * warm-up, then reps >= 1 timed launches, median kept). Candidates the
+ * planner refuses or whose workspace exceeds workspace_bytes are skipped
+ * (time -1). The showers' traces are scratch: they receive every timed
+ * launch. Outputs: ms (host, may be NULL), *best (host, the fastest index);
+ * RT_E_UNSUPPORTED when none could be timed. Synchronizes `stream`;
+ * allocates no device memory. */
+int rt_batch_autotune(const rt_shower *showers, int32_t n_showers, int precision, double k,
+                      const rt_batch_options *candidates, int32_t n_candidates, void *workspace,
+                      size_t workspace_bytes, int32_t reps, void *stream, float *ms,
+                      int32_t *best);
 
 /* Profiling aid: the next rt_batch_launch enqueues its kernels directly (not
  * through the graph) and records start_event before and stop_event after its

@@ -1,11 +1,13 @@
 """Launch-shape autotuner for batches and single plans.
 
-Candidate shapes are timed on the device with HIP events around real
-launches (same inputs, direct launches, warm-up first); the fastest is kept in
-a JSON cache keyed by the device (architecture and compute-unit count) and a
-signature of the workload's shapes, so that later runs of the same shapes
-reuse it without timing anything. The cache file is written atomically
-(temporary file + rename).
+The library's autotuners (rt_plan_autotune, rt_batch_autotune) time the
+candidate shapes on the device with HIP events around real launches (same
+inputs, direct launches, warm-up first); this module chooses the candidates,
+re-times the best families on the whole workload when a sample was timed, and
+keeps the fastest in a JSON cache keyed by the device (architecture and
+compute-unit count) and a signature of the workload's shapes, so that later
+runs of the same shapes reuse it without timing anything. The cache file is
+written atomically (temporary file + rename).
 """
 from __future__ import annotations
 
@@ -13,7 +15,6 @@ import hashlib
 import itertools
 import json
 import os
-import statistics
 import tempfile
 import time
 from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
@@ -63,40 +64,35 @@ def signature(parts: Iterable) -> str:
     return hashlib.sha1(json.dumps(list(parts)).encode()).hexdigest()[:16]
 
 
-# ------------------------------------------------------------------ timing
-def time_launches(fn: Callable[[], None], warmup: int = 1, reps: int = 3) -> float:
-    """Median seconds of fn() on the current stream, by HIP events."""
-    for _ in range(warmup):
-        fn()
-    times = []
-    for _ in range(reps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record()
-        fn()
-        b.record()
-        b.synchronize()
-        times.append(a.elapsed_time(b) * 1e-3)
-    return statistics.median(times)
-
-
-def tune(key: str, candidates: Sequence, measure: Callable[[object], float],
+def tune(key: str, candidates: Sequence, measure: Optional[Callable[[object], float]] = None,
          cache: Optional[TuningCache] = None, log: Optional[Callable[[str], None]] = None,
          final_measure: Optional[Callable[[object], float]] = None, finalists: int = 3,
-         family: Callable[[object], object] = lambda c: json.dumps(c)):
+         family: Callable[[object], object] = lambda c: json.dumps(c),
+         measure_all: Optional[Callable[[Sequence], Sequence]] = None):
     """The candidate with the smallest measure(candidate) (seconds), cached
     under key. A candidate whose measurement raises (for example a shape the
-    library rejects) is skipped. With final_measure (say, the whole workload
-    where measure times a sample), the fastest candidate of each of the
-    `finalists` fastest families (family(candidate): candidates that differ
-    only in a minor knob share one) is timed again by it and the fastest of
-    those wins. Returns (best, timings, from_cache)."""
+    library rejects) is skipped. measure_all(candidates) may replace measure:
+    one call returning the seconds of every candidate (None for a skipped
+    one). With final_measure (say, the whole workload where measure times a
+    sample), the fastest candidate of each of the `finalists` fastest
+    families (family(candidate): candidates that differ only in a minor knob
+    share one) is timed again by it and the fastest of those wins. Returns
+    (best, timings, from_cache)."""
     cache = cache if cache is not None else TuningCache()
     hit = cache.get(key)
     if hit is not None:
         return hit, None, True
     timings: List[Tuple[object, float]] = []
-    for c in candidates:
+    if measure_all is not None:
+        for c, t in zip(candidates, measure_all(list(candidates))):
+            if t is None:
+                if log:
+                    log(f"  {c}: skipped (refused, or beyond the workspace)")
+                continue
+            timings.append((c, t))
+            if log:
+                log(f"  {c}: {t * 1e3:.3f} ms")
+    for c in (candidates if measure_all is None else ()):
         try:
             t = measure(c)
         except (RuntimeError, ValueError) as e:
@@ -140,7 +136,7 @@ def batch_key(showers, precision: str) -> str:
 
 def tune_batch(showers, precision: str = "mixed", k: float = 1.0,
                cache_path: Optional[str] = None, candidates=None, sample_tracks: Optional[int] = None,
-               warmup: int = 1, reps: int = 2, log=None):
+               reps: int = 2, log=None):
     """BatchOptions for the showers (list of (DeviceDetector, medium,
     formalism, DeviceTracks)). Candidates are (block_threads, max antennas
     per tile, items per CU) triples (1024 threads with one-antenna tiles
@@ -155,21 +151,25 @@ def tune_batch(showers, precision: str = "mixed", k: float = 1.0,
     if sample_tracks is not None:
         sample = [(d, m, f, t.slice(0, min(t.n, sample_tracks))) for d, m, f, t in showers]
 
-    def timed(showers_, c, reps_):
-        opt = rt.BatchOptions(block_threads=c[0], max_antennas_per_tile=c[1], items_per_cu=c[2],
-                              direct_launch=1)
-        b = rt.Batch(showers_, precision, k, opt)
-        t = time_launches(b.launch, warmup, reps_)
-        del b
-        return t
+    def options(c):
+        return rt.BatchOptions(block_threads=c[0], max_antennas_per_tile=c[1], items_per_cu=c[2])
+
+    def timed(showers_, cs, reps_):   # one rt_batch_autotune call over the candidates
+        return rt.rt_batch_autotune(showers_, precision, k, [options(c) for c in cs], reps_)
 
     # shapes within a percent on the sample can order differently on the
     # whole batch: the best of the three best (workgroup size, tile width)
     # families are timed again on all tracks
-    final = (lambda c: timed(showers, c, 1)) if sample is not showers else None
-    best, timings, cached = tune(key, cands, lambda c: timed(sample, c, reps),
-                                 TuningCache(cache_path), log, final_measure=final,
-                                 family=lambda c: (c[0], c[1]))
+    def final(c):
+        t = timed(showers, [c], 1)[0]
+        if t is None:
+            raise RuntimeError(f"{c} could not be timed on the whole batch")
+        return t
+
+    best, timings, cached = tune(key, cands, None, TuningCache(cache_path), log,
+                                 final_measure=final if sample is not showers else None,
+                                 family=lambda c: (c[0], c[1]),
+                                 measure_all=lambda cs: timed(sample, cs, reps))
     return rt.BatchOptions(block_threads=best[0], max_antennas_per_tile=best[1],
                            items_per_cu=best[2]), timings, cached
 
@@ -185,20 +185,16 @@ def plan_key(plan, n_tracks: int) -> str:
     return f"plan/{device_key()}/{signature(shapes)}"
 
 
-def tune_plan(plan, tracks, cache_path: Optional[str] = None, candidates=None, warmup: int = 1,
-              reps: int = 2, log=None):
+def tune_plan(plan, tracks, cache_path: Optional[str] = None, candidates=None, reps: int = 2,
+              log=None):
     """Sets and returns the fastest (antennas_per_block, track_splits,
     block_threads, bins_per_segment, tracks_per_pass) tiling of a Plan for
     calls like plan.accumulate(tracks); candidates default to the automatic
     tile with every block size and pass length above."""
+    from . import radtrace as rt
     key = plan_key(plan, tracks.n)
     cands = candidates or [[0, 0, b, 0, p] for b in PLAN_BLOCKS for p in PLAN_PASSES]
-    traces = plan.new_traces()
-
-    def measure(c):
-        plan.set_tiling(*c)
-        return time_launches(lambda: plan.accumulate(tracks, traces), warmup, reps)
-
-    best, timings, cached = tune(key, cands, measure, TuningCache(cache_path), log)
+    best, timings, cached = tune(key, cands, None, TuningCache(cache_path), log,
+                                 measure_all=lambda cs: rt.rt_plan_autotune(plan, tracks, cs, reps))
     plan.set_tiling(*best)
     return list(best), timings, cached

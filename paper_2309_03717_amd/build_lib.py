@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libradtrace.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "forward.hip", "adjoint.hip", "batch.hip", "filter.hip", "static_ws.hip"]
+SOURCES = ["api.hip", "forward.hip", "adjoint.hip", "batch.hip", "filter.hip", "static_ws.hip",
+           "autotune.hip"]
 ARCH = os.environ.get("RADTRACE_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-ffp-contract=off",

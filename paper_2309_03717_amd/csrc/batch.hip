@@ -13,6 +13,7 @@
 // replayed by later launches.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -321,12 +322,16 @@ struct rt_batch {
   int32_t group_begin[rt::kGroups + 1] = {0, 0, 0, 0};   // items, grouped
   int64_t total_blocks = 0, total_partial = 0, total_pairs = 0;
   int64_t total_tab = 0;       // doubles of the tabulated showers' F tables
-  rt::ShowerDesc *d_sh = nullptr;
-  rt::WorkItem *d_items = nullptr;
-  rt::MergeTask *d_merges = nullptr;
-  int64_t *d_cum = nullptr;
-  int *d_counter = nullptr;
-  hipStream_t cap_stream = nullptr;
+  // the device tables (shower descriptors, work items, merge tasks,
+  // cumulative record blocks, item counters) live at the start of the
+  // caller's workspace; host_tables is their image, copied there by the
+  // launches (offsets: tab_off[]), and tables_ws the workspace that last
+  // received it
+  std::vector<unsigned char> host_tables;
+  size_t tab_off[5] = {0, 0, 0, 0, 0};
+  size_t tables_bytes = 0;
+  void *tables_ws = nullptr;
+  hipStream_t cap_stream = nullptr;   // created when a graph is first built
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void *cap_ws = nullptr;
@@ -345,25 +350,47 @@ static size_t partial_bytes(const rt_batch &b) {
   return align256((size_t)b.total_partial * sizeof(acc_t));
 }
 
-// records, partial slots, then the F tables of the tabulated showers
+// the batch's tables, records, partial slots, then the F tables of the
+// tabulated showers
 size_t batch_workspace_bytes(const rt_batch &b) {
-  return record_bytes(b) + partial_bytes(b) + align256((size_t)b.total_tab * sizeof(double));
+  return b.tables_bytes + record_bytes(b) + partial_bytes(b) +
+         align256((size_t)b.total_tab * sizeof(double));
+}
+
+// The host image of the device tables, each part 256-byte aligned: shower
+// descriptors, work items, merge tasks, cumulative record blocks, and the
+// kGroups item counters (reset by every launch).
+static void build_table_image(rt_batch &b) {
+  const size_t sizes[5] = {b.sh.size() * sizeof(ShowerDesc), b.items.size() * sizeof(WorkItem),
+                           b.merges.size() * sizeof(MergeTask), b.cum.size() * sizeof(int64_t),
+                           kGroups * sizeof(int)};
+  const void *src[5] = {b.sh.data(), b.items.data(), b.merges.data(), b.cum.data(), nullptr};
+  size_t off = 0;
+  for (int i = 0; i < 5; ++i) {
+    b.tab_off[i] = off;
+    off += align256(sizes[i]);
+  }
+  b.tables_bytes = off;
+  b.host_tables.assign(off, 0);
+  for (int i = 0; i < 4; ++i)
+    if (sizes[i]) std::memcpy(b.host_tables.data() + b.tab_off[i], src[i], sizes[i]);
 }
 
 static BatchArgs batch_args(const rt_batch &b, void *workspace) {
   BatchArgs a;
-  a.sh = b.d_sh;
-  a.items = b.d_items;
-  a.merges = b.d_merges;
-  a.cum_blocks = b.d_cum;
+  char *ws = reinterpret_cast<char *>(workspace);
+  a.sh = reinterpret_cast<const ShowerDesc *>(ws + b.tab_off[0]);
+  a.items = reinterpret_cast<const WorkItem *>(ws + b.tab_off[1]);
+  a.merges = reinterpret_cast<const MergeTask *>(ws + b.tab_off[2]);
+  a.cum_blocks = reinterpret_cast<const int64_t *>(ws + b.tab_off[3]);
+  a.counter = reinterpret_cast<int *>(ws + b.tab_off[4]);
   a.n_showers = (int32_t)b.sh.size();
   a.n_items = (int32_t)b.items.size();
   for (int g = 0; g <= kGroups; ++g) a.group_begin[g] = b.group_begin[g];
-  a.counter = b.d_counter;
-  char *ws = reinterpret_cast<char *>(workspace);
-  a.rec = reinterpret_cast<double *>(ws);
-  a.partial = reinterpret_cast<double *>(ws + record_bytes(b));
-  a.tables = reinterpret_cast<double *>(ws + record_bytes(b) + partial_bytes(b));
+  char *data = ws + b.tables_bytes;
+  a.rec = reinterpret_cast<double *>(data);
+  a.partial = reinterpret_cast<double *>(data + record_bytes(b));
+  a.tables = reinterpret_cast<double *>(data + record_bytes(b) + partial_bytes(b));
   a.total_blocks = b.total_blocks;
   return a;
 }
@@ -397,7 +424,7 @@ static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t 
                                 hipEvent_t ev0, hipEvent_t ev1) {
   if (b.items.empty()) return hipSuccess;
   BatchArgs a = batch_args(b, workspace);
-  batch_reset_kernel<<<1, 64, 0, stream>>>(b.d_counter);
+  batch_reset_kernel<<<1, 64, 0, stream>>>(a.counter);
   if (b.total_tab > 0) batch_tables_kernel<<<(unsigned)b.sh.size(), 64, 0, stream>>>(a);
   const unsigned pblocks = (unsigned)std::min<int64_t>((b.total_blocks * 64 + 255) / 256, 1 << 16);
   if (b.precision == RT_FP64)
@@ -545,23 +572,10 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
   return "";
 }
 
-template <class T>
-static hipError_t upload(T **dst, const std::vector<T> &src) {
-  if (src.empty()) return hipSuccess;
-  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
-  if (e != hipSuccess) return e;
-  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
-}
-
 static void release(rt_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
-  (void)hipFree(b->d_sh);
-  (void)hipFree(b->d_items);
-  (void)hipFree(b->d_merges);
-  (void)hipFree(b->d_cum);
-  (void)hipFree(b->d_counter);
   delete b;
 }
 
@@ -620,21 +634,17 @@ int rt_batch_create(rt_batch **batch, const rt_shower *showers, int32_t n_shower
     delete b;
     return rt_fail(RT_E_UNSUPPORTED, err);
   }
+  rt::build_table_image(*b);
   (void)hipGetLastError();
-  hipError_t e = rt::upload(&b->d_sh, b->sh);
-  if (e == hipSuccess) e = rt::upload(&b->d_items, b->items);
-  if (e == hipSuccess) e = rt::upload(&b->d_merges, b->merges);
-  if (e == hipSuccess) e = rt::upload(&b->d_cum, b->cum);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, rt::kGroups * sizeof(int));
+  hipError_t e = hipSuccess;
   for (int g = 0; g < rt::kGroups && e == hipSuccess; ++g) {
     int threads = 0;
     e = hipFuncSetAttribute((const void *)rt::deposit_fn(*b, g, &threads),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes);
   }
-  if (e == hipSuccess && !b->direct) e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     rt::release(b);
-    return rt_hip_fail(e, "setting up the batch tables");
+    return rt_hip_fail(e, "setting up the batch kernels");
   }
   *batch = b;
   return RT_OK;
@@ -684,6 +694,20 @@ int rt_batch_launch(rt_batch *batch, void *workspace, size_t workspace_bytes, vo
     hipError_t e = hipStreamIsCapturing(s, &cap);
     if (e != hipSuccess) return rt_hip_fail(e, "querying the stream's capture state");
   }
+  // the tables: copied into the workspace on the launch stream before every
+  // launch outside a capture (the host image persists until
+  // rt_batch_destroy); a launch inside the caller's capture reuses the copy
+  // an earlier launch left in this workspace
+  if (cap == hipStreamCaptureStatusNone) {
+    hipError_t e = hipMemcpyAsync(workspace, batch->host_tables.data(), batch->tables_bytes,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return rt_hip_fail(e, "copying the batch tables");
+    batch->tables_ws = workspace;
+  } else if (batch->tables_ws != workspace) {
+    return rt_fail(RT_E_INVALID,
+                   "a launch inside a stream capture needs the batch tables in its workspace: "
+                   "launch once with this workspace outside the capture first");
+  }
   const bool timed = batch->ev_start != nullptr;
   if (batch->direct || timed || cap != hipStreamCaptureStatusNone) {
     hipError_t e = rt::batch_enqueue(*batch, workspace, s, batch->ev_start, batch->ev_stop);
@@ -692,6 +716,10 @@ int rt_batch_launch(rt_batch *batch, void *workspace, size_t workspace_bytes, vo
     return RT_OK;
   }
   if (!batch->exec || batch->cap_ws != workspace) {
+    if (!batch->cap_stream) {
+      hipError_t e = hipStreamCreateWithFlags(&batch->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return rt_hip_fail(e, "creating the capture stream");
+    }
     if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
     if (batch->graph) (void)hipGraphDestroy(batch->graph);
     batch->exec = nullptr;

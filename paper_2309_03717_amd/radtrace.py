@@ -111,6 +111,12 @@ _lib.rt_batch_set_timing_events.argtypes = [_P, _P, _P]
 _lib.rt_filter_tracks.argtypes = [C.POINTER(rt_tracks), C.c_int, C.c_double,
                                   C.POINTER(rt_tracks), _P, _P, C.c_size_t, _P]
 _lib.rt_filter_workspace_bytes.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+_lib.rt_plan_autotune.argtypes = [_P, C.POINTER(rt_tracks), _P, _P, C.c_size_t,
+                                  C.POINTER(rt_tiling), C.c_int32, C.c_int32, _P,
+                                  C.POINTER(C.c_float), C.POINTER(C.c_int32)]
+_lib.rt_batch_autotune.argtypes = [C.POINTER(rt_shower), C.c_int32, C.c_int, C.c_double,
+                                   C.POINTER(rt_batch_options), C.c_int32, _P, C.c_size_t,
+                                   C.c_int32, _P, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
 
 
 class RadtraceError(RuntimeError):
@@ -578,6 +584,74 @@ class BatchOptions:
         return o, keep
 
 
+def rt_plan_autotune(plan: "Plan", tracks: "DeviceTracks", tilings, reps: int = 2,
+                  stream=None):
+    """rt_plan_autotune: times each tiling (tuples of the five rt_tiling
+    fields) on the tracks; returns the median seconds per candidate (None for
+    a skipped one) and leaves the fastest tiling set on the plan. Allocates
+    one workspace for the largest candidate and a scratch trace tensor."""
+    cands = (rt_tiling * len(tilings))(*[rt_tiling(*map(int, t)) for t in tilings])
+    need = 0
+    for t in cands:   # the workspace of the largest candidate
+        if _lib.rt_plan_set_tiling(plan.handle, C.byref(t)) == RT_OK:
+            need = max(need, rt_plan_workspace_bytes(plan.handle, tracks.n))
+    dev = plan.det.x.device
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    scratch = plan.new_traces()
+    ms = (C.c_float * len(tilings))()
+    best = C.c_int32(-1)
+    _check(_lib.rt_plan_autotune(plan.handle, C.byref(tracks.struct(plan.precision)),
+                                 _ptr(scratch), _ptr(ws), ws.numel(), cands, len(tilings),
+                                 int(reps), _stream(stream), ms, C.byref(best)),
+           "rt_plan_autotune")
+    return [m * 1e-3 if m >= 0 else None for m in ms]
+
+
+def _shower_structs(showers, precision: int, traces=None):
+    """rt_shower structures for (DeviceDetector, medium, formalism name,
+    DeviceTracks) tuples, with new zeroed traces unless given; returns the
+    structures and the tensors they point into (keep them alive)."""
+    dtype = torch.float64 if precision == RT_FP64 else torch.float32
+    structs, keep, out = [], [], []
+    for i, (det, medium, formalism, tracks) in enumerate(showers):
+        tr = traces[i] if traces is not None else torch.zeros(
+            (det.m, det.n_bins, 3), dtype=dtype, device=det.x.device)
+        table = _device_table(medium, det.x.device)
+        out.append(tr)
+        keep.append(table)
+        structs.append(rt_shower(det.struct(), _medium_struct(medium, table),
+                                 FORMALISM[formalism], tracks.struct(precision), _ptr(tr)))
+    return structs, keep, out
+
+
+def rt_batch_autotune(showers, precision: str, k: float, options, reps: int = 2, stream=None):
+    """rt_batch_autotune: times a whole launch of the showers with each
+    BatchOptions; returns the median seconds per candidate (None for a
+    skipped one). The traces are scratch tensors of this call."""
+    prec = PRECISION[precision]
+    structs, keep, traces = _shower_structs(showers, prec)
+    arr = (rt_shower * len(structs))(*structs)
+    opts, keeps = zip(*[o.struct() for o in options])
+    oarr = (rt_batch_options * len(opts))(*opts)
+    need = 0
+    for o in opts:   # the workspace of the largest candidate (host planning only)
+        h = _P()
+        if _lib.rt_batch_create(C.byref(h), arr, len(structs), prec, float(k), C.byref(o)) == RT_OK:
+            n = C.c_size_t(0)
+            _lib.rt_batch_workspace_bytes(h, C.byref(n))
+            need = max(need, n.value)
+            _lib.rt_batch_destroy(h)
+    dev = traces[0].device if traces else "cuda"
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    ms = (C.c_float * len(opts))()
+    best = C.c_int32(-1)
+    _check(_lib.rt_batch_autotune(arr, len(structs), prec, float(k), oarr, len(opts), _ptr(ws),
+                                  ws.numel(), int(reps), _stream(stream), ms, C.byref(best)),
+           "rt_batch_autotune")
+    del keeps, keep
+    return [m * 1e-3 if m >= 0 else None for m in ms]
+
+
 class Batch:
     """Many showers in one persistent launch (rt_batch_*). showers: a list of
     (DeviceDetector, medium, formalism name, DeviceTracks). The batch owns one
@@ -590,17 +664,7 @@ class Batch:
         self.dtype = torch.float64 if self.precision == RT_FP64 else torch.float32
         self.inputs = list(showers)
         self.options = options or BatchOptions()
-        self.traces = []
-        structs = []
-        self._tables = []
-        for det, medium, formalism, tracks in self.inputs:
-            tr = torch.zeros((det.m, det.n_bins, 3), dtype=self.dtype, device=det.x.device)
-            self.traces.append(tr)
-            table = _device_table(medium, det.x.device)
-            self._tables.append(table)
-            structs.append(rt_shower(det.struct(), _medium_struct(medium, table),
-                                     FORMALISM[formalism], tracks.struct(self.precision),
-                                     _ptr(tr)))
+        structs, self._tables, self.traces = _shower_structs(self.inputs, self.precision)
         opt, keep = self.options.struct()
         self.handle = rt_batch_create(structs, self.precision, k, opt)
         self.info = rt_batch_get_info(self.handle)

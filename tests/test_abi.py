@@ -105,7 +105,29 @@ def test_null_plan_arguments(rt):
     assert rt._lib.rt_plan_set_tiling(None, C.byref(rt.rt_tiling())) == rt.RT_E_INVALID
     tr = rt.rt_tracks()
     assert rt._lib.rt_accumulate(None, C.byref(tr), None, None, 0, None) == rt.RT_E_INVALID
+    assert rt._lib.rt_accumulate_static(None, C.byref(tr), None, None) == rt.RT_E_INVALID
     assert rt._lib.rt_propagate(None, C.byref(tr), None, None, None) == rt.RT_E_INVALID
+    assert rt._lib.rt_plan_set_n0m1_device(None, None) == rt.RT_E_INVALID
+
+
+def test_autotuners_reject_invalid_arguments(rt):
+    """Both autotuners check their arguments before touching a device."""
+    tr = rt.rt_tracks()
+    cands = (rt.rt_tiling * 1)()
+    ms = (C.c_float * 1)()
+    best = C.c_int32(7)
+    assert rt._lib.rt_plan_autotune(None, C.byref(tr), None, None, 0, cands, 1, 1, None, ms,
+                                    C.byref(best)) == rt.RT_E_INVALID
+    assert "required" in rt.rt_last_error()
+    sh, keep = _shower(rt)
+    opts = (rt.rt_batch_options * 1)()
+    assert rt._lib.rt_batch_autotune(None, 1, rt.RT_FP64, 1.0, opts, 1, None, 0, 1, None, ms,
+                                     C.byref(best)) == rt.RT_E_INVALID
+    assert rt._lib.rt_batch_autotune(C.byref(sh), 1, rt.RT_FP64, 1.0, opts, 0, None, 0, 1, None,
+                                     ms, C.byref(best)) == rt.RT_E_INVALID
+    assert rt._lib.rt_batch_autotune(C.byref(sh), 1, rt.RT_FP64, 1.0, opts, 1, None, 0, 0, None,
+                                     ms, C.byref(best)) == rt.RT_E_INVALID
+    assert "reps" in rt.rt_last_error()
 
 
 def _shower(rt):
@@ -315,3 +337,20 @@ def test_filter_rejects_invalid_arguments(rt, case):
     st = rt._lib.rt_filter_tracks(*args)
     want = rt.RT_E_WORKSPACE if case == "small_workspace" else rt.RT_E_INVALID
     assert st == want, (case, st, rt.rt_last_error())
+
+
+def test_library_sources_allocate_no_device_memory():
+    """The caller owns every device buffer (workspaces included): no source
+    of the library calls a device allocator or free (the static workspace
+    of rt_accumulate_static is a device array of the code object)."""
+    import glob
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    call = re.compile(r"\bhip(Malloc\w*|ExtMalloc\w*|Free\w*|HostMalloc|HostAlloc|MemPool\w*)\s*\(")
+    sources = glob.glob(os.path.join(root, "paper_2309_03717_amd", "csrc", "*"))
+    assert sources
+    for f in sources:
+        with open(f) as fh:
+            for i, line in enumerate(fh, 1):
+                assert not call.search(line.split("//")[0]), f"{f}:{i}: {line.strip()}"

@@ -365,3 +365,39 @@ def test_autotuner_picks_and_caches(rt, tmp_path):
     got = fetch(rt.Batch(dev, "mixed", options=opt).launch())
     for g, e in zip(got, ref):
         assert np.abs(g - e).max() <= 1e-6 * max(np.abs(e).max(), 1e-30)
+
+
+def test_batch_autotune_entry_point_times_every_candidate(rt):
+    """rt_batch_autotune through the binding: one time per candidate, None
+    for a candidate the planner refuses (a tile wider than three antennas),
+    and the showers' own traces untouched (the tuner's launches go to
+    scratch traces)."""
+    showers = small_showers(4, 1500)
+    dev = device_showers(rt, showers, "mixed")
+    cands = [rt.BatchOptions(block_threads=256, max_antennas_per_tile=1, items_per_cu=2),
+             rt.BatchOptions(block_threads=512, max_antennas_per_tile=4),
+             rt.BatchOptions(block_threads=1024, max_antennas_per_tile=1, items_per_cu=4)]
+    times = rt.rt_batch_autotune(dev, "mixed", 1.0, cands, reps=2)
+    assert len(times) == 3 and times[1] is None
+    assert times[0] > 0 and times[2] > 0
+
+
+def test_batch_tables_travel_in_the_workspace(rt):
+    """The batch's tables live in the caller's workspace: two batches of
+    different showers launched alternately on one shared workspace (each
+    launch copies its own tables first) give each batch's own results."""
+    import torch
+    a_sh, b_sh = small_showers(3, 1000), small_showers(6, 1200)[3:]
+    a = rt.Batch(device_showers(rt, a_sh, "mixed"), "mixed", options=rt.BatchOptions(direct_launch=1))
+    b = rt.Batch(device_showers(rt, b_sh, "mixed"), "mixed", options=rt.BatchOptions(direct_launch=1))
+    ref_a, ref_b = fetch(a.launch()), fetch(b.launch())
+    shared = torch.empty(max(a.workspace.numel(), b.workspace.numel()), dtype=torch.uint8,
+                         device="cuda")
+    for bt in (a, b):
+        bt.zero_traces()
+    for _ in range(2):
+        rt.rt_batch_launch(a.handle, shared)
+        rt.rt_batch_launch(b.handle, shared)
+    for got, ref in ((fetch(a.traces), ref_a), (fetch(b.traces), ref_b)):
+        for g, e in zip(got, ref):
+            np.testing.assert_allclose(g, 2 * e, rtol=0, atol=1e-5 * max(np.abs(e).max(), 1e-30))
