@@ -18,16 +18,17 @@
 // Endpoint deposit, bound by record delivery, also loads each record one wave
 // block ahead (register double-buffering).
 //
-// Precision. Accumulation in LDS and in the split partials is double in both
-// modes: gfx950 executes LDS double-precision atomic adds (ds_add_f64) at close
-// to the rate of plain LDS stores, while single-precision ones (ds_add_f32)
-// are several times slower on this workload. In RT_MIXED the arrival time and
-// bin are computed exactly as in RT_FP64; the amplitude uses the hardware
-// reciprocal / reciprocal square root refined by one Newton step (about 28
-// correct bits) instead of correctly rounded division, in double precision,
-// because unpacked single-precision arithmetic runs at the double-precision
-// rate on this chip and would only add conversions. Tracks carry beta and qw
-// as float and the traces are float in RT_MIXED.
+// Precision. The LDS tiles accumulate in double (ds_add_f64), or for RT_MIXED
+// ZHS calls in 64-bit fixed point (ds_add_u64, exact and order-independent):
+// on gfx950 a single-precision LDS atomic add (ds_add_f32) executes about 13x
+// slower than ds_add_f64 at any address pattern, and ds_add_u64 about twice as
+// fast. In RT_MIXED the arrival time and bin are computed exactly as in
+// RT_FP64; the amplitude uses the hardware reciprocal / reciprocal square root
+// refined by one Newton step (relative error at most a few 1e-15) instead of
+// correctly rounded division, in double precision, because unpacked
+// single-precision arithmetic runs at the double-precision rate on this chip
+// and would only add conversions. Tracks carry beta and qw as float and the
+// traces are float in RT_MIXED.
 #include "rt_deposit.h"
 #include "rt_internal.h"
 

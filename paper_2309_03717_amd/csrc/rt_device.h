@@ -174,8 +174,11 @@ __device__ __forceinline__ double path_index(double zp, double za, double pp, do
   return 1.0 + c.n0m1 * exp(-(((zp + za) * 0.5) / c.h));
 }
 
-// 1/x and 1/sqrt(x) from the hardware estimate plus one Newton step (about
-// 1e-15 relative; the mixed-precision amplitudes and adjoints use them).
+// 1/x and 1/sqrt(x) from the hardware estimate plus one Newton step, which
+// squares the estimate's relative error: measured on gfx950 over 1.3e8
+// log-uniform inputs in [1e-6, 1e12], at most 2.2e-15 (fast_rcp) and 4.3e-15
+// (fast_rsq), from estimates good to 4.6e-8 and 5.3e-8. The mixed-precision
+// amplitudes and adjoints use them.
 __device__ __forceinline__ double fast_rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);

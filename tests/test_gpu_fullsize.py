@@ -178,3 +178,27 @@ def test_shower_like_stream_sampled_antennas(rt, orc, formalism):
     print(formalism, "shower-like: max rel L2", err.max())
     assert np.abs(ref).max() > 0
     assert err.max() <= MIXED_BOUND
+
+
+@pytest.mark.parametrize("formalism", ["endpoint", "zhs"])
+def test_grid4096_one_pass_every_antenna(rt, orc, formalism):
+    """One 2^20-track pass of the grid workload (the launch the bench times:
+    2^20-track passes, eight ZHS splits, one 4096-bin tile per workgroup in
+    the XCD-major block order) over all 4096 antennas, every antenna against
+    the oracle (4.3e9 pairs): mixed bound per antenna, and for the Endpoint
+    the same set of nonzero bins as the oracle (no impulse misplaced)."""
+    import torch
+    w = W.config(2)
+    tr = w.tracks(1 << 20, mixed=True)
+    det = rt.DeviceDetector.from_array(w.array)
+    plan = rt.Plan(det, w.medium, formalism, "mixed", 1.0)
+    assert plan.tiling(tr.n)[4] == 1 << 20   # one pass
+    gpu = plan.traces(rt.DeviceTracks.from_tracks(tr))
+    torch.cuda.synchronize()
+    gpu = gpu.cpu().numpy().astype(np.float64)
+    ref = orc.traces(formalism, tr.widened(), w.array, w.medium, k=1.0, n_threads=THREADS)
+    err = rel_l2(gpu, ref)
+    print(f"{formalism}: 4096 antennas, max rel L2 {err.max():.3e}, median {np.median(err):.3e}")
+    assert err.max() <= MIXED_BOUND
+    if formalism == "endpoint":
+        np.testing.assert_array_equal(gpu != 0, ref != 0)
