@@ -22,13 +22,16 @@
 // ZHS calls in 64-bit fixed point (ds_add_u64, exact and order-independent):
 // on gfx950 a single-precision LDS atomic add (ds_add_f32) executes about 13x
 // slower than ds_add_f64 at any address pattern, and ds_add_u64 about twice as
-// fast. In RT_MIXED the arrival time and bin are computed exactly as in
-// RT_FP64; the amplitude uses the hardware reciprocal / reciprocal square root
-// refined by one Newton step (relative error at most a few 1e-15) instead of
-// correctly rounded division, in double precision, because unpacked
-// single-precision arithmetic runs at the double-precision rate on this chip
-// and would only add conversions. Tracks carry beta and qw as float and the
-// traces are float in RT_MIXED.
+// fast. In RT_MIXED the Endpoint arrival time and bin are computed exactly as
+// in RT_FP64 (an impulse's bin is a step function of its time) and its
+// amplitude uses the hardware reciprocals refined by one Newton step
+// (relative error a few 1e-15); the ZHS box, continuous in the arrival times,
+// takes them from a square root good to 5e-15 and from times and path
+// indices stored in bins, and its amplitude and weights from the unrefined
+// hardware estimates (5e-8, single-precision accuracy). All of it runs in
+// double precision: unpacked single-precision arithmetic issues at the same
+// rate on this chip and would only add conversions. Tracks carry beta and qw
+// as float and the traces are float in RT_MIXED.
 #include "rt_deposit.h"
 #include "rt_internal.h"
 
@@ -89,7 +92,7 @@ __global__ void __launch_bounds__(kPrepThreads) prepare_kernel(PrepArgs g) {
        i += (int64_t)gridDim.x * blockDim.x) {
     double v[kRec];
     make_record<F, P>(g.tr, i, i < g.tr.n, c, z_ref, e_ref, v);
-    store_record<P>(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v);
+    store_record<F, P>(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v);
     if (kFx && g.fx_part) {
       const double b = zhs_track_bound(v, g.bbox);
       bsum += b;

@@ -44,15 +44,15 @@ struct Prec<1> {  // RT_MIXED
 // ------------------------------------------------------------------ track record
 
 // Per-track record, kRec doubles per track, blocked by waves of 64 tracks.
-// FP64 records are stored in field pairs (2g, 2g + 1): field f of track
+// Paired records are stored in field pairs (2g, 2g + 1): field f of track
 // 64 b + l is rec[(b * kRec + (f & ~1)) * 64 + 2 l + (f & 1)], so one 16-byte
 // load per lane brings a pair and a wave reads it as one contiguous 1-KB run.
-// Mixed records keep one field per run: rec[(b * kRec + f) * 64 + l], one
-// 8-byte load per lane and field (measured faster for their deposits, the
-// paired layout faster for the FP64 ones).
+// Mixed Endpoint records keep one field per run: rec[(b * kRec + f) * 64 + l],
+// one 8-byte load per lane and field (measured faster for that deposit, the
+// paired layout faster for the FP64 ones and the mixed ZHS one).
 constexpr int kRec = 16;
-template <int P>
-constexpr bool paired_records() { return P == 0; }
+template <int F, int P>
+constexpr bool paired_records() { return P == 0 || F == 1; }
 enum : int {
   R_X0, R_Y0, R_Z0, R_T0,  // start point and time
   R_X1, R_Y1, R_Z1, R_T1,  // end point and time
@@ -68,7 +68,9 @@ enum : int {
 // rounded index would dominate the error). A wave reads 12 of the 16 slots
 // (10 without the path indices: uniform medium, spherical Earth), plus the
 // height factors where the Endpoint needs the source index or a tile antenna
-// sits off the reference height.
+// sits off the reference height. Mixed ZHS records hold the times in bins
+// (t / dt) and the path indices over c dt, the operands of
+// arrival_bins_scaled.
 enum : int { M_AB = 10, M_YZ = 11, M_E0 = 12, M_E1 = 13 };
 
 __device__ __forceinline__ double pack2(float lo, float hi) {
@@ -104,9 +106,9 @@ constexpr bool pairs_agree() {
 }
 
 // Writes the record v of lane l into its wave block.
-template <int P>
+template <int F, int P>
 __device__ __forceinline__ void store_record(double *blk, int l, const double *v) {
-  if constexpr (paired_records<P>()) {
+  if constexpr (paired_records<F, P>()) {
 #pragma unroll
     for (int g = 0; g < kRec; g += 2)
       *reinterpret_cast<double2 *>(blk + g * 64 + 2 * l) = make_double2(v[g], v[g + 1]);
@@ -120,9 +122,9 @@ __device__ __forceinline__ void store_record(double *blk, int l, const double *v
 // Reads the slots of lane l's paired record that a deposit uses
 // (slot_loaded), one pair per load; the other slots read as 0. (Mixed records
 // are read field by field where they are used.)
-template <int P, int MED, bool H>
+template <int F, int P, int MED, bool H>
 __device__ __forceinline__ void load_record_pairs(const double *blk, int l, double *v) {
-  static_assert(paired_records<P>() && pairs_agree<P, MED, H>(),
+  static_assert(paired_records<F, P>() && pairs_agree<P, MED, H>(),
                 "paired records, loaded a whole pair at a time");
 #pragma unroll
   for (int g = 0; g < kRec; g += 2) {
@@ -193,6 +195,13 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
     v[M_E0] = e0;
     v[M_E1] = e1;
     v[14] = v[15] = 0.0;
+    if (F == 1) {
+      const double k = c.inv_c * c.inv_dt;
+      v[R_T0] *= c.inv_dt;
+      v[R_T1] *= c.inv_dt;
+      v[R_NE0] *= k;
+      v[R_NE1] *= k;
+    }
   }
 }
 
@@ -264,14 +273,17 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
   double ex = dx0 + dx1, ey = dy0 + dy1, ez = dz0 + dz1;
   double e2 = fma(ex, ex, fma(ey, ey, ez * ez));
   if (e2 == 0.0) return;
-  double rinv = P == 0 ? 1.0 / sqrt(e2) : fast_rsq(e2);
+  // RT_MIXED: 1 / R_m and 1 / width from the hardware estimates (relative
+  // errors at most 5.3e-8 and 4.6e-8, a single-precision amplitude's
+  // accuracy); the arrival times stay double
+  double rinv = P == 0 ? 1.0 / sqrt(e2) : __builtin_amdgcn_rsq(e2);
   double q = fma(bx, ex, fma(by, ey, bz * ez)) * (rinv * rinv);
   double s = cz2 * rinv;
   double ix = fma(-ex, q, bx) * s, iy = fma(-ey, q, by) * s, iz = fma(-ez, q, bz) * s;
   double kl = floor(ulo), kh = floor(uhi);
   const bool one = kl == kh, two = kh == kl + 1.0;
   double w = uhi - ulo;
-  double wi = P == 0 ? 1.0 / w : fast_rcp(w);
+  double wi = P == 0 ? 1.0 / w : __builtin_amdgcn_rcp(w);
   double flo = (kl + 1.0) - ulo;   // share of bin kl, in (0, 1]
   double fhi = uhi - kh;           // share of bin kh, in [0, 1)
   double a = flo * wi, bb = fhi * wi;
@@ -327,6 +339,7 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
 template <int AT>
 struct Tile {
   double ax[AT], ay[AT], az[AT], tau[AT], ea[AT];
+  double taub[AT];   // window opening in bins, tau / dt
   bool at_ref[AT];   // at the height of antenna 0: the record's path index applies
 };
 
@@ -396,6 +409,22 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
         ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
       }
       lds<acc_t> *row = tr.row(a);
+      if constexpr (F == 1 && P == 1) {
+        // times in bins, path indices over c dt (make_record); the indices
+        // taken here are plain
+        if (MED == 0 || MED == 3 || (kOff && !t.at_ref[a])) {
+          ne0 *= c.inv_c * c.inv_dt;
+          ne1 *= c.inv_c * c.inv_dt;
+        }
+        double dx0, dy0, dz0, dx1, dy1, dz1;
+        const double u0 = arrival_bins_scaled(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a],
+                                              t.taub[a], ne0, dx0, dy0, dz0);
+        const double u1 = arrival_bins_scaled(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a],
+                                              t.taub[a], ne1, dx1, dy1, dz1);
+        zhs_box<P, FX>(row, tr.lo, tr.lo_d, tr.hi_d, u0, u1, dx0, dy0, dz0, dx1, dy1, dz1, amp,
+                       bx, by, bz);
+        continue;
+      }
       double dx0, dy0, dz0, r0, q0, dx1, dy1, dz1, r1, q1;
       const double u0 = arrival_bins(x0, y0, z0, t0, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne0, c,
                                      dx0, dy0, dz0, r0, q0);
@@ -415,10 +444,10 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 }
 
 // Reads the slots of lane l's record in wave block blk that a deposit uses.
-template <int P, int MED, bool H>
+template <int F, int P, int MED, bool H>
 __device__ __forceinline__ void load_record(const double *rec, int64_t blk, int lane, double *rv) {
-  if constexpr (paired_records<P>()) {
-    load_record_pairs<P, MED, H>(rec + blk * (kRec * 64), lane, rv);
+  if constexpr (paired_records<F, P>()) {
+    load_record_pairs<F, P, MED, H>(rec + blk * (kRec * 64), lane, rv);
   } else {
     const double *r = rec + blk * (kRec * 64) + lane;
 #pragma unroll
@@ -442,7 +471,7 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
   if (!PF) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
       double rv[kRec];
-      load_record<P, MED, H>(rec, blk, lane, rv);
+      load_record<F, P, MED, H>(rec, blk, lane, rv);
       deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
     }
     return;
@@ -450,12 +479,12 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
   double nx[kRec];
 #pragma unroll
   for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
-  if (b_first < b_end) load_record<P, MED, H>(rec, b_first, lane, nx);
+  if (b_first < b_end) load_record<F, P, MED, H>(rec, b_first, lane, nx);
   for (int64_t blk = b_first; blk < b_end; blk += waves) {
     double rv[kRec];
 #pragma unroll
     for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
-    if (blk + waves < b_end) load_record<P, MED, H>(rec, blk + waves, lane, nx);
+    if (blk + waves < b_end) load_record<F, P, MED, H>(rec, blk + waves, lane, nx);
     deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
   }
 }
@@ -489,6 +518,7 @@ __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, in
     t.ay[a] = an.y[ai];
     t.az[a] = an.z[ai];
     t.tau[a] = an.t_start[ai];
+    t.taub[a] = t.tau[a] * c.inv_dt;
     t.ea[a] = MED == 1 || MED == 2 ? path_factor_m<MED>(t.az[a], c) : 0.0;
     t.at_ref[a] = t.az[a] == z_ref;
   }

@@ -178,7 +178,7 @@ __device__ __forceinline__ double path_index(double zp, double za, double pp, do
 // squares the estimate's relative error: measured on gfx950 over 1.3e8
 // log-uniform inputs in [1e-6, 1e12], at most 2.2e-15 (fast_rcp) and 4.3e-15
 // (fast_rsq), from estimates good to 4.6e-8 and 5.3e-8. The mixed-precision
-// amplitudes and adjoints use them.
+// Endpoint amplitude and the adjoints use them.
 __device__ __forceinline__ double fast_rcp(double x) {
   double r = __builtin_amdgcn_rcp(x);
   double e = fma(-x, r, 1.0);
@@ -188,6 +188,19 @@ __device__ __forceinline__ double fast_rsq(double x) {
   double y = __builtin_amdgcn_rsq(x);
   double h = fma(-0.5 * x * y, y, 1.5);
   return y * h;
+}
+
+// sqrt(x) from the hardware reciprocal square root and one Newton step on
+// the root: relative error at most about 1.5 e^2 plus rounding, 4.5e-15 for
+// the estimate's e = 5.3e-8; inputs outside (2^-767, inf) take the library
+// sqrt, as in sqrt_rn. Not correctly rounded: for arrival times that enter a
+// continuous function of the time only (the ZHS box).
+__device__ __forceinline__ double sqrt_fast(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  g = fma(g, fma(-0.5 * y, g, 0.5), g);
+  if (__builtin_expect(!(x > 0x1p-767 && x < __builtin_inf()), 0)) g = sqrt(x);
+  return g;
 }
 
 // Correctly rounded sqrt: the hardware reciprocal square root refined by
@@ -259,6 +272,21 @@ __device__ __forceinline__ double sph_path_index(double px, double py, double pz
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an
 // antenna at (ax,ay,az) whose bin 0 starts at tau. Returns u, the arrival in
 // bins; d = X - P, R and R^2 are returned for the amplitude.
+// Arrival in bins from an end whose emission time is given in bins (tb = t /
+// dt) and whose path index over c dt (nb = n_eff / (c dt)), at an antenna
+// whose window opens at taub = t_start / dt: u = nb R + (tb - taub), R from
+// sqrt_fast. Differs from arrival_bins by rounding only (a few 1e-15 of u);
+// the deposits that use it are continuous in u.
+__device__ __forceinline__ double arrival_bins_scaled(double px, double py, double pz, double tb,
+                                                      double ax, double ay, double az, double taub,
+                                                      double nb, double &dx, double &dy,
+                                                      double &dz) {
+  dx = ax - px;
+  dy = ay - py;
+  dz = az - pz;
+  return fma(nb, sqrt_fast((dx * dx + dy * dy) + dz * dz), tb - taub);
+}
+
 __device__ __forceinline__ double arrival_bins(double px, double py, double pz, double tp,
                                                double ax, double ay, double az, double tau,
                                                double neff, const Consts &c, double &dx,
