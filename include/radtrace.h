@@ -62,9 +62,13 @@ typedef enum {
 typedef enum { RT_ENDPOINT = 0, RT_ZHS = 1 } rt_formalism;
 
 /* RT_FP64: all arithmetic and the traces in double precision.
- * RT_MIXED: arrival time, distance and bin decision in double precision
- * (the same bins as RT_FP64); amplitudes in float, accumulated in double,
- * traces in float; tracks carry beta and qw as float. */
+ * RT_MIXED: tracks carry beta and qw as float and the traces are float; the
+ * arithmetic runs in double precision. Endpoint: arrival time, distance and
+ * bin exactly as RT_FP64 (the same bins), amplitude from refined hardware
+ * reciprocals (relative error a few 1e-15), LDS accumulation in double.
+ * ZHS: arrival times to a few 1e-15 (the box is continuous in them), box
+ * amplitude and weights at single-precision accuracy (hardware estimates,
+ * 5e-8), LDS accumulation in 64-bit fixed point (see rt_accumulate). */
 typedef enum { RT_FP64 = 0, RT_MIXED = 1 } rt_precision;
 
 /* Refractive-index model of the environment the propagator is built from

@@ -263,8 +263,9 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
                                         double us, double ue, double dx0, double dy0, double dz0,
                                         double dx1, double dy1, double dz1, double cz2, double bx,
                                         double by, double bz) {
-  double ulo = us < ue ? us : ue;
-  double uhi = us < ue ? ue : us;
+  // an invalid track's ends are both NaN (NaN times), so ulo and uhi are NaN
+  // and the window test below rejects the box
+  const double ulo = fmin(us, ue), uhi = fmax(us, ue);
   if (!(uhi >= lo_d && ulo < hi_d)) return;   // outside this segment (or NaN)
   // midpoint geometry from e = (X - P0) + (X - P1) = 2 (X - M), the end
   // offsets the timing computed: with r = 1 / |e| = 1 / (2 R_m),
@@ -294,8 +295,8 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
   double s4 = -bb;
   // kl <= hi - 1 (the box starts before the segment end) and lo <= jh <= hi
   const double lo_m2 = lo_d - 2.0;
-  const int jl = (int)(kl > lo_m2 ? kl : lo_m2) - lo;
-  const int jh = (int)(kh < hi_d ? kh : hi_d) - lo;
+  const int jl = (int)fmax(kl, lo_m2) - lo;
+  const int jh = (int)fmin(kh, hi_d) - lo;
   lds<acc_t> *p1 = lds_bin(row, max(jl, 0));
   lds<acc_t> *p2 = lds_bin(row, max(jl + 1, 0));
   lds<acc_t> *p3 = lds_bin(row, jh);

@@ -272,21 +272,6 @@ __device__ __forceinline__ double sph_path_index(double px, double py, double pz
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an
 // antenna at (ax,ay,az) whose bin 0 starts at tau. Returns u, the arrival in
 // bins; d = X - P, R and R^2 are returned for the amplitude.
-// Arrival in bins from an end whose emission time is given in bins (tb = t /
-// dt) and whose path index over c dt (nb = n_eff / (c dt)), at an antenna
-// whose window opens at taub = t_start / dt: u = nb R + (tb - taub), R from
-// sqrt_fast. Differs from arrival_bins by rounding only (a few 1e-15 of u);
-// the deposits that use it are continuous in u.
-__device__ __forceinline__ double arrival_bins_scaled(double px, double py, double pz, double tb,
-                                                      double ax, double ay, double az, double taub,
-                                                      double nb, double &dx, double &dy,
-                                                      double &dz) {
-  dx = ax - px;
-  dy = ay - py;
-  dz = az - pz;
-  return fma(nb, sqrt_fast((dx * dx + dy * dy) + dz * dz), tb - taub);
-}
-
 __device__ __forceinline__ double arrival_bins(double px, double py, double pz, double tp,
                                                double ax, double ay, double az, double tau,
                                                double neff, const Consts &c, double &dx,
@@ -300,7 +285,24 @@ __device__ __forceinline__ double arrival_bins(double px, double py, double pz, 
   return (t - tau) * c.inv_dt;
 }
 
-// Arrival time (seconds) for the same path; used by the propagate entry point.
+// Arrival in bins from an end whose emission time is given in bins (tb = t /
+// dt) and whose path index over c dt (nb = n_eff / (c dt)), at an antenna
+// whose window opens at taub = t_start / dt: u = nb R + (tb - taub), R^2
+// by fused multiply-adds and R from sqrt_fast. Differs from arrival_bins by
+// rounding only (a few 1e-15 of u); the deposits that use it are continuous
+// in u.
+__device__ __forceinline__ double arrival_bins_scaled(double px, double py, double pz, double tb,
+                                                      double ax, double ay, double az, double taub,
+                                                      double nb, double &dx, double &dy,
+                                                      double &dz) {
+  dx = ax - px;
+  dy = ay - py;
+  dz = az - pz;
+  return fma(nb, sqrt_fast(fma(dx, dx, fma(dy, dy, dz * dz))), tb - taub);
+}
+
+// Arrival time (seconds) by the canonical chain of arrival_bins; used by the
+// propagate entry point.
 __device__ __forceinline__ double arrival_time(double px, double py, double pz, double tp,
                                                double ax, double ay, double az, double neff,
                                                const Consts &c) {
