@@ -171,17 +171,19 @@ __device__ __forceinline__ void index_derivatives(double zp, double za, double p
 // emission point P (all three components) and its derivative in n0 - 1, from
 // the quadrature: n = 1 + n0m1 S, S = sum_k w_k exp(-H(q_k) / h),
 // q_k = P + s_k (X - P), dH/dq = (q - C) / |q - C|, dq_k / dP = 1 - s_k.
+template <class Nodes>
 __device__ __forceinline__ void sph_index_gradient(double px, double py, double pz, double ax,
                                                    double ay, double az, const Consts &c,
-                                                   double grad[3], double &dn_dn0) {
+                                                   const Nodes &nd, double grad[3],
+                                                   double &dn_dn0) {
   double sum = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
 #pragma unroll 1
   for (int k = 0; k < kGl; ++k) {
-    const double sk = c.gl_s[k];
+    const double sk = nd.s(k);
     const double qx = px + sk * (ax - px), qy = py + sk * (ay - py), qz = pz + sk * (az - pz);
     const double rho2 = (qx * qx + qy * qy) + qz * (qz + c.re_twice);
     const double len = sqrt(rho2 + c.re2);   // |q - C|
-    const double we = c.gl_w[k] * exp(-sph_exponent(rho2, c));
+    const double we = nd.w(k) * exp(-sph_exponent(rho2, c));
     sum += we;
     const double f = we * (1.0 - sk) / len;
     g0 += f * qx;
@@ -256,10 +258,10 @@ vjp_kernel(VjpArgs v) {
     for (int64_t a = 0; ok && a < v.an.m; ++a) {
       const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
       if (MED == 3) {
-        ne0 = sph_path_index(x0, y0, z0, ax, ay, az, c);
-        ne1 = sph_path_index(x1, y1, z1, ax, ay, az, c);
-        sph_index_gradient(x0, y0, z0, ax, ay, az, c, gn0, dnn0);
-        sph_index_gradient(x1, y1, z1, ax, ay, az, c, gn1, dnn1);
+        ne0 = sph_path_index(x0, y0, z0, ax, ay, az, c, ConstNodes{v.c});
+        ne1 = sph_path_index(x1, y1, z1, ax, ay, az, c, ConstNodes{v.c});
+        sph_index_gradient(x0, y0, z0, ax, ay, az, c, ConstNodes{v.c}, gn0, dnn0);
+        sph_index_gradient(x1, y1, z1, ax, ay, az, c, ConstNodes{v.c}, gn1, dnn1);
       } else if (!(az == z_prev)) {
         const double ea = path_factor_flat<MED>(az, c);
         index_derivatives<MED>(z0, az, e0, ea, c, ne0, gn0[2], dnn0);
@@ -381,7 +383,8 @@ __global__ void __launch_bounds__(kVjpBlock) ep_vjp_kernel(VjpArgs v) {
       const double ax = v.an.x[a], ay = v.an.y[a], az = v.an.z[a], tau = v.an.t_start[a];
       if (MED == 3) {
         for (int e = 0; e < 2; ++e)
-          nes[e] = sph_path_index(pos[e][0], pos[e][1], pos[e][2], ax, ay, az, c);
+          nes[e] = sph_path_index(pos[e][0], pos[e][1], pos[e][2], ax, ay, az, c,
+                                  ConstNodes{v.c});
       } else if ((MED == 1 || MED == 2) && !(az == z_prev)) {   // uniform test
         const double pa = path_factor_flat<MED>(az, c);
         for (int e = 0; e < 2; ++e) nes[e] = path_index_m<MED>(pos[e][2], az, pf[e], pa, c);

@@ -262,10 +262,10 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   constexpr bool kPf = F == 0 && MED != 3;
   if (kFxCap && fx_unit > 0.0)
     deposit_blocks<F, P, MED, AT, kPf, true>(g.rec, b_first, b_end, waves, mask, t, tr, c,
-                                             ConstNodes{c});
+                                             ConstNodes{g.c});
   else
     deposit_blocks<F, P, MED, AT, kPf, false>(g.rec, b_first, b_end, waves, mask, t, tr, c,
-                                              ConstNodes{c});
+                                              ConstNodes{g.c});
   __syncthreads();
 
   if (kFxCap && fx_unit > 0.0)
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(256) propagate_kernel(TrackPtrs tr, AntPtrs an
       double tp = e ? tr.t1[i] : tr.t0[i];
       double neff = c.n_uniform;
       if (c.medium == 3)
-        neff = sph_path_index(px, py, pz, ax, ay, az, c);
+        neff = sph_path_index(px, py, pz, ax, ay, az, c, ConstNodes{c0});
       else if (c.medium != 0)
         neff = path_index(pz, az, path_factor(pz, c), path_factor(az, c), c);
       double t = arrival_time(px, py, pz, tp, ax, ay, az, neff, c);

@@ -236,6 +236,9 @@ __device__ __forceinline__ double sph_factor(double x, double y, double z, const
 
 // The quadrature nodes and weights of the spherical path mean as the
 // constants hold them (a single plan's kernel arguments).
+// Nodes read from a Consts in constant memory: a kernel argument, never a
+// kernel's local copy (indexing a local copy by the loop counter puts the whole
+// copy in per-lane scratch memory).
 struct ConstNodes {
   const Consts &c;
   __device__ __forceinline__ double s(int k) const { return c.gl_s[k]; }
@@ -264,10 +267,6 @@ __device__ __forceinline__ double sph_path_index(double px, double py, double pz
   return 1.0 + c.n0m1 * s;
 }
 
-__device__ __forceinline__ double sph_path_index(double px, double py, double pz, double ax,
-                                                 double ay, double az, const Consts &c) {
-  return sph_path_index(px, py, pz, ax, ay, az, c, ConstNodes{c});
-}
 
 // Straight-line propagation of an emission at (px,py,pz), time tp, to an
 // antenna at (ax,ay,az) whose bin 0 starts at tau. Returns u, the arrival in
