@@ -67,8 +67,9 @@ enum : int {
 // source index 1 + (n0 - 1) e sits next to the Cherenkov pole, where a
 // rounded index would dominate the error). A wave reads 12 of the 16 slots
 // (10 without the path indices: uniform medium, spherical Earth), plus the
-// height factors where the Endpoint needs the source index or a tile antenna
-// sits off the reference height. Mixed ZHS records hold the times in bins
+// height factors where the Endpoint needs the source index in the tabulated
+// medium or over the spherical Earth, or a tile antenna sits off the
+// reference height. Mixed ZHS records hold the times in bins
 // (t / dt) and the path indices over c dt, the operands of
 // arrival_bins_scaled.
 enum : int { M_AB = 10, M_YZ = 11, M_E0 = 12, M_E1 = 13 };
@@ -224,6 +225,19 @@ __device__ __forceinline__ unsigned long long fx_biased(double v, double s) {
   return (unsigned long long)__double_as_longlong(fma(v, s, kFxMagic));
 }
 
+// Local index at an emission point P from the exponential medium's path
+// index n_eff to an antenna X (dz = z_P - z_X, ns_x = 1 + n0m1 e_X, inv_h =
+// 1 / h): inverting n_eff = 1 + n0m1 h (e_X - e_P) / dz gives
+// 1 + n0m1 e_P = ns_x - (n_eff - 1) dz / h; below the 1-mm branch, where
+// n_eff - 1 = n0m1 e((z_P + z_X) / 2), it is n_eff - (n_eff - 1) dz / (2 h) up
+// to a term below 1e-18. The result differs from 1 + n0m1 e_P by a few units
+// in the last place.
+__device__ __forceinline__ double source_from_path(double neff, double dz, double ns_x,
+                                                   double inv_h) {
+  const bool mid = fabs(dz) < 1e-3;
+  return fma(-(neff - 1.0), dz * (mid ? 0.5 * inv_h : inv_h), mid ? neff : ns_x);
+}
+
 // Endpoint impulse of one track end at one antenna: s k qw [r x (r x beta)] /
 // ((1 - n_src beta.r) R dt), evaluated as sc (d (beta.d) / R^2 - beta) / num
 // with num = R - n_src (beta.d) = (1 - n_src beta.r) R and sc = s k qw / dt.
@@ -341,6 +355,8 @@ template <int AT>
 struct Tile {
   double ax[AT], ay[AT], az[AT], tau[AT], ea[AT];
   double taub[AT];   // window opening in bins, tau / dt
+  double nsa[AT];    // exponential medium: local index at the antenna, 1 + n0m1 ea
+  double inv_h;      // exponential medium: 1 / scale height
   bool at_ref[AT];   // at the height of antenna 0: the record's path index applies
 };
 
@@ -393,8 +409,11 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
   // ZHS: the box takes twice its amplitude constant (times the inverse unit
   // for fixed-point tiles; all exact powers of two)
   if (F == 1) amp *= FX ? 2.0 * tr.fx_inv : 2.0;
-  const double ns0 = MED != 0 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
-  const double ns1 = MED != 0 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
+  // mixed Endpoint, exponential medium, tile at the reference height: the
+  // source index comes from the record's path index (no height-factor slots)
+  constexpr bool kNsFromPath = F == 0 && P == 1 && MED == 1 && !H;
+  double ns0 = MED != 0 ? fma(c.n0m1, e0, 1.0) : c.n_uniform;
+  double ns1 = MED != 0 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
     if ((mask >> a) & 1) {
@@ -410,6 +429,10 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
         ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
       }
       lds<acc_t> *row = tr.row(a);
+      if constexpr (kNsFromPath) {
+        ns0 = source_from_path(ne0, z0 - t.az[a], t.nsa[a], t.inv_h);
+        ns1 = source_from_path(ne1, z1 - t.az[a], t.nsa[a], t.inv_h);
+      }
       if constexpr (F == 1 && P == 1) {
         // times in bins, path indices over c dt (make_record); the indices
         // taken here are plain
@@ -491,8 +514,11 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
 }
 
 // As deposit_blocks_n, reading the height factors only where they are used:
-// the Endpoint source index in non-uniform media, and tiles with an antenna off
-// the reference height (whose path index is taken per pair from them).
+// the Endpoint source index (except for mixed records in the exponential
+// medium, where it follows from the path index; the FP64 deposit, which
+// spends more of its time in arithmetic, keeps the two slots: 6% faster), and
+// tiles with an antenna off the reference height (whose path index is taken
+// per pair from them).
 template <int F, int P, int MED, int AT, bool PF, bool FX, class Nodes>
 __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
                                                int64_t waves, uint64_t mask, const Tile<AT> &t,
@@ -501,7 +527,7 @@ __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_firs
   bool off = false;
 #pragma unroll
   for (int a = 0; a < AT; ++a) off = off || (((mask >> a) & 1) && !t.at_ref[a]);
-  if (MED == 3 ? F == 0 : MED != 0 && (F == 0 || off))
+  if (MED == 3 ? F == 0 : MED != 0 && ((F == 0 && (MED != 1 || P == 0)) || off))
     deposit_blocks_n<F, P, MED, AT, true, PF, FX>(rec, b_first, b_end, waves, mask, t, tr, c, nd);
   else
     deposit_blocks_n<F, P, MED, AT, false, PF, FX>(rec, b_first, b_end, waves, mask, t, tr, c, nd);
@@ -512,6 +538,7 @@ template <int AT, int MED>
 __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, int n_ant,
                                           const Consts &c, Tile<AT> &t) {
   const double z_ref = an.z[0];
+  t.inv_h = MED == 1 ? 1.0 / c.h : 0.0;
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
     int64_t ai = a_begin + (a < n_ant ? a : 0);
@@ -521,6 +548,7 @@ __device__ __forceinline__ void load_tile(const AntPtrs &an, int64_t a_begin, in
     t.tau[a] = an.t_start[ai];
     t.taub[a] = t.tau[a] * c.inv_dt;
     t.ea[a] = MED == 1 || MED == 2 ? path_factor_m<MED>(t.az[a], c) : 0.0;
+    t.nsa[a] = fma(c.n0m1, t.ea[a], 1.0);
     t.at_ref[a] = t.az[a] == z_ref;
   }
 }
