@@ -145,14 +145,13 @@ __global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
     const double z_ref = s.an.z[0];
     const double e_ref = c.medium == 1 || c.medium == 2 ? path_factor(z_ref, c) : 0.0;
     double v[kRec];
-    double *out = b.rec + (blk * kRec) * 64;
-    if (s.formalism == RT_ENDPOINT) {
+    if (s.formalism == RT_ENDPOINT)
       make_record<0, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
-      store_record<0, P>(out, (int)(g & 63), v);
-    } else {
+    else
       make_record<1, P>(s.tr, i, i < s.tr.n, c, z_ref, e_ref, v);
-      store_record<1, P>(out, (int)(g & 63), v);
-    }
+    const bool single = s.formalism == RT_ENDPOINT ? single_slot_records<0, P>(c.medium)
+                                                   : single_slot_records<1, P>(c.medium);
+    store_record(b.rec + (blk * kRec) * 64, (int)(g & 63), v, single);
   }
 }
 

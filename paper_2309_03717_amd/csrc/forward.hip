@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(kPrepThreads) prepare_kernel(PrepArgs g) {
        i += (int64_t)gridDim.x * blockDim.x) {
     double v[kRec];
     make_record<F, P>(g.tr, i, i < g.tr.n, c, z_ref, e_ref, v);
-    store_record<F, P>(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v);
+    store_record(g.rec + ((i >> 6) * kRec) * 64, (int)(i & 63), v,
+                 single_slot_records<F, P>(c.medium));
     if (kFx && g.fx_part) {
       const double b = zhs_track_bound(v, g.bbox);
       bsum += b;

@@ -43,16 +43,19 @@ struct Prec<1> {  // RT_MIXED
 
 // ------------------------------------------------------------------ track record
 
-// Per-track record, kRec doubles per track, blocked by waves of 64 tracks.
-// Paired records are stored in field pairs (2g, 2g + 1): field f of track
-// 64 b + l is rec[(b * kRec + (f & ~1)) * 64 + 2 l + (f & 1)], so one 16-byte
-// load per lane brings a pair and a wave reads it as one contiguous 1-KB run.
-// Mixed Endpoint records keep one field per run: rec[(b * kRec + f) * 64 + l],
-// one 8-byte load per lane and field (measured faster for that deposit, the
-// paired layout faster for the FP64 ones and the mixed ZHS one).
+// Per-track record, kRec doubles per track, blocked by waves of 64 tracks and
+// stored in field pairs (2g, 2g + 1): field f of track 64 b + l is
+// rec[(b * kRec + (f & ~1)) * 64 + 2 l + (f & 1)], so one 16-byte load per
+// lane brings a pair and a wave reads it as one contiguous 1-KB run. Mixed
+// Endpoint records of the tabulated medium, whose deposit reads 14 slots,
+// keep one field per run instead: rec[(b * kRec + f) * 64 + l], one 8-byte
+// load per lane and field (measured: pairs 9% slower there, 6% faster for
+// the 12 slots of the exponential medium).
 constexpr int kRec = 16;
 template <int F, int P>
-constexpr bool paired_records() { return P == 0 || F == 1; }
+__host__ __device__ constexpr bool single_slot_records(int medium) {
+  return F == 0 && P == 1 && medium == 2;
+}
 enum : int {
   R_X0, R_Y0, R_Z0, R_T0,  // start point and time
   R_X1, R_Y1, R_Z1, R_T1,  // end point and time
@@ -106,27 +109,24 @@ constexpr bool pairs_agree() {
   return true;
 }
 
-// Writes the record v of lane l into its wave block.
-template <int F, int P>
-__device__ __forceinline__ void store_record(double *blk, int l, const double *v) {
-  if constexpr (paired_records<F, P>()) {
+// Writes the record v of lane l into its wave block (single: one field per
+// run, see single_slot_records).
+__device__ __forceinline__ void store_record(double *blk, int l, const double *v, bool single) {
+  if (single) {
+#pragma unroll
+    for (int f = 0; f < kRec; ++f) blk[f * 64 + l] = v[f];
+  } else {
 #pragma unroll
     for (int g = 0; g < kRec; g += 2)
       *reinterpret_cast<double2 *>(blk + g * 64 + 2 * l) = make_double2(v[g], v[g + 1]);
-  } else {
-    double *out = blk + l;
-#pragma unroll
-    for (int f = 0; f < kRec; ++f) out[f * 64] = v[f];
   }
 }
 
-// Reads the slots of lane l's paired record that a deposit uses
-// (slot_loaded), one pair per load; the other slots read as 0. (Mixed records
-// are read field by field where they are used.)
-template <int F, int P, int MED, bool H>
+// Reads the slots of lane l's record that a deposit uses (slot_loaded), one
+// pair per load; the other slots read as 0.
+template <int P, int MED, bool H>
 __device__ __forceinline__ void load_record_pairs(const double *blk, int l, double *v) {
-  static_assert(paired_records<F, P>() && pairs_agree<P, MED, H>(),
-                "paired records, loaded a whole pair at a time");
+  static_assert(pairs_agree<P, MED, H>(), "records are loaded a whole pair at a time");
 #pragma unroll
   for (int g = 0; g < kRec; g += 2) {
     if (slot_loaded<P, MED, H>(g)) {
@@ -470,12 +470,12 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
 // Reads the slots of lane l's record in wave block blk that a deposit uses.
 template <int F, int P, int MED, bool H>
 __device__ __forceinline__ void load_record(const double *rec, int64_t blk, int lane, double *rv) {
-  if constexpr (paired_records<F, P>()) {
-    load_record_pairs<F, P, MED, H>(rec + blk * (kRec * 64), lane, rv);
-  } else {
+  if constexpr (single_slot_records<F, P>(MED)) {
     const double *r = rec + blk * (kRec * 64) + lane;
 #pragma unroll
     for (int f = 0; f < kRec; ++f) rv[f] = slot_loaded<P, MED, H>(f) ? r[f * 64] : 0.0;
+  } else {
+    load_record_pairs<P, MED, H>(rec + blk * (kRec * 64), lane, rv);
   }
 }
 
