@@ -70,13 +70,13 @@ VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 # only while the kernel sources and the launch shape are the measured ones;
 # otherwise null.
 COUNTER_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
-COUNTERS_HASH = "89ca0808b956718f"
+COUNTERS_HASH = "bcd99bc6dfcd631c"
 COUNTERS_PROFILE = {"traffic": "profiles/deposit_grid4096_mixed_hbm_bytes.md",
                     "valu": "profiles/deposit_grid4096_mixed_counters.md"}
-TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.5, "write": 1048576.0 / 1048576.0}
-TRAFFIC_KIB = {"endpoint": {"fetch": 9030073.3, "write": 393216.0},
-               "zhs": {"fetch": 8771653.6, "write": 3145728.0}}
-SQ_INSTS_VALU = {"endpoint": 1.0081e10, "zhs": 8.839e9}
+TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.4, "write": 1048576.0 / 1048576.0}
+TRAFFIC_KIB = {"endpoint": {"fetch": 14999151.8, "write": 393216.0},
+               "zhs": {"fetch": 8450915.9, "write": 3145728.0}}
+SQ_INSTS_VALU = {"endpoint": 8.607e9, "zhs": 8.839e9}
 COUNTERS_PASS = 1 << 20
 
 

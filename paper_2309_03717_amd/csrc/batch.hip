@@ -174,8 +174,9 @@ __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int
   load_tile<AT, MED>(an, a_begin, n_ant, c, t);
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
-  deposit_blocks<F, P, MED, AT, MED != 3, false>(rec, b_first, b_end, waves, mask, t, tr, c,
-                                                 LdsNodes{nodes});
+  constexpr int kPf = MED != 3 ? kPfNext : kPfNone;
+  deposit_blocks<F, P, MED, AT, kPf, false>(rec, b_first, b_end, waves, mask, t, tr, c,
+                                            LdsNodes{nodes});
 }
 
 // Tile width switch; ATMAX = 1 compiles the one-antenna path only.

@@ -481,18 +481,23 @@ __device__ __forceinline__ void load_record(const double *rec, int64_t blk, int 
 
 // Deposits of the wave blocks [b_first, b_end) (stride `waves`, one block per
 // wave per step) of a record array into the LDS tile. Only the slots the
-// formalism and precision use are read. PF: load the next record before
-// processing the current one. That pays where record delivery bounds the loop
-// (the Endpoint deposit) or few waves share a SIMD (the 512-thread batch
-// kernel); the single-plan ZHS deposit, with more arithmetic per record and
-// four waves per SIMD, runs faster without the register copies it costs.
-template <int F, int P, int MED, int AT, bool H, bool PF, bool FX, class Nodes>
+// formalism and precision use are read. PF: kPfNext loads the next record
+// before processing the current one (one buffer, copied); kPfAlternate does
+// so, for mixed records without height factors, into the other of two record
+// buffers (the loop takes two blocks per turn: no copies, more registers).
+// That pays where record latency shows (the Endpoint deposit) or few waves
+// share a SIMD (the 512-thread batch kernel); the single-plan ZHS deposit,
+// with more arithmetic per record and four waves per SIMD, runs faster
+// without it.
+enum : int { kPfNone = 0, kPfNext = 1, kPfAlternate = 2 };
+
+template <int F, int P, int MED, int AT, bool H, int PF, bool FX, class Nodes>
 __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_first,
                                                  int64_t b_end, int64_t waves, uint64_t mask,
                                                  const Tile<AT> &t, const TileRef &tr,
                                                  const Consts &c, const Nodes &nd) {
   const int lane = threadIdx.x & 63;
-  if (!PF) {
+  if (PF == kPfNone) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
       double rv[kRec];
       load_record<F, P, MED, H>(rec, blk, lane, rv);
@@ -500,16 +505,33 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
     }
     return;
   }
-  double nx[kRec];
+  if constexpr (PF == kPfAlternate && P == 1 && !H) {
+    double ra[kRec], rb[kRec];
 #pragma unroll
-  for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
-  if (b_first < b_end) load_record<F, P, MED, H>(rec, b_first, lane, nx);
-  for (int64_t blk = b_first; blk < b_end; blk += waves) {
-    double rv[kRec];
+    for (int f = 0; f < kRec; ++f) ra[f] = rb[f] = 0.0;
+    if (b_first < b_end) load_record<F, P, MED, H>(rec, b_first, lane, ra);
+    for (int64_t blk = b_first; blk < b_end; blk += 2 * waves) {
+      if (blk + waves < b_end) load_record<F, P, MED, H>(rec, blk + waves, lane, rb);
+      deposit_record<F, P, MED, AT, H, FX>(ra, mask, t, tr, c, nd);
+      if (blk + waves >= b_end) break;
+      if (blk + 2 * waves < b_end) load_record<F, P, MED, H>(rec, blk + 2 * waves, lane, ra);
+      deposit_record<F, P, MED, AT, H, FX>(rb, mask, t, tr, c, nd);
+    }
+  } else {
+    // the deposits that read the height factors, the FP64 ones and the batch
+    // kernels need the registers the second buffer would take (they spill
+    // with it): one buffer, copied
+    double nx[kRec];
 #pragma unroll
-    for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
-    if (blk + waves < b_end) load_record<F, P, MED, H>(rec, blk + waves, lane, nx);
-    deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
+    for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
+    if (b_first < b_end) load_record<F, P, MED, H>(rec, b_first, lane, nx);
+    for (int64_t blk = b_first; blk < b_end; blk += waves) {
+      double rv[kRec];
+#pragma unroll
+      for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
+      if (blk + waves < b_end) load_record<F, P, MED, H>(rec, blk + waves, lane, nx);
+      deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
+    }
   }
 }
 
@@ -519,7 +541,7 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
 // spends more of its time in arithmetic, keeps the two slots: 6% faster), and
 // tiles with an antenna off the reference height (whose path index is taken
 // per pair from them).
-template <int F, int P, int MED, int AT, bool PF, bool FX, class Nodes>
+template <int F, int P, int MED, int AT, int PF, bool FX, class Nodes>
 __device__ __forceinline__ void deposit_blocks(const double *rec, int64_t b_first, int64_t b_end,
                                                int64_t waves, uint64_t mask, const Tile<AT> &t,
                                                const TileRef &tr, const Consts &c,
