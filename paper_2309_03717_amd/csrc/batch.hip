@@ -8,9 +8,11 @@
 // as the single-plan kernel does and writes the tile to its own partial slot,
 // so the result does not depend on which workgroup took which item. A merge
 // kernel then adds, per (shower, antenna, segment), the slots of the splits in
-// index order into the shower's traces (with the ZHS prefix scan). On a
-// non-null stream the whole sequence is captured once into a HIP graph and
-// replayed by later launches.
+// index order into the shower's traces (with the ZHS prefix scan). Mixed
+// ZHS showers accumulate in 64-bit fixed point, with a unit per shower from
+// its tracks' deposit bounds (as a single plan's call does), so their traces
+// do not depend on the launch shape. On a non-null stream the whole sequence
+// is captured once into a HIP graph and replayed by later launches.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -36,7 +38,18 @@ struct ShowerDesc {
   int64_t slot_len;          // doubles per slot: at * seg_len * 3
   int64_t tab_off;           // tabulated medium: first double of its F table in the
                              // workspace's table region (-1 otherwise)
+  int32_t fx_chunk0, fx_chunks;   // mixed ZHS: its chunks of the fixed-point bound
+                                  // reduction (none otherwise)
 };
+
+// A range of one mixed ZHS shower's record blocks whose deposit bounds one
+// workgroup reduces (the fixed-point unit's sum and maximum).
+struct FxChunk {
+  int32_t shower, pad;
+  int64_t block0, n_blocks;   // first wave block (within the shower) and count
+};
+constexpr int64_t kFxChunkBlocks = 1024;   // 65536 tracks per chunk
+constexpr int kFxThreads = 256;
 
 struct WorkItem {
   int32_t shower, atile, seg, split;
@@ -57,12 +70,16 @@ struct BatchArgs {
   const WorkItem *items;       // grouped: [group_begin[g], group_begin[g + 1])
   const MergeTask *merges;
   const int64_t *cum_blocks;   // [n_showers + 1] first wave block of each shower
-  int32_t n_showers, n_items;
+  const FxChunk *fx_chunks;    // [n_fx_chunks]
+  int32_t n_showers, n_items, n_fx_chunks;
   int32_t group_begin[kGroups + 1];
   int *counter;                // [kGroups]: next item of each group
   double *rec;
   double *partial;
   double *tables;              // F tables of the tabulated showers
+  double *fx;                  // [n_showers][2]: fixed-point unit and its inverse
+                               // (0: the shower keeps the double tile)
+  double *fx_part;             // [n_fx_chunks][2]: bound sum and maximum
   int64_t total_blocks;
 };
 
@@ -155,6 +172,65 @@ __global__ void __launch_bounds__(256) batch_prepare_kernel(BatchArgs b) {
   }
 }
 
+// Deposit bounds of one chunk of a mixed ZHS shower's records (its antennas'
+// bounding box first): their sum and maximum, reduced over the workgroup in
+// a fixed order.
+__global__ void __launch_bounds__(kFxThreads) batch_fx_part_kernel(BatchArgs b) {
+  __shared__ double red[6 * kFxThreads];
+  const FxChunk ch = b.fx_chunks[blockIdx.x];
+  const ShowerDesc &s = b.sh[ch.shower];
+  double bb[6];
+  antenna_bbox<kFxThreads>(s.an, red, bb);
+  const double *rec = b.rec + (s.rec_block0 + ch.block0) * (kRec * 64);
+  double sum = 0.0, mx = 0.0;
+  for (int64_t i = threadIdx.x; i < ch.n_blocks * 64; i += kFxThreads) {
+    double v[kRec];
+    const double *blk = rec + (i >> 6) * (kRec * 64);
+    const int l = (int)(i & 63);
+    // the slots the bound reads: points, times, amplitude and velocity
+#pragma unroll
+    for (int f = 0; f < kRec; ++f)
+      v[f] = (f <= R_T1 || f == M_AB || f == M_YZ) ? blk[(f & ~1) * 64 + 2 * l + (f & 1)] : 0.0;
+    const double bnd = zhs_track_bound(v, bb);
+    sum += bnd;
+    mx = fmax(mx, bnd);
+  }
+  red[threadIdx.x] = sum;
+  red[kFxThreads + threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = kFxThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[threadIdx.x] += red[threadIdx.x + h];
+      red[kFxThreads + threadIdx.x] = fmax(red[kFxThreads + threadIdx.x],
+                                           red[kFxThreads + threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    b.fx_part[2 * blockIdx.x] = red[0];
+    b.fx_part[2 * blockIdx.x + 1] = red[kFxThreads];
+  }
+}
+
+// The fixed-point unit of every shower (chunk partials added in chunk
+// order); 0 for the showers that keep the double tile. One thread per shower.
+__global__ void batch_fx_unit_kernel(BatchArgs b) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= b.n_showers) return;
+  const ShowerDesc &d = b.sh[s];
+  double unit = 0.0;
+  if (d.fx_chunks > 0) {
+    double S = 0.0, B = 0.0;
+    for (int c = 0; c < d.fx_chunks; ++c) {
+      S += b.fx_part[2 * (d.fx_chunk0 + c)];
+      B = fmax(B, b.fx_part[2 * (d.fx_chunk0 + c) + 1]);
+    }
+    unit = fx_unit(S, B, d.tr.n);
+  }
+  b.fx[2 * s] = unit;
+  b.fx[2 * s + 1] = unit > 0.0 ? 1.0 / unit : 0.0;
+}
+
 // The quadrature nodes and weights of a spherical shower, copied to LDS for
 // the item (kGl nodes, then kGl weights): every lane reads the same node, so
 // the reads are broadcasts, and the constants copied per item need no
@@ -165,18 +241,24 @@ struct LdsNodes {
   __device__ __forceinline__ double w(int k) const { return p[kGl + k]; }
 };
 
-// The deposits of one work item into the LDS tile.
+// The deposits of one work item into the LDS tile (FX: the fixed-point ZHS
+// tile, for mixed ZHS showers whose unit is not 0).
 template <int F, int P, int MED, int AT>
 __device__ __forceinline__ void run_item(const double *rec, int64_t b_first, int64_t b_end,
                                          const AntPtrs &an, const Consts &c, const TileRef &tr,
-                                         int64_t a_begin, int n_ant, const double *nodes) {
+                                         int64_t a_begin, int n_ant, const double *nodes,
+                                         bool fx) {
   Tile<AT> t;
   load_tile<AT, MED>(an, a_begin, n_ant, c, t);
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
   constexpr int kPf = MED != 3 ? kPfNext : kPfNone;
-  deposit_blocks<F, P, MED, AT, kPf, false>(rec, b_first, b_end, waves, mask, t, tr, c,
-                                            LdsNodes{nodes});
+  if (F == 1 && P == 1 && fx)
+    deposit_blocks<F, P, MED, AT, kPf, true>(rec, b_first, b_end, waves, mask, t, tr, c,
+                                             LdsNodes{nodes});
+  else
+    deposit_blocks<F, P, MED, AT, kPf, false>(rec, b_first, b_end, waves, mask, t, tr, c,
+                                              LdsNodes{nodes});
 }
 
 // Tile width switch; ATMAX = 1 compiles the one-antenna path only.
@@ -184,13 +266,13 @@ template <int ATMAX, int F, int P, int MED>
 __device__ __forceinline__ void run_item_at(int at, const double *rec, int64_t b_first,
                                             int64_t b_end, const AntPtrs &an, const Consts &c,
                                             const TileRef &tr, int64_t a_begin, int n_ant,
-                                            const double *nodes) {
+                                            const double *nodes, bool fx) {
   if (ATMAX == 1 || at == 1)
-    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+    run_item<F, P, MED, 1>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes, fx);
   else if (at == 2)
-    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+    run_item<F, P, MED, 2>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes, fx);
   else
-    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+    run_item<F, P, MED, 3>(rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes, fx);
 }
 
 // Persistent workgroups: take the items of one group until its counter
@@ -228,7 +310,10 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     const int f = FF >= 0 ? FF : uniform(sd.formalism);
     const int stride = (seg_len + tile_pad(f)) * 3;
     for (int i = threadIdx.x; i < at * stride; i += blockDim.x) tile[i] = 0.0;
-    const TileRef tr{tile, stride, lo, (double)lo, (double)hi, 0.0};
+    // mixed ZHS showers with a fixed-point unit: int64 tile (zero bits are 0)
+    const double fx_inv = P == 1 && f == 1 ? uniform(b.fx[2 * w.shower + 1]) : 0.0;
+    const bool fx = fx_inv > 0.0;
+    const TileRef tr{tile, stride, lo, (double)lo, (double)hi, fx_inv};
     if (HEAVY && c.medium == 3 && threadIdx.x < 2 * kGl)
       nodes[threadIdx.x] =
           threadIdx.x < kGl ? sd.c.gl_s[threadIdx.x] : sd.c.gl_w[threadIdx.x - kGl];
@@ -241,14 +326,18 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     const bool m1 = c.medium == M1;
     if (FF != 1 && f == 0) {
       if (m1)
-        run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+        run_item_at<ATMAX, 0, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes,
+                                     false);
       else
-        run_item_at<ATMAX, 0, P, M0>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+        run_item_at<ATMAX, 0, P, M0>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes,
+                                     false);
     } else if (FF != 0) {
       if (m1)
-        run_item_at<ATMAX, 1, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+        run_item_at<ATMAX, 1, P, M1>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes,
+                                     fx);
       else
-        run_item_at<ATMAX, 1, P, M0>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes);
+        run_item_at<ATMAX, 1, P, M0>(at, rec, b_first, b_end, an, c, tr, a_begin, n_ant, nodes,
+                                     fx);
     }
     __syncthreads();
     const int64_t slot_len = uniform(sd.slot_len);
@@ -301,8 +390,12 @@ __global__ void __launch_bounds__(kMergeThreads) batch_merge_kernel(BatchArgs b)
                       ((int64_t)atile * s.n_segs + mt.seg) * s.splits * s.slot_len +
                       (int64_t)ai * s.seg_len * 3;
   T *out = reinterpret_cast<T *>(s.traces) + ((size_t)mt.antenna * s.c.n_bins + lo) * 3;
+  const double unit = P == 1 && s.formalism == RT_ZHS ? b.fx[2 * mt.shower] : 0.0;
   if (s.formalism == RT_ENDPOINT)
     merge_segment<0, T>(part, s.slot_len, s.splits, out, nb, 1.0);
+  else if (unit > 0.0)
+    merge_segment<1, T>(reinterpret_cast<const long long *>(part), s.slot_len, s.splits, out, nb,
+                        unit);
   else
     merge_segment<1, T>(part, s.slot_len, s.splits, out, nb, 1.0);
 }
@@ -322,6 +415,7 @@ struct rt_batch {
   std::vector<rt::WorkItem> items;
   std::vector<rt::MergeTask> merges;
   std::vector<int64_t> cum;
+  std::vector<rt::FxChunk> fx_chunks;   // mixed ZHS showers' bound-reduction chunks
   int32_t group_begin[rt::kGroups + 1] = {0, 0, 0, 0};   // items, grouped
   int64_t total_blocks = 0, total_partial = 0, total_pairs = 0;
   int64_t total_tab = 0;       // doubles of the tabulated showers' F tables
@@ -331,7 +425,7 @@ struct rt_batch {
   // launches (offsets: tab_off[]), and tables_ws the workspace that last
   // received it
   std::vector<unsigned char> host_tables;
-  size_t tab_off[5] = {0, 0, 0, 0, 0};
+  size_t tab_off[6] = {0, 0, 0, 0, 0, 0};
   size_t tables_bytes = 0;
   void *tables_ws = nullptr;
   hipStream_t cap_stream = nullptr;   // created when a graph is first built
@@ -353,30 +447,40 @@ static size_t partial_bytes(const rt_batch &b) {
   return align256((size_t)b.total_partial * sizeof(acc_t));
 }
 
-// the batch's tables, records, partial slots, then the F tables of the
-// tabulated showers
+static size_t tab_bytes(const rt_batch &b) {
+  return align256((size_t)b.total_tab * sizeof(double));
+}
+
+// per shower {unit, 1 / unit}, then per bound-reduction chunk {sum, max}
+static size_t fx_bytes(const rt_batch &b) {
+  return align256(b.sh.size() * 2 * sizeof(double)) +
+         align256(b.fx_chunks.size() * 2 * sizeof(double));
+}
+
+// the batch's tables, records, partial slots, the F tables of the tabulated
+// showers, then the fixed-point region
 size_t batch_workspace_bytes(const rt_batch &b) {
-  return b.tables_bytes + record_bytes(b) + partial_bytes(b) +
-         align256((size_t)b.total_tab * sizeof(double));
+  return b.tables_bytes + record_bytes(b) + partial_bytes(b) + tab_bytes(b) + fx_bytes(b);
 }
 
 // The host image of the device tables, each part 256-byte aligned: shower
-// descriptors, work items, merge tasks, cumulative record blocks, and the
-// kGroups item counters (reset by every launch).
+// descriptors, work items, merge tasks, cumulative record blocks, the kGroups
+// item counters (reset by every launch) and the fixed-point chunks.
 static void build_table_image(rt_batch &b) {
-  const size_t sizes[5] = {b.sh.size() * sizeof(ShowerDesc), b.items.size() * sizeof(WorkItem),
+  const size_t sizes[6] = {b.sh.size() * sizeof(ShowerDesc), b.items.size() * sizeof(WorkItem),
                            b.merges.size() * sizeof(MergeTask), b.cum.size() * sizeof(int64_t),
-                           kGroups * sizeof(int)};
-  const void *src[5] = {b.sh.data(), b.items.data(), b.merges.data(), b.cum.data(), nullptr};
+                           kGroups * sizeof(int), b.fx_chunks.size() * sizeof(FxChunk)};
+  const void *src[6] = {b.sh.data(), b.items.data(), b.merges.data(), b.cum.data(), nullptr,
+                        b.fx_chunks.data()};
   size_t off = 0;
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     b.tab_off[i] = off;
     off += align256(sizes[i]);
   }
   b.tables_bytes = off;
   b.host_tables.assign(off, 0);
-  for (int i = 0; i < 4; ++i)
-    if (sizes[i]) std::memcpy(b.host_tables.data() + b.tab_off[i], src[i], sizes[i]);
+  for (int i = 0; i < 6; ++i)
+    if (sizes[i] && src[i]) std::memcpy(b.host_tables.data() + b.tab_off[i], src[i], sizes[i]);
 }
 
 static BatchArgs batch_args(const rt_batch &b, void *workspace) {
@@ -387,13 +491,17 @@ static BatchArgs batch_args(const rt_batch &b, void *workspace) {
   a.merges = reinterpret_cast<const MergeTask *>(ws + b.tab_off[2]);
   a.cum_blocks = reinterpret_cast<const int64_t *>(ws + b.tab_off[3]);
   a.counter = reinterpret_cast<int *>(ws + b.tab_off[4]);
+  a.fx_chunks = reinterpret_cast<const FxChunk *>(ws + b.tab_off[5]);
   a.n_showers = (int32_t)b.sh.size();
   a.n_items = (int32_t)b.items.size();
+  a.n_fx_chunks = (int32_t)b.fx_chunks.size();
   for (int g = 0; g <= kGroups; ++g) a.group_begin[g] = b.group_begin[g];
   char *data = ws + b.tables_bytes;
   a.rec = reinterpret_cast<double *>(data);
   a.partial = reinterpret_cast<double *>(data + record_bytes(b));
   a.tables = reinterpret_cast<double *>(data + record_bytes(b) + partial_bytes(b));
+  a.fx = reinterpret_cast<double *>(data + record_bytes(b) + partial_bytes(b) + tab_bytes(b));
+  a.fx_part = a.fx + align256(b.sh.size() * 2 * sizeof(double)) / sizeof(double);
   a.total_blocks = b.total_blocks;
   return a;
 }
@@ -430,10 +538,15 @@ static hipError_t batch_enqueue(const rt_batch &b, void *workspace, hipStream_t 
   batch_reset_kernel<<<1, 64, 0, stream>>>(a.counter);
   if (b.total_tab > 0) batch_tables_kernel<<<(unsigned)b.sh.size(), 64, 0, stream>>>(a);
   const unsigned pblocks = (unsigned)std::min<int64_t>((b.total_blocks * 64 + 255) / 256, 1 << 16);
-  if (b.precision == RT_FP64)
+  if (b.precision == RT_FP64) {
     batch_prepare_kernel<0><<<pblocks, 256, 0, stream>>>(a);
-  else
+  } else {
     batch_prepare_kernel<1><<<pblocks, 256, 0, stream>>>(a);
+    // fixed-point units of the mixed ZHS showers (0 for the others)
+    if (!b.fx_chunks.empty())
+      batch_fx_part_kernel<<<(unsigned)b.fx_chunks.size(), kFxThreads, 0, stream>>>(a);
+    batch_fx_unit_kernel<<<(unsigned)((b.sh.size() + 63) / 64), 64, 0, stream>>>(a);
+  }
   if (ev0) (void)hipEventRecord(ev0, stream);
   for (int g = 0; g < kGroups; ++g) {
     if (b.group_begin[g + 1] == b.group_begin[g]) continue;
@@ -529,6 +642,11 @@ static std::string batch_plan(rt_batch &b, const rt_shower *showers, int32_t n, 
     d.splits = d.n_blocks == 0 ? 0 : (int32_t)((d.n_blocks + d.blocks_per_split - 1) / d.blocks_per_split);
     d.rec_block0 = b.cum[s];
     b.cum[s + 1] = b.cum[s] + d.n_blocks;
+    d.fx_chunk0 = (int32_t)b.fx_chunks.size();
+    d.fx_chunks = 0;
+    if (precision == RT_MIXED && d.formalism == RT_ZHS)
+      for (int64_t b0 = 0; b0 < d.n_blocks; b0 += kFxChunkBlocks, ++d.fx_chunks)
+        b.fx_chunks.push_back(FxChunk{s, 0, b0, std::min(kFxChunkBlocks, d.n_blocks - b0)});
     d.part0 = b.total_partial;
     b.total_partial += (int64_t)d.n_atiles * d.n_segs * d.splits * d.slot_len;
   }

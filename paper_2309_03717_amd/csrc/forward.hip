@@ -53,28 +53,6 @@ struct PrepArgs {
 constexpr int kPrepThreads = 256;
 constexpr int kPrepMaxBlocks = 65536;
 
-// Bound on the values a ZHS box of one track (mixed record v) rounds at any
-// antenna of the box [xlo, xhi] x [ylo, yhi] x [zlo, zhi]: its three levels
-// are at most |Ibar| = |cz| |beta_perp| / R_m per component, and R_m
-// (midpoint to antenna) is at least the midpoint's distance to the box.
-// Factor 1.01 covers the rounding of the deposit arithmetic.
-// Infinite when the midpoint lies in the box or more than 1e100 m from it (a
-// distance whose square would overflow the deposit geometry); 0 for a track
-// that deposits nothing (zero amplitude, or NaN times).
-__device__ __forceinline__ double zhs_track_bound(const double *v, const double *bb) {
-  const double cz = fabs((double)lo32(v[M_AB]));
-  const double bx = hi32(v[M_AB]), by = lo32(v[M_YZ]), bz = hi32(v[M_YZ]);
-  if (cz == 0.0 || isnan(v[R_T0])) return 0.0;
-  const double mx = (v[R_X0] + v[R_X1]) * 0.5, my = (v[R_Y0] + v[R_Y1]) * 0.5,
-               mz = (v[R_Z0] + v[R_Z1]) * 0.5;
-  const double ox = fmax(fmax(bb[0] - mx, mx - bb[1]), 0.0);
-  const double oy = fmax(fmax(bb[2] - my, my - bb[3]), 0.0);
-  const double oz = fmax(fmax(bb[4] - mz, mz - bb[5]), 0.0);
-  const double d2 = ox * ox + oy * oy + oz * oz;
-  if (!(d2 > 0.0 && d2 < 1e200)) return __builtin_inf();
-  return 1.01 * cz * sqrt(bx * bx + by * by + bz * bz) / sqrt(d2);
-}
-
 // One thread per (padded) track. A track with any non-finite field, and the
 // padding past the last track, get NaN times so that no antenna window
 // accepts them. Fixed-point ZHS calls also reduce the per-track deposit
@@ -122,42 +100,15 @@ __global__ void __launch_bounds__(kPrepThreads) prepare_kernel(PrepArgs g) {
 // The antennas' bounding box: bbox = {xmin, xmax, ymin, ymax, zmin, zmax}.
 // One workgroup of kPrepThreads threads.
 __global__ void __launch_bounds__(kPrepThreads) bbox_kernel(AntPtrs an, double *bbox) {
-  __shared__ double red[6][kPrepThreads];
-  double v[6] = {__builtin_inf(), -__builtin_inf(), __builtin_inf(), -__builtin_inf(),
-                 __builtin_inf(), -__builtin_inf()};
-  for (int64_t a = threadIdx.x; a < an.m; a += kPrepThreads) {
-    const double x = an.x[a], y = an.y[a], z = an.z[a];
-    v[0] = fmin(v[0], x); v[1] = fmax(v[1], x);
-    v[2] = fmin(v[2], y); v[3] = fmax(v[3], y);
-    v[4] = fmin(v[4], z); v[5] = fmax(v[5], z);
-  }
-  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = v[k];
-  __syncthreads();
-  for (int h = kPrepThreads / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
-      for (int k = 0; k < 6; ++k)
-        red[k][threadIdx.x] = (k & 1) ? fmax(red[k][threadIdx.x], red[k][threadIdx.x + h])
-                                      : fmin(red[k][threadIdx.x], red[k][threadIdx.x + h]);
-    __syncthreads();
-  }
-  if (threadIdx.x < 6) bbox[threadIdx.x] = red[threadIdx.x][0];
+  __shared__ double red[6 * kPrepThreads];
+  double bb[6];
+  antenna_bbox<kPrepThreads>(an, red, bb);
+  if (threadIdx.x < 6) bbox[threadIdx.x] = bb[threadIdx.x];
 }
 
-// The call's fixed-point unit from the prepare workgroups' bound sums and
-// maxima (summed in a fixed order, so the unit depends only on the tracks),
-// written as fx = {unit, 1 / unit}, both powers of two, or {0, 0} when the
-// call keeps the double-precision tile. With S the sum of the track bounds
-// and B their maximum:
-//  - no int64 bin of any tile, split partial or merge sum can overflow: the
-//    deposits a track adds to one bin (all four in the folded first bin of a
-//    segment) are differences of its three rounded levels, so their absolute
-//    values sum to at most 2 (r1 + r2 + r3) <= 6 (bound / unit + 1/2), and
-//    6.06 S / unit <= 2^62 leaves room for the halves of 2^31 tracks;
-//  - every deposit stays in the exact range of the rounding FMA: B / unit <
-//    2^50;
-//  - a unit coarser than 2^-30 of the mean track bound (one dominant track,
-//    or more than about 2^28 tracks in one call) would round typical
-//    deposits too coarsely: the double tile is kept.
+// The call's fixed-point unit (fx_unit) from the prepare workgroups' bound
+// sums and maxima, summed in a fixed order, written as fx = {unit, 1 / unit},
+// both powers of two, or {0, 0} when the call keeps the double-precision tile.
 __global__ void fx_reduce_kernel(const double *fx_part, int n_parts, int64_t n_tracks,
                                  double *fx) {
   __shared__ double ssum[kPrepThreads], smax[kPrepThreads];
@@ -177,16 +128,7 @@ __global__ void fx_reduce_kernel(const double *fx_part, int n_parts, int64_t n_t
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  const double S = ssum[0], B = smax[0];
-  double unit = 0.0;
-  if (S == 0.0) {
-    unit = 1.0;   // nothing deposits: any unit
-  } else if (S < 1e300 && B > 0.0) {
-    // smallest powers of two with 6.06 S / 2^e <= 2^62 and B / 2^e < 2^50
-    const int e = max(ilogb(6.06 * S) + 1 - 62, ilogb(B) + 1 - 50);
-    if (e > -1000 && e < 1000 && ldexp(1.0, e) <= ldexp(S / (double)n_tracks, -30))
-      unit = ldexp(1.0, e);
-  }
+  const double unit = fx_unit(ssum[0], smax[0], n_tracks);
   fx[0] = unit;
   fx[1] = unit > 0.0 ? 1.0 / unit : 0.0;
 }

@@ -206,6 +206,77 @@ __device__ __forceinline__ void make_record(const TrackPtrs &tr, int64_t i, bool
   }
 }
 
+// Bound on the values a ZHS box of one track (mixed record v) rounds at any
+// antenna of the box [xlo, xhi] x [ylo, yhi] x [zlo, zhi]: its three levels
+// are at most |Ibar| = |cz| |beta_perp| / R_m per component, and R_m
+// (midpoint to antenna) is at least the midpoint's distance to the box.
+// Factor 1.01 covers the rounding of the deposit arithmetic.
+// Infinite when the midpoint lies in the box or more than 1e100 m from it (a
+// distance whose square would overflow the deposit geometry); 0 for a track
+// that deposits nothing (zero amplitude, or NaN times).
+__device__ __forceinline__ double zhs_track_bound(const double *v, const double *bb) {
+  const double cz = fabs((double)lo32(v[M_AB]));
+  const double bx = hi32(v[M_AB]), by = lo32(v[M_YZ]), bz = hi32(v[M_YZ]);
+  if (cz == 0.0 || isnan(v[R_T0])) return 0.0;
+  const double mx = (v[R_X0] + v[R_X1]) * 0.5, my = (v[R_Y0] + v[R_Y1]) * 0.5,
+               mz = (v[R_Z0] + v[R_Z1]) * 0.5;
+  const double ox = fmax(fmax(bb[0] - mx, mx - bb[1]), 0.0);
+  const double oy = fmax(fmax(bb[2] - my, my - bb[3]), 0.0);
+  const double oz = fmax(fmax(bb[4] - mz, mz - bb[5]), 0.0);
+  const double d2 = ox * ox + oy * oy + oz * oz;
+  if (!(d2 > 0.0 && d2 < 1e200)) return __builtin_inf();
+  return 1.01 * cz * sqrt(bx * bx + by * by + bz * bz) / sqrt(d2);
+}
+
+// The antennas' bounding box {xmin, xmax, ymin, ymax, zmin, zmax} over a
+// workgroup of NT threads (red: 6 NT doubles of LDS); every thread gets it.
+template <int NT>
+__device__ __forceinline__ void antenna_bbox(const AntPtrs &an, double *red, double bb[6]) {
+  double v[6] = {__builtin_inf(), -__builtin_inf(), __builtin_inf(), -__builtin_inf(),
+                 __builtin_inf(), -__builtin_inf()};
+  for (int64_t a = threadIdx.x; a < an.m; a += NT) {
+    const double x = an.x[a], y = an.y[a], z = an.z[a];
+    v[0] = fmin(v[0], x); v[1] = fmax(v[1], x);
+    v[2] = fmin(v[2], y); v[3] = fmax(v[3], y);
+    v[4] = fmin(v[4], z); v[5] = fmax(v[5], z);
+  }
+  for (int k = 0; k < 6; ++k) red[k * NT + threadIdx.x] = v[k];
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 6; ++k) {
+        double &r = red[k * NT + threadIdx.x];
+        const double o = red[k * NT + threadIdx.x + h];
+        r = (k & 1) ? fmax(r, o) : fmin(r, o);
+      }
+    __syncthreads();
+  }
+  for (int k = 0; k < 6; ++k) bb[k] = red[k * NT];
+  __syncthreads();
+}
+
+// The fixed-point unit of a call (or of a batched shower) from the sum S and
+// the maximum B of its n_tracks tracks' deposit bounds (zhs_track_bound),
+// reduced in a fixed order so that the unit depends only on the tracks: the
+// smallest power of two with
+//  - no int64 bin of any tile, split partial or merge sum overflowing: the
+//    deposits a track adds to one bin (all four in the folded first bin of a
+//    segment) are differences of its three rounded levels, so their absolute
+//    values sum to at most 2 (r1 + r2 + r3) <= 6 (bound / unit + 1/2), and
+//    6.06 S / unit <= 2^62 leaves room for the halves of 2^31 tracks;
+//  - every deposit in the exact range of the rounding FMA: B / unit < 2^50.
+// 0 (keep the double-precision tile) when that unit would be coarser than
+// 2^-30 of the mean track bound (one dominant track, or more than about 2^28
+// tracks) or no finite bound exists; 1 when nothing deposits.
+__device__ __forceinline__ double fx_unit(double S, double B, int64_t n_tracks) {
+  if (S == 0.0) return 1.0;
+  if (!(S < 1e300 && B > 0.0)) return 0.0;
+  const int e = max(ilogb(6.06 * S) + 1 - 62, ilogb(B) + 1 - 50);
+  if (e > -1000 && e < 1000 && ldexp(1.0, e) <= ldexp(S / (double)n_tracks, -30))
+    return ldexp(1.0, e);
+  return 0.0;
+}
+
 // Adds (vx, vy, vz) to the three components at p (bin j of a tile row, from
 // lds_bin).
 __device__ __forceinline__ void put3(lds<acc_t> *p, double vx, double vy, double vz) {

@@ -401,3 +401,29 @@ def test_batch_tables_travel_in_the_workspace(rt):
     for got, ref in ((fetch(a.traces), ref_a), (fetch(b.traces), ref_b)):
         for g, e in zip(got, ref):
             np.testing.assert_allclose(g, 2 * e, rtol=0, atol=1e-5 * max(np.abs(e).max(), 1e-30))
+
+
+SHAPES = [dict(), dict(block_threads=256, items_per_cu=1),
+          dict(block_threads=1024, max_antennas_per_tile=1, items_per_cu=8),
+          dict(max_antennas_per_tile=1, direct_launch=1)]
+
+
+def test_mixed_zhs_batches_are_bitwise_identical_across_launch_shapes(rt):
+    """Mixed ZHS showers accumulate in 64-bit fixed point with a unit per
+    shower: every launch shape (workgroup size, tile width, items per CU,
+    graph or direct) and a single plan over the same tracks give the same
+    bits; the Endpoint showers agree to summation order."""
+    showers = small_showers(8, 3000)
+    assert {s.formalism for s in showers} == {"zhs", "endpoint"}
+    tracks = [host_tracks(s, "mixed") for s in showers]
+    dev = device_showers(rt, showers, "mixed", tracks)
+    runs = [fetch(rt.Batch(dev, "mixed", options=rt.BatchOptions(**o)).launch()) for o in SHAPES]
+    singles = [fetch([rt.Plan(det, md, f, "mixed").traces(dtr)])[0] for det, md, f, dtr in dev]
+    for i, sh in enumerate(showers):
+        for r in runs[1:]:
+            if sh.formalism == "zhs":
+                np.testing.assert_array_equal(r[i], runs[0][i], err_msg=f"shower {i}")
+            else:
+                assert np.abs(r[i] - runs[0][i]).max() <= 1e-6 * max(np.abs(runs[0][i]).max(), 1e-300)
+        if sh.formalism == "zhs":
+            np.testing.assert_array_equal(runs[0][i], singles[i], err_msg=f"shower {i} vs plan")
