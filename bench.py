@@ -70,7 +70,7 @@ VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 # only while the kernel sources and the launch shape are the measured ones;
 # otherwise null.
 COUNTER_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
-COUNTERS_HASH = "bcd99bc6dfcd631c"
+COUNTERS_HASH = "42190ea2fb13481b"
 COUNTERS_PROFILE = {"traffic": "profiles/deposit_grid4096_mixed_hbm_bytes.md",
                     "valu": "profiles/deposit_grid4096_mixed_counters.md"}
 TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.4, "write": 1048576.0 / 1048576.0}
