@@ -349,11 +349,13 @@ Tiling choose_tiling(const rt_plan &p, int64_t n) {
     // of the workgroup over its tracks
     int64_t resident = (int64_t)p.num_cus * (int64_t)std::max<size_t>(1, p.lds_per_cu / t.lds_bytes);
     splits = (2 * resident + n_tiles - 1) / n_tiles;
-    // ZHS workgroups drift apart (a box costs more than a missed window, and
-    // which tracks land depends on the antenna), so the workgroups resident
-    // together stop sharing records in L2 over long track ranges: cap a
-    // split at kZhsSplitBlocks wave blocks
-    if (p.formalism == RT_ZHS) splits = std::max(splits, (nb + kZhsSplitBlocks - 1) / kZhsSplitBlocks);
+    // workgroups drift apart where deposits cost unequally across antennas
+    // (a ZHS box costs more than a missed window; shower-like tracks land far
+    // more often near the axis), so the workgroups resident together stop
+    // sharing records in L2 over long track ranges: cap a split at
+    // kZhsSplitBlocks (ZHS) or kEpSplitBlocks (Endpoint) wave blocks
+    const int64_t cap_blocks = p.formalism == RT_ZHS ? kZhsSplitBlocks : kEpSplitBlocks;
+    splits = std::max(splits, (nb + cap_blocks - 1) / cap_blocks);
     int64_t cap = std::max<int64_t>(1, nb / (4 * (t.block / 64)));
     if (splits > cap) splits = cap;
     if (splits < 1) splits = 1;

@@ -34,6 +34,7 @@ constexpr int kMaxTile = 8;     // antennas per workgroup tile (template bound)
 constexpr int64_t kDefaultPass = 1 << 20;   // tracks per deposit pass by default
 constexpr int kXcds = 8;        // MI355X: 8 XCDs, workgroups dealt round-robin
 constexpr int64_t kZhsSplitBlocks = 2048;   // ZHS track split cap: 128K tracks
+constexpr int64_t kEpSplitBlocks = 4096;    // Endpoint track split cap: 256K tracks
 constexpr int kGl = 8;          // Gauss-Legendre nodes of the spherical path mean
 
 struct Consts {

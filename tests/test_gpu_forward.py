@@ -468,3 +468,36 @@ def test_large_array_and_long_traces(rt, orc):
         ref = oracle_traces(orc, formalism, "mixed", tr, sub, md)
         assert np.abs(ref).max() > 0
         assert rel_l2(got, ref).max() <= MIXED_BOUND, formalism
+
+
+def test_endpoint_source_index_near_the_antenna_height(rt, orc):
+    """Exponential medium, antennas on the ground: mixed Endpoint deposits take
+    the source index from the path index (inverting the path mean), and below
+    1 mm of height difference from its midpoint form. Track ends within a
+    millimetre of the antennas' height (including exactly at it), just outside
+    that branch, and far above it: both precisions and both formalisms meet
+    their bounds against the oracle, which uses the local index directly."""
+    md = W.EXPONENTIAL_AIR
+    ant = np.array([[0.0, 0.0, 0.0], [100.0, 0.0, 0.0], [0.0, 150.0, 0.0], [-80.0, -40.0, 0.0]])
+    ends = [((50.0, 20.0, 4e-4), (52.0, 20.0, 2e-4)),
+            ((-30.0, 40.0, 9e-4), (-30.0, 38.0, 0.0)),
+            ((10.0, -60.0, 3e-4), (10.5, -60.0, -3e-4)),
+            ((20.0, 80.0, 1.5e-3), (25.0, 80.0, 1.2e-3)),
+            ((5.0, 5.0, 300.0), (5.0, 5.0, 290.0)),
+            ((-60.0, 10.0, 2.0), (-58.0, 10.0, 0.0005))]
+    tracks = []
+    for i, (p0, p1) in enumerate(ends):
+        d = np.subtract(p1, p0)
+        beta = 0.995 * d / np.linalg.norm(d)
+        tracks.append(one_track(p0, p1, beta, t0=1e-8 * i, qw=1.0 if i % 2 else -1.0))
+    tr = W.Tracks.concat(tracks)
+    arr = antennas(ant, 0.0, 0.1e-9, 65536)
+    for formalism in ("endpoint", "zhs"):
+        for precision, bound in (("fp64", FP64_BOUND), ("mixed", MIXED_BOUND)):
+            t = tr.to_mixed() if precision == "mixed" else tr
+            ref = orc.traces(formalism, t.widened() if precision == "mixed" else t, arr, md)
+            got = gpu_traces(rt, formalism, precision, t, arr, md)
+            assert np.abs(ref).max() > 0
+            err = rel_l2(got, ref).max()
+            print(formalism, precision, "near the antenna height: max rel L2", err)
+            assert err <= bound, (formalism, precision, err)
