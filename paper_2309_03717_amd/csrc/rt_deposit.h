@@ -297,16 +297,15 @@ __device__ __forceinline__ unsigned long long fx_biased(double v, double s) {
 }
 
 // Local index at an emission point P from the exponential medium's path
-// index n_eff to an antenna X (dz = z_P - z_X, ns_x = 1 + n0m1 e_X, inv_h =
-// 1 / h): inverting n_eff = 1 + n0m1 h (e_X - e_P) / dz gives
-// 1 + n0m1 e_P = ns_x - (n_eff - 1) dz / h; below the 1-mm branch, where
-// n_eff - 1 = n0m1 e((z_P + z_X) / 2), it is n_eff - (n_eff - 1) dz / (2 h) up
-// to a term below 1e-18. The result differs from 1 + n0m1 e_P by a few units
-// in the last place.
+// index n_eff to an antenna X (dz = z_X - z_P, the offset the timing forms;
+// ns_x = 1 + n0m1 e_X, inv_h = 1 / h): inverting n_eff = 1 + n0m1 h (e_P -
+// e_X) / dz gives 1 + n0m1 e_P = ns_x + (n_eff - 1) dz / h. Below the 1-mm
+// branch, where n_eff - 1 = n0m1 e((z_P + z_X) / 2), the same expression
+// misses 1 + n0m1 e_P by n0m1 e_X (dz / h)^3 / 24, below 1e-22. The result
+// differs from 1 + n0m1 e_P by a few units in the last place.
 __device__ __forceinline__ double source_from_path(double neff, double dz, double ns_x,
                                                    double inv_h) {
-  const bool mid = fabs(dz) < 1e-3;
-  return fma(-(neff - 1.0), dz * (mid ? 0.5 * inv_h : inv_h), mid ? neff : ns_x);
+  return fma(neff - 1.0, dz * inv_h, ns_x);
 }
 
 // Endpoint impulse of one track end at one antenna: s k qw [r x (r x beta)] /
@@ -327,6 +326,10 @@ __device__ __forceinline__ void endpoint_amp(lds<acc_t> *row, int lo, double lo_
     q = bd / r2;
     a = sc / num;
   } else {
+    // RT_MIXED: refined reciprocals. The hardware estimate of 1 / num (4.6e-8)
+    // is 2% faster but raised the worst antenna's error from 6e-8 to 3.6e-7:
+    // a bin's start and end impulses largely cancel, and an error relative
+    // to each impulse is not small relative to their sum.
     q = bd * fast_rcp(r2);
     a = sc * fast_rcp(num);
   }
@@ -446,7 +449,7 @@ struct TileRef {
 };
 
 // All deposits of one track record (this lane's track) into the tile
-// antennas selected by mask.
+// antennas selected by mask (a one-antenna tile always holds its antenna).
 // H: the height factors were loaded (deposit_blocks loads them where they are
 // used). FX: fixed-point ZHS tile.
 // Nodes: where the spherical path mean reads its quadrature nodes.
@@ -487,7 +490,7 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
   double ns1 = MED != 0 ? fma(c.n0m1, e1, 1.0) : c.n_uniform;
 #pragma unroll
   for (int a = 0; a < AT; ++a) {
-    if ((mask >> a) & 1) {
+    if (AT == 1 || ((mask >> a) & 1)) {
       double ne0 = MED == 0 ? c.n_uniform : v[R_NE0];
       double ne1 = MED == 0 ? c.n_uniform : v[R_NE1];
       if (MED == 3) {
@@ -500,10 +503,6 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
         ne1 = path_index_m<MED>(z1, t.az[a], p1, t.ea[a], c);
       }
       lds<acc_t> *row = tr.row(a);
-      if constexpr (kNsFromPath) {
-        ns0 = source_from_path(ne0, z0 - t.az[a], t.nsa[a], t.inv_h);
-        ns1 = source_from_path(ne1, z1 - t.az[a], t.nsa[a], t.inv_h);
-      }
       if constexpr (F == 1 && P == 1) {
         // times in bins, path indices over c dt (make_record); the indices
         // taken here are plain
@@ -525,6 +524,10 @@ __device__ __forceinline__ void deposit_record(const double *v, uint64_t mask, c
                                      dx0, dy0, dz0, r0, q0);
       const double u1 = arrival_bins(x1, y1, z1, t1, t.ax[a], t.ay[a], t.az[a], t.tau[a], ne1, c,
                                      dx1, dy1, dz1, r1, q1);
+      if constexpr (kNsFromPath) {
+        ns0 = source_from_path(ne0, dz0, t.nsa[a], t.inv_h);
+        ns1 = source_from_path(ne1, dz1, t.nsa[a], t.inv_h);
+      }
       if (F == 0) {
         endpoint_amp<P>(row, tr.lo, tr.lo_d, tr.hi_d, u0, amp, dx0, dy0, dz0, r0, q0, ns0, bx, by,
                         bz);
