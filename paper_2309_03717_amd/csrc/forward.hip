@@ -200,9 +200,11 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   const int64_t waves = blockDim.x >> 6;
   const int64_t b_first = (int64_t)split * g.blocks_per_split + (threadIdx.x >> 6);
   const int64_t b_end = min(g.n_blocks, (int64_t)(split + 1) * g.blocks_per_split);
-  // record prefetch where record latency shows: the Endpoint deposit, except
-  // over the spherical Earth, whose per-pair quadrature dominates
-  constexpr int kPf = F == 0 && MED != 3 ? kPfAlternate : kPfNone;
+  // record prefetch: the Endpoint deposit and the one-antenna ZHS deposit
+  // (alternating buffers for mixed records; the wider ZHS tiles would spill
+  // the second buffer), except over the spherical Earth, whose per-pair
+  // quadrature dominates
+  constexpr int kPf = MED != 3 && (F == 0 || AT == 1) ? kPfAlternate : kPfNone;
   if (kFxCap && fx_unit > 0.0)
     deposit_blocks<F, P, MED, AT, kPf, true>(g.rec, b_first, b_end, waves, mask, t, tr, c,
                                              ConstNodes{g.c});

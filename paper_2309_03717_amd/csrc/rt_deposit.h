@@ -382,9 +382,15 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
   double s3 = two ? bb : -t3;
   double s4 = -bb;
   // kl <= hi - 1 (the box starts before the segment end) and lo <= jh <= hi
+  // (the clamps as single v_max_f64 / v_min_f64: fmax and fmin would quiet
+  // each operand not known to be a number first, the loop-invariant bounds
+  // included, on every pair; none of the four is NaN here)
   const double lo_m2 = lo_d - 2.0;
-  const int jl = (int)fmax(kl, lo_m2) - lo;
-  const int jh = (int)fmin(kh, hi_d) - lo;
+  double cl, ch;
+  asm("v_max_f64 %0, %1, %2" : "=v"(cl) : "v"(kl), "v"(lo_m2));
+  asm("v_min_f64 %0, %1, %2" : "=v"(ch) : "v"(kh), "v"(hi_d));
+  const int jl = (int)cl - lo;
+  const int jh = (int)ch - lo;
   lds<acc_t> *p1 = lds_bin(row, max(jl, 0));
   lds<acc_t> *p2 = lds_bin(row, max(jl + 1, 0));
   lds<acc_t> *p3 = lds_bin(row, jh);
@@ -559,10 +565,10 @@ __device__ __forceinline__ void load_record(const double *rec, int64_t blk, int 
 // before processing the current one (one buffer, copied); kPfAlternate does
 // so, for mixed records without height factors, into the other of two record
 // buffers (the loop takes two blocks per turn: no copies, more registers).
-// That pays where record latency shows (the Endpoint deposit) or few waves
-// share a SIMD (the 512-thread batch kernel); the single-plan ZHS deposit,
-// with more arithmetic per record and four waves per SIMD, runs faster
-// without it.
+// That pays where record latency shows (the Endpoint deposit), few waves
+// share a SIMD (the 512-thread batch kernel), or, with alternating buffers,
+// for the one-antenna mixed ZHS deposit; with a copied buffer the single-plan
+// ZHS deposit runs faster without it.
 enum : int { kPfNone = 0, kPfNext = 1, kPfAlternate = 2 };
 
 template <int F, int P, int MED, int AT, bool H, int PF, bool FX, class Nodes>
@@ -571,7 +577,11 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
                                                  const Tile<AT> &t, const TileRef &tr,
                                                  const Consts &c, const Nodes &nd) {
   const int lane = threadIdx.x & 63;
-  if (PF == kPfNone) {
+  constexpr bool kAlt = PF == kPfAlternate && P == 1 && !H;
+  // ZHS deposits prefetch only into alternating buffers: with a copied
+  // buffer they ran slower than with none
+  constexpr bool kCopy = !kAlt && (PF == kPfNext || (PF == kPfAlternate && F == 0));
+  if (!kAlt && !kCopy) {
     for (int64_t blk = b_first; blk < b_end; blk += waves) {
       double rv[kRec];
       load_record<F, P, MED, H>(rec, blk, lane, rv);
@@ -579,7 +589,7 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
     }
     return;
   }
-  if constexpr (PF == kPfAlternate && P == 1 && !H) {
+  if constexpr (kAlt) {
     double ra[kRec], rb[kRec];
 #pragma unroll
     for (int f = 0; f < kRec; ++f) ra[f] = rb[f] = 0.0;
