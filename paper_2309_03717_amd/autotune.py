@@ -177,6 +177,25 @@ def tune_batch(showers, precision: str = "mixed", k: float = 1.0,
 # ------------------------------------------------------------------ single plans
 PLAN_BLOCKS = (256, 512, 1024)
 PLAN_PASSES = (1 << 19, 1 << 20, 1 << 21)
+# track-split multiples of the automatic count tried at the automatic block
+# size and pass length: time-ordered track streams (a shower's) keep the
+# workgroups of an XCD sharing their records in L2 better with shorter splits
+PLAN_SPLIT_FACTORS = (2,)
+
+
+def plan_candidates(auto_tiling):
+    """Default candidates of tune_plan: the automatic tile at every block size
+    and pass length, then the automatic block size and pass length with twice
+    the automatic track splits. auto_tiling is the plan's automatic
+    (antennas_per_block, track_splits, block_threads, bins_per_segment,
+    tracks_per_pass) for the tuned call."""
+    cands = [[0, 0, b, 0, p] for b in PLAN_BLOCKS for p in PLAN_PASSES]
+    splits, block, pass_len = auto_tiling[1], auto_tiling[2], auto_tiling[4]
+    for f in PLAN_SPLIT_FACTORS:
+        c = [0, splits * f, block, 0, pass_len]
+        if c not in cands:
+            cands.append(c)
+    return cands
 
 
 def plan_key(plan, n_tracks: int) -> str:
@@ -189,11 +208,14 @@ def tune_plan(plan, tracks, cache_path: Optional[str] = None, candidates=None, r
               log=None):
     """Sets and returns the fastest (antennas_per_block, track_splits,
     block_threads, bins_per_segment, tracks_per_pass) tiling of a Plan for
-    calls like plan.accumulate(tracks); candidates default to the automatic
-    tile with every block size and pass length above."""
+    calls like plan.accumulate(tracks); candidates default to plan_candidates
+    of the plan's automatic tiling."""
     from . import radtrace as rt
     key = plan_key(plan, tracks.n)
-    cands = candidates or [[0, 0, b, 0, p] for b in PLAN_BLOCKS for p in PLAN_PASSES]
+    if not candidates:
+        plan.set_tiling()   # the automatic tiling, whatever was set before
+        candidates = plan_candidates(list(plan.tiling(tracks.n)))
+    cands = candidates
     best, timings, cached = tune(key, cands, None, TuningCache(cache_path), log,
                                  measure_all=lambda cs: rt.rt_plan_autotune(plan, tracks, cs, reps))
     plan.set_tiling(*best)

@@ -96,3 +96,15 @@ def test_finalists_come_from_distinct_families(tmp_path):
                                final_measure=final, family=lambda c: (c[0], c[1]))
     assert best == [512, 3, 2]
     assert finals == [(1024, 1, 2), (512, 3, 2), (512, 2, 2)]
+
+
+def test_plan_candidates_add_shorter_track_splits():
+    """The plan autotuner's default candidates: every block size and pass
+    length with the automatic tile, plus the automatic launch with twice the
+    automatic split count (shorter splits suit time-ordered track streams)."""
+    auto = (1, 4, 1024, 4096, 1 << 20)
+    cands = autotune.plan_candidates(auto)
+    base = [[0, 0, b, 0, p] for b in autotune.PLAN_BLOCKS for p in autotune.PLAN_PASSES]
+    assert cands[:len(base)] == base
+    assert cands[len(base):] == [[0, 8, 1024, 0, 1 << 20]]
+    assert len({tuple(c) for c in cands}) == len(cands)

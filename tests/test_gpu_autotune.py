@@ -63,3 +63,26 @@ def test_plan_autotune_skips_candidates_beyond_the_workspace(rt):
     assert st == rt.RT_OK, rt.rt_last_error()
     assert ms[0] == -1.0 and ms[1] > 0 and best.value == 1
     assert plan.tiling(dtr.n)[1] == 1
+
+
+def test_plan_autotune_default_candidates(rt, tmp_path):
+    """tune_plan without candidates: the automatic tile at every block size and
+    pass length plus twice the automatic split count, all timed; the winner is
+    set on the plan and leaves the fixed-point ZHS traces bit for bit."""
+    import torch
+    from paper_2309_03717_amd import autotune
+    w = W.config(1)
+    det = rt.DeviceDetector.from_array(w.array)
+    plan = rt.Plan(det, w.medium, "zhs", "mixed")
+    dtr = rt.DeviceTracks.from_tracks(w.tracks(50_000, mixed=True))
+    plan.set_tiling(0, 5, 256, 0, 0)   # replaced by the automatic tiling first
+    ref = plan.traces(dtr).cpu().numpy()
+    plan.set_tiling()
+    auto = list(plan.tiling(dtr.n))
+    best, timings, cached = autotune.tune_plan(plan, dtr, cache_path=str(tmp_path / "t.json"))
+    cands = autotune.plan_candidates(auto)
+    assert not cached and len(timings) == len(cands) and best in cands
+    assert all(t > 0 for _, t in timings)
+    assert list(plan.tiling(dtr.n))[2] == (best[2] or auto[2])
+    np.testing.assert_array_equal(plan.traces(dtr).cpu().numpy(), ref)
+    torch.cuda.synchronize()
