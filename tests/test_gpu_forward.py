@@ -472,8 +472,9 @@ def test_large_array_and_long_traces(rt, orc):
 
 def test_endpoint_source_index_near_the_antenna_height(rt, orc):
     """Exponential medium, antennas on the ground: mixed Endpoint deposits take
-    the source index from the path index (inverting the path mean), and below
-    1 mm of height difference from its midpoint form. Track ends within a
+    the source index from the path index by inverting the path mean, also
+    below 1 mm of height difference, where the path index is the midpoint
+    value and the inversion is off by a term below 1e-22. Track ends within a
     millimetre of the antennas' height (including exactly at it), just outside
     that branch, and far above it: both precisions and both formalisms meet
     their bounds against the oracle, which uses the local index directly."""
