@@ -320,7 +320,8 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     __syncthreads();
     const double *rec = b.rec + uniform(sd.rec_block0) * (kRec * 64);
     const int64_t per_split = uniform(sd.blocks_per_split);
-    const int64_t b_first = (int64_t)w.split * per_split + (threadIdx.x >> 6);
+    const int64_t b_first =
+        (int64_t)w.split * per_split + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t b_end = min(uniform(sd.n_blocks), (int64_t)(w.split + 1) * per_split);
     constexpr int M0 = HEAVY ? 2 : 0, M1 = HEAVY ? 3 : 1;   // this kernel's two media
     const bool m1 = c.medium == M1;

@@ -198,7 +198,10 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
 
   const uint64_t mask = (1ull << n_ant) - 1;
   const int64_t waves = blockDim.x >> 6;
-  const int64_t b_first = (int64_t)split * g.blocks_per_split + (threadIdx.x >> 6);
+  // the wave index as a wave-uniform value: block counters and loop tests
+  // then live in scalar registers
+  const int64_t b_first =
+      (int64_t)split * g.blocks_per_split + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t b_end = min(g.n_blocks, (int64_t)(split + 1) * g.blocks_per_split);
   // record prefetch: the Endpoint deposit and the one-antenna ZHS deposit
   // (alternating buffers for mixed records; the wider ZHS tiles would spill

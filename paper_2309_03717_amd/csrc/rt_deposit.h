@@ -123,14 +123,16 @@ __device__ __forceinline__ void store_record(double *blk, int l, const double *v
 }
 
 // Reads the slots of lane l's record that a deposit uses (slot_loaded), one
-// pair per load; the other slots read as 0.
+// pair per load; the other slots read as 0. The lane's byte offset in the
+// 8-KB block is formed in 32 bits.
 template <int P, int MED, bool H>
 __device__ __forceinline__ void load_record_pairs(const double *blk, int l, double *v) {
   static_assert(pairs_agree<P, MED, H>(), "records are loaded a whole pair at a time");
 #pragma unroll
   for (int g = 0; g < kRec; g += 2) {
     if (slot_loaded<P, MED, H>(g)) {
-      const double2 d = *reinterpret_cast<const double2 *>(blk + g * 64 + 2 * l);
+      const double2 d = *reinterpret_cast<const double2 *>(
+          reinterpret_cast<const char *>(blk) + (unsigned)(g * 512 + 16 * l));
       v[g] = d.x;
       v[g + 1] = d.y;
     } else {
@@ -577,12 +579,15 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
                                                  const Tile<AT> &t, const TileRef &tr,
                                                  const Consts &c, const Nodes &nd) {
   const int lane = threadIdx.x & 63;
+  // block indices in 32 bits (a call holds at most 2^31 tracks, 2^25 blocks):
+  // with a wave-uniform b_first the loop tests are scalar compares
+  const int bf = (int)b_first, be = (int)b_end, wv = (int)waves;
   constexpr bool kAlt = PF == kPfAlternate && P == 1 && !H;
   // ZHS deposits prefetch only into alternating buffers: with a copied
   // buffer they ran slower than with none
   constexpr bool kCopy = !kAlt && (PF == kPfNext || (PF == kPfAlternate && F == 0));
   if (!kAlt && !kCopy) {
-    for (int64_t blk = b_first; blk < b_end; blk += waves) {
+    for (int blk = bf; blk < be; blk += wv) {
       double rv[kRec];
       load_record<F, P, MED, H>(rec, blk, lane, rv);
       deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
@@ -593,12 +598,12 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
     double ra[kRec], rb[kRec];
 #pragma unroll
     for (int f = 0; f < kRec; ++f) ra[f] = rb[f] = 0.0;
-    if (b_first < b_end) load_record<F, P, MED, H>(rec, b_first, lane, ra);
-    for (int64_t blk = b_first; blk < b_end; blk += 2 * waves) {
-      if (blk + waves < b_end) load_record<F, P, MED, H>(rec, blk + waves, lane, rb);
+    if (bf < be) load_record<F, P, MED, H>(rec, bf, lane, ra);
+    for (int blk = bf; blk < be; blk += 2 * wv) {
+      if (blk + wv < be) load_record<F, P, MED, H>(rec, blk + wv, lane, rb);
       deposit_record<F, P, MED, AT, H, FX>(ra, mask, t, tr, c, nd);
-      if (blk + waves >= b_end) break;
-      if (blk + 2 * waves < b_end) load_record<F, P, MED, H>(rec, blk + 2 * waves, lane, ra);
+      if (blk + wv >= be) break;
+      if (blk + 2 * wv < be) load_record<F, P, MED, H>(rec, blk + 2 * wv, lane, ra);
       deposit_record<F, P, MED, AT, H, FX>(rb, mask, t, tr, c, nd);
     }
   } else {
@@ -608,12 +613,12 @@ __device__ __forceinline__ void deposit_blocks_n(const double *rec, int64_t b_fi
     double nx[kRec];
 #pragma unroll
     for (int f = 0; f < kRec; ++f) nx[f] = 0.0;
-    if (b_first < b_end) load_record<F, P, MED, H>(rec, b_first, lane, nx);
-    for (int64_t blk = b_first; blk < b_end; blk += waves) {
+    if (bf < be) load_record<F, P, MED, H>(rec, bf, lane, nx);
+    for (int blk = bf; blk < be; blk += wv) {
       double rv[kRec];
 #pragma unroll
       for (int f = 0; f < kRec; ++f) rv[f] = nx[f];
-      if (blk + waves < b_end) load_record<F, P, MED, H>(rec, blk + waves, lane, nx);
+      if (blk + wv < be) load_record<F, P, MED, H>(rec, blk + wv, lane, nx);
       deposit_record<F, P, MED, AT, H, FX>(rv, mask, t, tr, c, nd);
     }
   }
