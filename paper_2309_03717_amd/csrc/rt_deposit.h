@@ -261,12 +261,14 @@ __device__ __forceinline__ void antenna_bbox(const AntPtrs &an, double *red, dou
 // the maximum B of its n_tracks tracks' deposit bounds (zhs_track_bound),
 // reduced in a fixed order so that the unit depends only on the tracks: the
 // smallest power of two with
-//  - no int64 bin of any tile, split partial or merge sum overflowing: the
-//    deposits a track adds to one bin (all four in the folded first bin of a
-//    segment) are differences of its three rounded levels, so their absolute
-//    values sum to at most 2 (r1 + r2 + r3) <= 6 (bound / unit + 1/2), and
-//    6.06 S / unit <= 2^62 leaves room for the halves of 2^31 tracks;
-//  - every deposit in the exact range of the rounding FMA: B / unit < 2^50.
+//  - no int64 bin of any tile, split partial or merge sum overflowing: what
+//    a track adds to one bin (all four deposits in the folded first bin of
+//    a segment) is a signed sum of the rounded levels that reach a bin, at
+//    most 2 (r1 + r2 + r3) <= 6 (bound / unit + 1/2) in absolute value, and
+//    6.06 S / unit <= 2^62 leaves room for the halves of 2^31 tracks (the
+//    sums wrap modulo 2^64, so only the final values need to fit);
+//  - every level that reaches a bin in the exact range of the rounding FMA:
+//    B / unit < 2^50 (a two-bin box's middle level cancels out of its bin).
 // 0 (keep the double-precision tile) when that unit would be coarser than
 // 2^-30 of the mean track bound (one dominant track, or more than about 2^28
 // tracks) or no finite bound exists; 1 when nothing deposits.
@@ -401,18 +403,22 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
     // kl), r(l2 I) (the whole bins between) and r(l3 I) (bin kh), deposited
     // as their exact integer differences, so that every box's deposits
     // telescope to zero after its last bin (no rounding residue reaches the
-    // bins beyond it, whatever the segmentation). Every level is at most 1:
-    // a one-bin box has l1 = 1, l2 = 0; a two-bin box has no whole bin
-    // between (l2 = a, its difference vanishes there).
-    const double l1 = one ? 1.0 : a, l2 = one ? 0.0 : (two ? a : wi), l3 = bb;
+    // bins beyond it, whatever the segmentation). A one-bin box has l1 = 1,
+    // l2 = 0. A two-bin box has no whole bin between: its p2 and p3 deposits
+    // fall into the same bin (kl + 1 = kh, clamps included), where l2 drops
+    // out of their wrapping int64 sum, so it takes l2 = wi like a wider box
+    // (wi may exceed 1 there; every level that reaches a bin is at most 1).
+    // The p2 difference is issued before the p1 level so that b1 can be
+    // rebased in place.
+    const double l1 = one ? 1.0 : a, l2 = one ? 0.0 : wi, l3 = bb;
     const double v[3] = {ix, iy, iz};
     unsigned long long b1[3], b2[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       b1[k] = fx_biased(v[k], l1);
       b2[k] = fx_biased(v[k], l2);
-      lds_add(as_u64(p1) + k, b1[k] - kFxMagicBits);
       lds_add(as_u64(p2) + k, b2[k] - b1[k]);
+      lds_add(as_u64(p1) + k, b1[k] - kFxMagicBits);
     }
     if (!one) {
 #pragma unroll
