@@ -70,13 +70,13 @@ VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9
 # only while the kernel sources and the launch shape are the measured ones;
 # otherwise null.
 COUNTER_SOURCES = ("rt_device.h", "rt_deposit.h", "forward.hip")
-COUNTERS_HASH = "b9fb6957f73da72b"
+COUNTERS_HASH = "c3588e4b4cbd6da9"
 COUNTERS_PROFILE = {"traffic": "profiles/deposit_grid4096_mixed_hbm_bytes.md",
                     "valu": "profiles/deposit_grid4096_mixed_counters.md"}
-TRAFFIC_SCALE = {"fetch": 1048576.0 / 524303.5, "write": 1048576.0 / 1048576.0}
-TRAFFIC_KIB = {"endpoint": {"fetch": 16799679.1, "write": 1572864.0},
-               "zhs": {"fetch": 11768740.0, "write": 3145728.0}}
-SQ_INSTS_VALU = {"endpoint": 7.512e9, "zhs": 8.103e9}
+TRAFFIC_SCALE = {"fetch": 1048576.0 / 524304.4, "write": 1048576.0 / 1048576.0}
+TRAFFIC_KIB = {"endpoint": {"fetch": 16921235.0, "write": 1572864.0},
+               "zhs": {"fetch": 11875037.5, "write": 3145728.0}}
+SQ_INSTS_VALU = {"endpoint": 7.512e9, "zhs": 7.841e9}
 COUNTERS_PASS = 1 << 20
 
 

@@ -313,7 +313,8 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     // mixed ZHS showers with a fixed-point unit: int64 tile (zero bits are 0)
     const double fx_inv = P == 1 && f == 1 ? uniform(b.fx[2 * w.shower + 1]) : 0.0;
     const bool fx = fx_inv > 0.0;
-    const TileRef tr{tile, stride, lo, (double)lo, (double)hi, fx_inv};
+    const int front = tile_front(f) * 3;
+    const TileRef tr{tile, stride, lo, (double)lo, (double)hi, fx_inv, front};
     if (HEAVY && c.medium == 3 && threadIdx.x < 2 * kGl)
       nodes[threadIdx.x] =
           threadIdx.x < kGl ? sd.c.gl_s[threadIdx.x] : sd.c.gl_w[threadIdx.x - kGl];
@@ -345,9 +346,13 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
     const int64_t slot =
         ((int64_t)w.atile * uniform(sd.n_segs) + w.seg) * uniform(sd.splits) + w.split;
     acc_t *dst = b.partial + uniform(sd.part0) + slot * slot_len;
-    for (int a = 0; a < n_ant; ++a)
+    for (int a = 0; a < n_ant; ++a) {
+      const lds<acc_t> *src = tile + a * stride + front;
       for (int i = threadIdx.x; i < row_len; i += blockDim.x)
-        dst[(int64_t)a * seg_len * 3 + i] = tile[a * stride + i];
+        dst[(int64_t)a * seg_len * 3 + i] =
+            fx ? __longlong_as_double(fold_front(reinterpret_cast<const lds<long long> *>(src), i, front))
+               : fold_front(src, i, front);
+    }
   }
 }
 

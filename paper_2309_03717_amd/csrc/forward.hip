@@ -151,16 +151,16 @@ struct DepositArgs {
 // antennas into their partial slots.
 template <typename A>
 __device__ __forceinline__ void flush_tile(const DepositArgs &g, lds<acc_t> *tile, int stride,
-                                           int split, int64_t a_begin, int n_ant, int lo,
-                                           int row_len) {
+                                           int front, int split, int64_t a_begin, int n_ant,
+                                           int lo, int row_len) {
   A *dst = reinterpret_cast<A *>(g.partial);
   for (int a = 0; a < n_ant; ++a) {
     A *out = dst + (((size_t)split * g.an.m + (size_t)(a_begin + a)) * g.c.n_bins + lo) * 3;
-    const lds<A> *src = reinterpret_cast<lds<A> *>(tile) + a * stride;
+    const lds<A> *src = reinterpret_cast<lds<A> *>(tile) + a * stride + front;
     if (g.accumulate)
-      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] += src[i];
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] += fold_front(src, i, front);
     else
-      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = src[i];
+      for (int i = threadIdx.x; i < row_len; i += blockDim.x) out[i] = fold_front(src, i, front);
   }
 }
 
@@ -193,7 +193,8 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   load_tile<AT, MED>(g.an, a_begin, n_ant, c, t);
   constexpr bool kFxCap = F == 1 && P == 1;
   const double fx_unit = kFxCap ? g.fx[0] : 0.0;
-  const TileRef tr{tile, stride, lo, (double)lo, (double)hi, kFxCap ? g.fx[1] : 0.0};
+  const TileRef tr{tile, stride, lo, (double)lo, (double)hi, kFxCap ? g.fx[1] : 0.0,
+                   tile_front(F) * 3};
   __syncthreads();
 
   const uint64_t mask = (1ull << n_ant) - 1;
@@ -217,9 +218,9 @@ __global__ void __launch_bounds__(1024) deposit_kernel(DepositArgs g) {
   __syncthreads();
 
   if (kFxCap && fx_unit > 0.0)
-    flush_tile<long long>(g, tile, stride, split, a_begin, n_ant, lo, row_len);
+    flush_tile<long long>(g, tile, stride, tile_front(F) * 3, split, a_begin, n_ant, lo, row_len);
   else
-    flush_tile<acc_t>(g, tile, stride, split, a_begin, n_ant, lo, row_len);
+    flush_tile<acc_t>(g, tile, stride, tile_front(F) * 3, split, a_begin, n_ant, lo, row_len);
 }
 
 // ------------------------------------------------------------------ merge

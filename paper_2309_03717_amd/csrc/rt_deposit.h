@@ -12,11 +12,17 @@ using acc_t = double;
 
 // Rows of a ZHS trace tile carry two bins past the segment end, which take
 // the difference deposits that fall just beyond it (at most two bins: the
-// box's last bin is clamped to the segment end first) and are never read.
-// Endpoint impulses land inside the segment only.
-// (Measured: predicating those deposits instead costs the ZHS deposit 4%;
-// padding the Endpoint tile past 96 KiB cost its FP64 deposit 20%.)
-__host__ __device__ constexpr int tile_pad(int formalism) { return formalism == 1 ? 2 : 0; }
+// box's last bin is clamped to the segment end first) and are never read,
+// and two bins before its start (below). Endpoint impulses land inside the
+// segment only.
+// (Measured: predicating the deposits past the end instead costs the ZHS
+// deposit 4%; padding the Endpoint tile past 96 KiB cost its FP64 deposit
+// 20%.)
+__host__ __device__ constexpr int tile_pad(int formalism) { return formalism == 1 ? 4 : 0; }
+// ZHS rows also start two bins early: the differences a box deposits before
+// the segment land there and are added into its first bin when the tile is
+// flushed (fold_front), so the box takes no clamps on its first two bins.
+__host__ __device__ constexpr int tile_front(int formalism) { return formalism == 1 ? 2 : 0; }
 
 // Fixed-point ZHS accumulation (RT_MIXED): every value v, scaled by the
 // call's power-of-two inverse unit s, is rounded to the nearest integer by
@@ -345,10 +351,11 @@ __device__ __forceinline__ void endpoint_amp(lds<acc_t> *row, int lo, double lo_
 // The box [u_lo, u_hi] of time integral I = k qw beta_perp (t1-t0) /
 // R_mid has bin averages Ibar * overlap / (u_hi - u_lo), Ibar = I / dt; it is
 // deposited as at most four differences whose prefix sum is that average,
-// each bounded by |Ibar|. Differences before the segment [lo, hi) fold into
-// its first bin (its prefix scan starts there); those at or past its end land
-// in the row's padding (the last bin is clamped to hi first, so they reach at
-// most hi + 1). cz2 = 2 k qw (t1 - t0) / dt (times the inverse unit for
+// each bounded by |Ibar|. Differences before the segment [lo, hi) land in the
+// row's two front padding bins (the first bin is clamped to lo - 2 first) and
+// are folded into its first bin at the flush (its prefix scan starts there);
+// those at or past its end land in the row's back padding (the last bin is
+// clamped to hi first, so they reach at most hi + 1). cz2 = 2 k qw (t1 - t0) / dt (times the inverse unit for
 // fixed-point deposits, FX).
 template <int P, bool FX>
 __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, double hi_d,
@@ -385,7 +392,9 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
   double s2 = one ? -1.0 : (two ? -a : t2);
   double s3 = two ? bb : -t3;
   double s4 = -bb;
-  // kl <= hi - 1 (the box starts before the segment end) and lo <= jh <= hi
+  // kl <= hi - 1 (the box starts before the segment end), lo <= jh <= hi,
+  // and differences before the segment (jl = -2 or -1) go to the row's front
+  // padding, which the flush folds into the first bin
   // (the clamps as single v_max_f64 / v_min_f64: fmax and fmin would quiet
   // each operand not known to be a number first, the loop-invariant bounds
   // included, on every pair; none of the four is NaN here)
@@ -395,8 +404,8 @@ __device__ __forceinline__ void zhs_box(lds<acc_t> *row, int lo, double lo_d, do
   asm("v_min_f64 %0, %1, %2" : "=v"(ch) : "v"(kh), "v"(hi_d));
   const int jl = (int)cl - lo;
   const int jh = (int)ch - lo;
-  lds<acc_t> *p1 = lds_bin(row, max(jl, 0));
-  lds<acc_t> *p2 = lds_bin(row, max(jl + 1, 0));
+  lds<acc_t> *p1 = lds_bin(row, jl);   // jl >= -2: the row's front padding
+  lds<acc_t> *p2 = p1 + 3;
   lds<acc_t> *p3 = lds_bin(row, jh);
   if (FX) {
     // Fixed point: the bin averages are the rounded levels r(l1 I) (bin
@@ -457,10 +466,20 @@ struct TileRef {
   int lo;            // first bin of the segment
   double lo_d, hi_d;
   double fx_inv;     // fixed-point tiles: 1 / unit (a power of two)
+  int front;         // doubles before bin 0 of a row: tile_front * 3
   __device__ __forceinline__ lds<acc_t> *row(int a) const {
-    return lds_elem(tile, (unsigned)(a * stride));
+    return lds_elem(tile, (unsigned)(a * stride + front));
   }
 };
+
+// Element i of a flushed row (its bin 0 at src): the first bin's three
+// components take the two front padding bins before them.
+template <typename A>
+__device__ __forceinline__ A fold_front(const lds<A> *src, int i, int front) {
+  A v = src[i];
+  if (front > 0 && i < 3) v += src[i - 3] + src[i - 6];
+  return v;
+}
 
 // All deposits of one track record (this lane's track) into the tile
 // antennas selected by mask (a one-antenna tile always holds its antenna).

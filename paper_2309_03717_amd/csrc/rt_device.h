@@ -331,11 +331,12 @@ __device__ __forceinline__ lds<T> *lds_elem(lds<T> *base, unsigned i) {
   return (lds<T> *)((lds<char> *)base + __umul24(i, (unsigned)sizeof(T)));
 }
 
-// The first of the three components of bin j of a trace row (0 <= j, 24 j
-// sizeof(T) / 8 < 2^24): one 24-bit multiply.
+// The first of the three components of bin j of a trace row (|24 j
+// sizeof(T) / 8| < 2^23; j may be negative where the row has front padding):
+// one signed 24-bit multiply.
 template <class T>
 __device__ __forceinline__ lds<T> *lds_bin(lds<T> *row, int j) {
-  return (lds<T> *)((lds<char> *)row + __umul24((unsigned)j, 3u * (unsigned)sizeof(T)));
+  return (lds<T> *)((lds<char> *)row + __mul24(j, 3 * (int)sizeof(T)));
 }
 
 template <typename T>
