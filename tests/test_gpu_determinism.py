@@ -189,3 +189,55 @@ def test_autograd_reads_refractivity_on_the_device(rt):
         np.testing.assert_array_equal(outs[-1].cpu().numpy(), host.traces(dtr).cpu().numpy())
     assert len(det.__dict__["_autograd_plans"]) == 1
     assert not torch.equal(outs[0], outs[1])
+
+
+def test_mixed_zhs_boxes_at_window_and_segment_edges(rt, orc):
+    """Boxes that start before the window, straddle the edge between bin
+    segments, or run past the window end: uniform medium, four ground
+    antennas, track groups whose arrivals spread over about +-8 bins around
+    bin 0, bin 256 and bin 1024 (the window end). The fixed-point deposits of
+    the first two bins of a box land in the row's front padding and are folded
+    into the segment's first bin; every segmentation gives the same bits and
+    all meet the mixed bound against the oracle."""
+    from helpers import antennas
+    n0m1 = 2.92e-4
+    medium = W.Medium("uniform", n0m1, 8000.0)
+    ant = np.array([[0.0, 0.0, 0.0], [50.0, 0.0, 0.0], [0.0, 50.0, 0.0], [50.0, 50.0, 0.0]])
+    dt, nb = 0.2e-9, 1024
+    rng = np.random.default_rng(2309)
+    groups = []
+    for shift_bins in (0, 256, 1024):
+        n = 1500
+        p0 = np.stack([25.0 + rng.uniform(-20, 20, n), 25.0 + rng.uniform(-20, 20, n),
+                       3000.0 + rng.uniform(-0.5, 0.5, n)], axis=1)
+        d = np.stack([rng.normal(0, 0.02, n), rng.normal(0, 0.02, n), -np.ones(n)], axis=1)
+        d /= np.linalg.norm(d, axis=1)[:, None]
+        length = rng.uniform(0.1, 3.0, n)
+        beta = rng.uniform(0.9, 0.99999, n)
+        t0 = np.full(n, shift_bins * dt)
+        p1 = p0 + length[:, None] * d
+        t1 = t0 + length / (beta * W.C_LIGHT)
+        b = beta[:, None] * d
+        q = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+        groups.append(W.Tracks(p0[:, 0], p0[:, 1], p0[:, 2], t0, p1[:, 0], p1[:, 1], p1[:, 2], t1,
+                               b[:, 0], b[:, 1], b[:, 2], q))
+    tr = W.Tracks.concat(groups)
+    # each antenna's window opens at the mean arrival of the first group's starts
+    g0 = groups[0]
+    r = np.linalg.norm(np.stack([g0.x0, g0.y0, g0.z0], axis=1)[None, :, :] - ant[:, None, :], axis=2)
+    t_start = (g0.t0[None, :] + (1.0 + n0m1) * r / W.C_LIGHT).mean(axis=1)
+    arr = antennas(ant, t_start, dt, nb)
+    ref = orc.traces("zhs", tr.to_mixed().widened(), arr, medium, n_threads=8)
+    assert np.abs(ref[:, 0]).max() > 0 and np.abs(ref[:, 255:257]).max() > 0
+    assert np.abs(ref[:, nb - 1]).max() > 0
+    base = None
+    for tl in [(0, 0, 0, 0, 0), (1, 1, 256, 256, 0), (2, 3, 512, 128, 0), (0, 2, 64, 320, 512)]:
+        plan, _, g = mixed_zhs(rt, tr, arr, medium, tl)
+        assert fixed_point_unit(rt, plan, tr.n) > 0.0, "the fixed-point tile should be on"
+        err = rel_l2(g.astype(np.float64), ref).max()
+        assert err <= MIXED_BOUND, (tl, err)
+        if base is None:
+            base = g
+        else:
+            np.testing.assert_array_equal(g, base, err_msg=str(tl))
+    print("boxes at window and segment edges: max rel L2", err)
