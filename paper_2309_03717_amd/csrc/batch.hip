@@ -350,7 +350,8 @@ __device__ __forceinline__ void take_items(const BatchArgs &b, int group, lds<ac
       const lds<acc_t> *src = tile + a * stride + front;
       for (int i = threadIdx.x; i < row_len; i += blockDim.x)
         dst[(int64_t)a * seg_len * 3 + i] =
-            fx ? __longlong_as_double(fold_front(reinterpret_cast<const lds<long long> *>(src), i, front))
+            fx ? __longlong_as_double(
+                     fold_front(reinterpret_cast<const lds<long long> *>(src), i, front))
                : fold_front(src, i, front);
     }
   }
